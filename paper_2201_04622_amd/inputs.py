@@ -1,0 +1,232 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module holds none of the method's arithmetic: no spline construction, no
+EAM sums, no integrator, no lambda schedule and no free-energy estimator.  It
+only produces the *inputs* a user of the method would bring:
+
+* the tabulated potential: knot values of a synthetic analytic EAM (it stands in
+  for the Fe potential the paper uses, Sec. "bulk", which is not available),
+* crystal lattice sites (bcc / fcc cubic supercells, atom id = cell-major),
+* randomly displaced configurations for force tests (numpy Generator, seeded),
+* replica batches with their temperatures, spring constants and seeds.
+
+Units are LAMMPS "metal": eV, Angstrom, ps, amu, K.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import List, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Synthetic analytic EAM (stands in for the paper's Fe potential)
+# ---------------------------------------------------------------------------
+R_CUT = 5.3          # Angstrom, outer cutoff of phi and rho
+R_TAPER = 4.8        # Angstrom, start of the cosine taper
+N_KNOTS = 2000       # knots per tabulated function
+RHO_MAX = 200.0      # upper end of the embedding-function table
+MASS_FE = 55.845     # amu
+
+A_BCC_VERBATIM = 2.855   # lattice constants as configured (physical Fe values)
+A_FCC_VERBATIM = 3.65
+# Zero-pressure 0 K lattice constants of the synthetic potential itself, where
+# both structures are mechanically stable (the verbatim ones are not).
+A_BCC_STABLE = 1.9646
+A_FCC_STABLE = 2.5216
+
+
+def taper(r):
+    """Cosine taper: 1 below R_TAPER, 0 above R_CUT, half-cosine in between."""
+    r = np.asarray(r, dtype=np.float64)
+    s = np.where(r <= R_TAPER, 1.0, 0.5 * (1.0 + np.cos(np.pi * (r - R_TAPER) / (R_CUT - R_TAPER))))
+    return np.where(r >= R_CUT, 0.0, s)
+
+
+def phi_analytic(r):
+    r = np.asarray(r, dtype=np.float64)
+    x = r / 2.48 - 1.0
+    return (0.5 * np.exp(-7.0 * x) - 0.9 * np.exp(-3.5 * x)) * taper(r)
+
+
+def rho_analytic(r):
+    r = np.asarray(r, dtype=np.float64)
+    return np.exp(-6.0 * (r / 2.48 - 1.0)) * taper(r)
+
+
+def embed_analytic(rho):
+    return -2.0 * np.sqrt(np.asarray(rho, dtype=np.float64))
+
+
+@dataclass(frozen=True)
+class PotentialKnots:
+    """Knot values on uniform grids: r_k = k*r_cut/(n-1), rho_k = k*rho_max/(n-1)."""
+    r_cut: float
+    rho_max: float
+    phi: np.ndarray   # [n] eV
+    rho: np.ndarray   # [n]
+    embed: np.ndarray  # [n] eV
+
+    @property
+    def n(self) -> int:
+        return int(self.phi.shape[0])
+
+    def stacked(self) -> np.ndarray:
+        """[3][n] in the order (phi, rho, F)."""
+        return np.stack([self.phi, self.rho, self.embed]).astype(np.float64)
+
+
+def synthetic_eam_knots(n: int = N_KNOTS, r_cut: float = R_CUT, rho_max: float = RHO_MAX) -> PotentialKnots:
+    r = np.arange(n, dtype=np.float64) * (r_cut / (n - 1))
+    rho = np.arange(n, dtype=np.float64) * (rho_max / (n - 1))
+    return PotentialKnots(r_cut, rho_max, phi_analytic(r), rho_analytic(r), embed_analytic(rho))
+
+
+# ---------------------------------------------------------------------------
+# Lattices
+# ---------------------------------------------------------------------------
+BASIS = {
+    "bcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]),
+    "fcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]]),
+}
+
+
+def lattice_sites(kind: str, n: int, a: float) -> np.ndarray:
+    """Sites of an n x n x n cubic supercell, shape [N, 3], id = ((ix*n+iy)*n+iz)*nb + b."""
+    basis = BASIS[kind]
+    idx = np.arange(n)
+    cells = np.stack(np.meshgrid(idx, idx, idx, indexing="ij"), axis=-1).reshape(-1, 3)
+    pos = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    return np.ascontiguousarray(pos, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Replicas and workloads
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Replica:
+    kind: str            # "bcc" | "fcc"
+    n: int               # unit cells per edge
+    a: float             # lattice constant (Angstrom)
+    T: float             # thermostat temperature (K)
+    k: float             # Einstein spring constant (eV/A^2); k1 for the harmonic test mode
+    seed: int            # Philox key
+    mass: float = MASS_FE
+    k2: float = 0.0      # second spring constant (harmonic -> harmonic test mode only)
+
+    @property
+    def natoms(self) -> int:
+        return len(BASIS[self.kind]) * self.n ** 3
+
+    @property
+    def box(self) -> np.ndarray:
+        return np.full(3, self.n * self.a, dtype=np.float64)
+
+    def sites(self) -> np.ndarray:
+        return lattice_sites(self.kind, self.n, self.a)
+
+
+@dataclass(frozen=True)
+class Schedule:
+    """Segment lengths of a switching run (steps).  mode: "fl" | "rs" | "hh" | "ein_rs"."""
+    mode: str
+    n_eq: int
+    n_sw: int
+    n_hold: int
+    n_hold2: int
+    function: int = 2          # lambda(tau) form for FL/HH: 1 linear, 2 smooth-step polynomial
+    lambda_f: float = 1.0      # RS end point lambda_f = T0 / T_f
+    dt: float = 0.001          # ps
+    damp: float = 0.1          # ps (gamma = 1/damp)
+    fix_com: bool = True
+
+    @property
+    def total_steps(self) -> int:
+        return self.n_eq + 2 * self.n_sw + self.n_hold + self.n_hold2
+
+
+@dataclass
+class Workload:
+    name: str
+    replicas: List[Replica]
+    schedule: Schedule
+    description: str = ""
+
+    @property
+    def natoms(self) -> int:
+        return sum(r.natoms for r in self.replicas)
+
+    @property
+    def atom_steps(self) -> int:
+        return self.natoms * self.schedule.total_steps
+
+
+def _cfg2_shapes(a_bcc: float, a_fcc: float):
+    return [("bcc", n, a_bcc) for n in range(6, 13)] + [("fcc", n, a_fcc) for n in range(5, 11)]
+
+
+def workload(name: str, stable: bool = False) -> Workload:
+    """The five configured workloads.  ``stable`` swaps in the synthetic
+    potential's own zero-pressure lattice constants (and the smallest box that
+    keeps L > 2*(r_cut + skin))."""
+    ab = A_BCC_STABLE if stable else A_BCC_VERBATIM
+    af = A_FCC_STABLE if stable else A_FCC_VERBATIM
+    if name == "cfg0":
+        n = 6 if stable else 4
+        reps = [Replica("bcc", n, ab, 100.0, 5.0, 0)]
+        sch = Schedule("fl", 1000, 2000, 500, 500, function=2)
+        desc = f"FL FP64, 1 x bcc {n}^3, T=100 K, k=5"
+    elif name == "cfg1":
+        reps = [Replica("bcc", 10, ab, 1400.0, 3.0, 0), Replica("fcc", 8, af, 1400.0, 3.0, 0)]
+        sch = Schedule("fl", 10000, 50000, 10000, 10000, function=2)
+        desc = "FL single replicas bcc 10^3 / fcc 8^3, T=1400 K, k=3"
+    elif name == "cfg2":
+        shapes = _cfg2_shapes(ab, af)
+        reps = []
+        for r in range(64):
+            kind, n, a = shapes[r % len(shapes)]
+            reps.append(Replica(kind, n, a, 100.0 * (1 + (r % 16)), 5.0, r))
+        sch = Schedule("fl", 2000, 20000, 2000, 0, function=2)
+        desc = "64 batched FL replicas, bcc 6..12^3 / fcc 5..10^3, T in 100..1600 K, k=5"
+    elif name == "cfg3":
+        reps = [Replica("bcc", 20, ab, 100.0, 5.0, s) for s in range(8)]
+        sch = Schedule("rs", 10000, 100000, 10000, 0, lambda_f=100.0 / 1600.0)
+        desc = "RS scan 100->1600 K, 8 x bcc 20^3"
+    elif name == "cfg4":
+        reps = [Replica("bcc", 30, ab, 1200.0, 5.0, s) for s in range(16)]
+        reps += [Replica("fcc", 24, af, 1200.0, 5.0, s) for s in range(16)]
+        sch = Schedule("fl", 3000, 30000, 3000, 0, function=2)
+        desc = "FL for dF/dtheta, 16 x bcc 30^3 + 16 x fcc 24^3, T=1200 K"
+    else:
+        raise ValueError(f"unknown workload {name!r}")
+    return Workload(name + ("_stable" if stable else ""), reps, sch, desc)
+
+
+def batch_arrays(replicas: Sequence[Replica]):
+    """Concatenate replica descriptions into flat host arrays.
+
+    Returns dict with n_atoms[int32 R], box[float64 R,3], x0[float64 N_tot,3]
+    (AoS, replica-major), T, k, k2, mass [float64 R], seed [uint64 R].
+    """
+    x0 = np.concatenate([r.sites() for r in replicas], axis=0)
+    return {
+        "n_atoms": np.array([r.natoms for r in replicas], dtype=np.int32),
+        "box": np.stack([r.box for r in replicas]).astype(np.float64),
+        "x0": np.ascontiguousarray(x0, dtype=np.float64),
+        "T": np.array([r.T for r in replicas], dtype=np.float64),
+        "k": np.array([r.k for r in replicas], dtype=np.float64),
+        "k2": np.array([r.k2 for r in replicas], dtype=np.float64),
+        "mass": np.array([r.mass for r in replicas], dtype=np.float64),
+        "seed": np.array([r.seed for r in replicas], dtype=np.uint64),
+    }
+
+
+def displaced(x0: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+    """x0 + N(0, sigma^2) per component, numpy PCG64 seeded by ``seed``."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(x0 + sigma * rng.standard_normal(x0.shape), dtype=np.float64)
+
+
+def random_velocities(n: int, scale: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(scale * rng.standard_normal((n, 3)), dtype=np.float64)
