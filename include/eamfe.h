@@ -1,0 +1,240 @@
+/*
+ * eamfe.h -- C ABI of the MI355X (gfx950) nonequilibrium free-energy engine
+ * for EAM solids: Langevin MD under a lambda-dependent Hamiltonian with the
+ * irreversible work accumulated on the device.
+ *
+ * Method (arXiv 2201.04622):
+ *   Frenkel--Ladd path   H(l) = (1-l) H0 + l H_E          (Eq. interp, Eq. H, Eq. einstein)
+ *   Reversible scaling   H(l) = KE + l U                   (Eq. H_rs)
+ *   work                 W = sum_k (l_{k+1} - l_k) dH/dl(G_k)   (Eq. w_irr, discrete form)
+ *   schedules            ti/spring phases and lambda(tau) forms (Sec. fl_lammps),
+ *                        RS lambda(tau) = 1/(1 + tau (1/l_f - 1)) (Sec. RS in LAMMPS)
+ *   estimators           Eq. W12, Eq. Ediss, Eq. fl (+ Eq. cm), Eq. rs
+ *
+ * Conventions for every entry point:
+ *   - Units are LAMMPS "metal": eV, Angstrom, ps, amu, K.
+ *   - "device" pointers are HIP device memory owned by the caller (for
+ *     example a torch tensor's data_ptr()); "host" pointers are ordinary
+ *     memory read or written before the call returns.  The library never
+ *     frees caller memory.  Internal work buffers (neighbour lists, cell
+ *     bins, tables, partial sums) are allocated by the library in
+ *     eam_setup / eamfe_system_setup / neigh_build and freed by
+ *     eamfe_destroy; the stepping calls allocate only when a larger lambda
+ *     table than any before is needed.
+ *   - Positions, velocities and forces are SoA float64 [3][N_tot]
+ *     (x of all atoms, then y, then z); replicas are stored back to back in
+ *     the order given to eamfe_system_setup.  Positions are unwrapped
+ *     (never folded into the box); pair separations use the minimum image.
+ *   - Work runs on the context's HIP stream.  Every call returns an int
+ *     status; calls that end with a stream synchronisation also report
+ *     conditions the kernels latched (overflow, table range, non-finite).
+ *     Nothing throws across the ABI.  A context is not thread safe.
+ */
+#ifndef EAMFE_H
+#define EAMFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define EAMFE_OK               0
+#define EAMFE_EINVAL           1   /* bad argument                                  */
+#define EAMFE_ENOMEM           2   /* device or host allocation failed              */
+#define EAMFE_EDEVICE          3   /* HIP runtime error                             */
+#define EAMFE_ESTATE           4   /* call out of order (e.g. forces before setup)  */
+#define EAMFE_EBOX             5   /* a box edge is <= 2 (r_cut + skin)             */
+#define EAMFE_ENEIGH_OVERFLOW  6   /* an atom had more than max_neighbors candidates */
+#define EAMFE_ECELL_OVERFLOW   7   /* a binning cell overflowed                     */
+#define EAMFE_ETABLE_RANGE     8   /* some density rho_i > rho_max                  */
+#define EAMFE_ENONFINITE       9   /* NaN/Inf in positions, forces or energies      */
+
+/* numeric form of the pair arithmetic */
+#define EAMFE_FP64 0   /* all arithmetic in float64                                    */
+#define EAMFE_FP32 1   /* pair terms, densities, tables in float32; positions, velocities,
+                          energies and work in float64; per-atom sums accumulated in
+                          fixed point (2^-32 quanta) so results do not depend on the
+                          order of the neighbour list or on the launch shape          */
+
+/* Hamiltonian family (dH/dl in brackets) */
+#define EAMFE_MODE_FL      0   /* (1-l) U_EAM + l U_E(k)          [U_E - U_EAM]  Eq. interp/w_irr2 */
+#define EAMFE_MODE_RS      1   /* l U_EAM                         [U_EAM]        Eq. H_rs/w_irr_rs */
+#define EAMFE_MODE_HH      2   /* (1-l) U_E(k) + l U_E(k2)        [U_E(k2)-U_E(k)] harmonic test path */
+#define EAMFE_MODE_EIN_RS  3   /* l U_E(k)                        [U_E(k)]       RS on an Einstein crystal */
+
+typedef struct eamfe_ctx eamfe_ctx;
+
+/* One replica: an independent periodic system.  x0 sites are given on the
+ * device in eamfe_system_setup. */
+typedef struct eamfe_replica {
+    int32_t  n_atoms;
+    int32_t  pad_;
+    double   box[3];    /* orthorhombic box edges, Angstrom                      */
+    double   T;         /* thermostat temperature, K                             */
+    double   k;         /* Einstein spring (FL, EIN_RS) or k1 (HH), eV/A^2        */
+    double   k2;        /* final spring of the HH test path, eV/A^2              */
+    double   mass;      /* amu                                                   */
+    uint64_t seed;      /* Philox key of this replica                            */
+} eamfe_replica;
+
+/* A switching protocol (shared by every replica of the context).
+ * FL/HH (ti/spring phases, Sec. fl_lammps):
+ *   [n_eq at l=0][n_sw forward 0->1][n_hold at 1][n_sw backward 1->0][n_hold2 at 0]
+ * RS/EIN_RS (Sec. RS in LAMMPS):
+ *   [n_eq at 1][n_sw forward 1->lambda_f][n_hold at lambda_f][n_sw backward][n_hold2 at 1]
+ * tau = (switching steps done)/n_sw; the backward branch is the time reverse.
+ * S = n_eq + 2 n_sw + n_hold + n_hold2 steps in total. */
+typedef struct eamfe_protocol {
+    int32_t mode;        /* EAMFE_MODE_*                                        */
+    int32_t function;    /* FL/HH lambda(tau): 1 = tau, 2 = tau^5(70tau^4-315tau^3+540tau^2-420tau+126) */
+    int32_t fix_com;     /* 1: thermostat noise has zero mean per replica (fixed centre of mass) */
+    int32_t n_eq, n_sw, n_hold, n_hold2;
+    int32_t pad_;
+    double  dt;          /* ps (the paper uses 0.001)                           */
+    double  damp;        /* Langevin relaxation time, ps; gamma = 1/damp; 0 = NVE (velocity Verlet) */
+    double  lambda_f;    /* RS end point T0/T_f                                 */
+    double  skin;        /* Verlet skin, Angstrom (list rebuilt when an atom moves > skin/2) */
+} eamfe_protocol;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  precision is
+ * EAMFE_FP64 or EAMFE_FP32.  *ctx is set on success. */
+int eamfe_create(eamfe_ctx** ctx, int device, void* hip_stream, int precision);
+
+/* Free every library-owned buffer.  NULL is accepted. */
+int eamfe_destroy(eamfe_ctx* ctx);
+
+/* Text of the last error of this context (static storage inside ctx). */
+const char* eamfe_last_error(const eamfe_ctx* ctx);
+
+/* Change the stream later calls use. */
+int eamfe_set_stream(eamfe_ctx* ctx, void* hip_stream);
+
+/* Launch shape of the pair kernels: lanes per atom (1, 2, 4, 8 or 16) and
+ * threads per block (64..1024, multiple of 64).  0 keeps the current value.
+ * In EAMFE_FP32 results are bit-identical for every shape. */
+int eamfe_set_launch(eamfe_ctx* ctx, int lanes_per_atom, int block_threads);
+int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threads);
+
+/* 1: place every replica's tiles on one XCD (workgroup id mod 8), balancing
+ * atoms across the eight XCDs; 0: replica-major order.  Default 1. */
+int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
+
+/* Synchronise the stream and return the first latched device condition
+ * (EAMFE_ENEIGH_OVERFLOW ...), clearing it. */
+int eamfe_check(eamfe_ctx* ctx);
+
+/* ---- potential --------------------------------------------------------- */
+
+/* Tabulated EAM (the paper's "pair eam" input; Eq. H with U = EAM):
+ *   U = sum_i F(rho_i) + 1/2 sum_{i != j} phi(r_ij),  rho_i = sum_{j != i} rho(r_ij),
+ * pairs counted only for r < r_cut.  Host knot arrays: phi_knots, rho_knots
+ * at r_k = k r_cut/(n_r-1), k = 0..n_r-1; F_knots at rho_k = k rho_max/(n_rho-1).
+ * Each function is the natural cubic spline through its knots; outside the
+ * table the last cubic piece is continued and EAMFE_ETABLE_RANGE is latched
+ * when a density exceeds rho_max.  May be called again to replace the tables. */
+int eam_setup(eamfe_ctx* ctx, int n_r, double r_cut, const double* phi_knots,
+              const double* rho_knots, int n_rho, double rho_max, const double* F_knots);
+
+/* ---- system ------------------------------------------------------------ */
+
+/* Describe n_rep replicas (host array) and their lattice sites x0 (device,
+ * SoA [3][N_tot], copied).  N_tot = sum n_atoms.  Replaces any previous system. */
+int eamfe_system_setup(eamfe_ctx* ctx, int n_rep, const eamfe_replica* reps, const double* x0_dev);
+
+/* Build the Verlet lists at positions x (device SoA) with cutoff r_cut+skin:
+ * cell binning with cells of edge >= r_cut+skin where a box holds at least
+ * three per edge, all-pairs otherwise.  max_neighbors bounds each atom's row
+ * (0 = estimate from the densest replica).  EAMFE_EBOX if an edge <= 2(r_cut+skin). */
+int neigh_build(eamfe_ctx* ctx, const double* x_dev, double skin, int max_neighbors);
+
+/* ---- evaluation -------------------------------------------------------- */
+
+/* EAM energy and forces at x (device SoA) using the current lists (rebuilt
+ * first if any atom moved more than skin/2 since they were built).
+ * f_dev: device SoA [3][N_tot] float64 (may be NULL); U_dev: device [n_rep]
+ * float64 (may be NULL); e_atom_dev: device [N_tot] per-atom energy
+ * F(rho_i) + 1/2 sum_j phi(r_ij) (may be NULL).  Synchronises. */
+int eam_forces(eamfe_ctx* ctx, const double* x_dev, double* f_dev, double* U_dev, double* e_atom_dev);
+
+/* Initial velocities v = sqrt(kB T / m) z with z from Philox stream 1 at
+ * step 0 (one counter per atom id within its replica); with fix_com the
+ * replica's mean velocity is removed.  v_dev: device SoA. */
+int eamfe_init_velocities(eamfe_ctx* ctx, double* v_dev, int fix_com);
+
+/* Host lambda table of the protocol: lam_host[0..S] (S+1 values), *n_steps = S.
+ * lam_host may be NULL to query S. */
+int eamfe_lambda_schedule(const eamfe_protocol* p, double* lam_host, int64_t* n_steps);
+
+/* Advance every replica through steps [step_begin, step_end) of the
+ * protocol (0 <= step_begin < step_end <= S).  One step s:
+ *   W += (l_{s+1} - l_s) dH/dl(x_s)                    (Eq. w_irr, left point)
+ *   BAOAB: v += dt/2m F(x_s; l_{s+1}); x += dt/2 v;
+ *          v = c1 v + sqrt((1-c1^2) kB T/m) (xi - <xi>); x += dt/2 v;
+ *          v += dt/2m F(x_{s+1}; l_{s+1}),   c1 = exp(-dt/damp),
+ *   with xi from Philox stream 0 keyed (seed; atom id, step s) and <xi> its
+ *   replica mean when fix_com (else 0).
+ * x_dev, v_dev: device SoA, updated in place.  The work carried between calls
+ * restarts at 0 when step_begin == 0.  Optional device outputs (NULL to skip),
+ * indexed by the global step s: dHdl_out[n_rep][S] = dH/dl(x_s),
+ * W_out[n_rep][S] = W after step s's increment; lam_out[S+1] = the table.
+ * Does not synchronise unless `sync` is nonzero. */
+int run_switching(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step_begin, int64_t step_end,
+                  double* x_dev, double* v_dev, double* lam_out, double* dHdl_out, double* W_out,
+                  int sync);
+
+/* One step s of the protocol (same arithmetic as run_switching) with the
+ * work of each replica carried in W_dev[n_rep] (device, in/out) and
+ * dH/dl(x_s) written to dHdl_dev[n_rep] (device, may be NULL). */
+int switch_step(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step, double* x_dev, double* v_dev,
+                double* W_dev, double* dHdl_dev);
+
+/* Per-replica work after the last stepping call: host W_host[n_rep]. */
+int eamfe_get_work(eamfe_ctx* ctx, double* W_host);
+
+/* ---- differentiation --------------------------------------------------- */
+
+/* dU_EAM/dtheta at x for every replica, theta = the knot values of
+ * (phi, rho, F) given to eam_setup (n_r == n_rho required):
+ *   dtheta_dev[r][0][k] += scale * dU_r/dphi_k,
+ *   dtheta_dev[r][1][k] += scale * dU_r/drho_k,
+ *   dtheta_dev[r][2][k] += scale * dU_r/dF_k,
+ * device float64 [n_rep][3][n_r], accumulated (the caller zeroes it).  By
+ * Eq. dFdL with theta in the role of lambda, averaging this over the H0
+ * ensemble gives dF/dtheta.  Per-bin sums are accumulated in fixed point so
+ * the result is deterministic.  Synchronises. */
+int eamfe_adjoint_theta(eamfe_ctx* ctx, const double* x_dev, double scale, double* dtheta_dev);
+
+/* ---- estimators (host, float64) ---------------------------------------- */
+
+/* Einstein crystal F_E = 3 n_eff kB T ln(hbar w / kB T), w = sqrt(k/m). */
+double eamfe_einstein_free_energy(double n_eff, double T, double k, double mass);
+
+/* Fixed centre-of-mass term of Eq. cm: kB T ln[(N/V)(2 pi kB T/(N k))^(3/2)]. */
+double eamfe_fixed_cm_correction(double N, double V, double T, double k);
+
+/* Frenkel--Ladd: from n replicas' forward (H0 -> H_E) and backward works,
+ * F0 = F_E + (mean W_bwd - mean W_fwd)/2 [+ delta F_CM if add_cm]
+ * (Eq. fl with the sign implied by Eq. W12).  Outputs: F0, the dissipation
+ * (Eq. Ediss) and the standard error of F0 (any may be NULL). */
+int eamfe_fl_free_energy(int n, const double* W_fwd, const double* W_bwd, double n_eff, double N,
+                         double V, double T, double k, double mass, int add_cm,
+                         double* F0, double* E_diss, double* F0_err);
+
+/* Reversible scaling (Eq. rs): from one replica's cumulative work trace
+ * W_trace[S] of an RS protocol and F0(T0), the free energy on n_T
+ * temperatures T_grid in [T0, T0/lambda_f]:
+ *   F(T) = F0(T0)/l + 3/2 n_eff kB T0 ln(l)/l + (W_{1->l} - W_{l->1})/(2l),  l = T0/T,
+ * work between steps interpolated linearly. */
+int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W_trace, double F0_T0, double T0,
+                         double n_eff, int n_T, const double* T_grid, double* F_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EAMFE_H */

@@ -1,0 +1,943 @@
+// Host side of the C ABI declared in include/eamfe.h: context and buffers,
+// spline tables, replica/tile layout, lambda schedules, the stepping loop and
+// the free-energy estimators.  All arithmetic of the MD path runs in the
+// kernels of eamfe_kernels.hip; this file only prepares tables and launches.
+#include "../../include/eamfe.h"
+#include "eamfe_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace eamfe;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct eamfe_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = EAMFE_FP64;
+    int lanes = 4;
+    int block = 256;
+    int xcd = 1;
+    std::string err;
+
+    // potential
+    bool have_pot = false;
+    int n_r = 0, n_rho = 0;
+    double r_cut = 0.0, rho_max = 0.0;
+    std::vector<double> knots_phi, knots_rho, knots_F;
+    std::vector<double> c_phi, c_rho, c_F;   // [n-1][4] float64
+    DevBuf tab_pair, tab_rho, tab_F;
+
+    // system
+    int n_rep = 0;
+    int N = 0;
+    std::vector<eamfe_replica> reps_in;
+    std::vector<RepDesc> reps;
+    std::vector<Tile> tiles;
+    int n_tiles = 0;   // real tiles
+    DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, xalt_d, Fp_d, e_emb_d, xi_d;
+    DevBuf noise_part_d, energy_part_d, noise_sum_d, U_rep_d, W_state_d;
+    DevBuf cnt_density_d, cnt_force_d, cnt_all_d, iter_d, rebuild_d, status_d;
+
+    // neighbour lists
+    bool have_list = false;
+    double skin = 0.3;
+    int cap = 0, ccap = 0, n_cells = 0;
+    DevBuf nbr_d, nnb_d, cell_cnt_d, cell_n_d, cell_atoms_d, cell_rep_d;
+
+    // lambda table
+    DevBuf lam_d;
+    std::vector<double> lam_h;
+    eamfe_protocol lam_key{};
+    bool lam_valid = false;
+};
+
+namespace {
+
+int fail(eamfe_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? EAMFE_ENOMEM : EAMFE_EDEVICE,        \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+#define LCHK(ctx, expr)                                                                        \
+    do {                                                                                       \
+        int e_ = (expr);                                                                       \
+        if (e_ != 0)                                                                           \
+            return fail(ctx, EAMFE_EDEVICE, std::string(#expr) + ": " +                        \
+                                                hipGetErrorString((hipError_t)e_));            \
+    } while (0)
+
+void release(DevBuf& b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// (Re)allocate to at least `bytes`; contents are not preserved.
+int ensure(eamfe_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    if (b.p && b.bytes >= bytes) return EAMFE_OK;
+    release(b);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, EAMFE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    return EAMFE_OK;
+}
+
+#define OK(expr)                        \
+    do {                                \
+        int r_ = (expr);                \
+        if (r_ != EAMFE_OK) return r_;  \
+    } while (0)
+
+// Natural cubic spline on x_k = k h through y[0..n-1] -> [n-1][4] (a, b, c, d)
+// with s(t) = a + t(b + t(c + t d)) on interval m, t = x/h - m.  The second
+// derivatives solve the tridiagonal system M_{k-1} + 4 M_k + M_{k+1} =
+// 6 (y_{k+1} - 2 y_k + y_{k-1}) / h^2 with M_0 = M_{n-1} = 0 (natural ends).
+std::vector<double> natural_spline(const double* y, int n, double h)
+{
+    std::vector<double> M(n, 0.0), diag(n, 4.0), rhs(n, 0.0);
+    for (int k = 1; k < n - 1; ++k) rhs[k] = 6.0 * (y[k + 1] - 2.0 * y[k] + y[k - 1]) / (h * h);
+    // forward elimination (unit off-diagonals)
+    for (int k = 2; k < n - 1; ++k) {
+        const double w = 1.0 / diag[k - 1];
+        diag[k] -= w;
+        rhs[k] -= w * rhs[k - 1];
+    }
+    for (int k = n - 2; k >= 1; --k) M[k] = (rhs[k] - (k + 1 < n - 1 ? M[k + 1] : 0.0)) / diag[k];
+    std::vector<double> c(4 * (size_t)(n - 1));
+    for (int m = 0; m < n - 1; ++m) {
+        c[4 * m + 0] = y[m];
+        c[4 * m + 1] = (y[m + 1] - y[m]) - h * h * (2.0 * M[m] + M[m + 1]) / 6.0;
+        c[4 * m + 2] = 0.5 * h * h * M[m];
+        c[4 * m + 3] = h * h * (M[m + 1] - M[m]) / 6.0;
+    }
+    return c;
+}
+
+template <typename real>
+int upload_tables_t(eamfe_ctx* c)
+{
+    const int mr = c->n_r - 1, mf = c->n_rho - 1;
+    const double inv_h = (c->n_r - 1) / c->r_cut;
+    std::vector<real> pair(8 * (size_t)mr), rho(4 * (size_t)mr), F(4 * (size_t)mf);
+    for (int m = 0; m < mr; ++m) {
+        for (int q = 0; q < 4; ++q) pair[8 * m + q] = (real)c->c_phi[4 * m + q];
+        pair[8 * m + 4] = (real)(c->c_rho[4 * m + 1] * inv_h);
+        pair[8 * m + 5] = (real)(2.0 * c->c_rho[4 * m + 2] * inv_h);
+        pair[8 * m + 6] = (real)(3.0 * c->c_rho[4 * m + 3] * inv_h);
+        pair[8 * m + 7] = (real)0;
+        for (int q = 0; q < 4; ++q) rho[4 * m + q] = (real)c->c_rho[4 * m + q];
+    }
+    for (int m = 0; m < mf; ++m)
+        for (int q = 0; q < 4; ++q) F[4 * m + q] = (real)c->c_F[4 * m + q];
+    OK(ensure(c, c->tab_pair, pair.size() * sizeof(real)));
+    OK(ensure(c, c->tab_rho, rho.size() * sizeof(real)));
+    OK(ensure(c, c->tab_F, F.size() * sizeof(real)));
+    HIPCHK(c, hipMemcpy(c->tab_pair.p, pair.data(), pair.size() * sizeof(real), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->tab_rho.p, rho.data(), rho.size() * sizeof(real), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->tab_F.p, F.data(), F.size() * sizeof(real), hipMemcpyHostToDevice));
+    return EAMFE_OK;
+}
+
+Tables tables_of(const eamfe_ctx* c)
+{
+    Tables t{};
+    t.pair = c->tab_pair.p;
+    t.rho = c->tab_rho.p;
+    t.F = c->tab_F.p;
+    t.n_r = c->n_r;
+    t.n_rho = c->n_rho;
+    t.r_cut = c->r_cut;
+    t.rc2 = c->r_cut * c->r_cut;
+    t.inv_h_r = (c->n_r - 1) / c->r_cut;
+    t.inv_h_rho = (c->n_rho - 1) / c->rho_max;
+    t.rho_max = c->rho_max;
+    return t;
+}
+
+// Tile table for the current launch shape.  With XCD affinity (and at least
+// eight replicas) replicas are packed into eight bins of about equal atom
+// count and the tiles of bin x are placed at grid positions p with p % 8 == x,
+// so a replica's workgroups share one XCD's L2; unused positions are padding
+// tiles (count 0).
+int build_tiles(eamfe_ctx* c)
+{
+    const int A = c->block / c->lanes;
+    c->tiles.clear();
+    std::vector<std::vector<Tile>> per(c->n_rep);
+    int base = 0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepDesc& R = c->reps[r];
+        R.n_tiles = (R.n + A - 1) / A;
+        R.tile_base = base;
+        base += R.n_tiles;
+        for (int t = 0; t < R.n_tiles; ++t) {
+            Tile tl;
+            tl.rep = r;
+            tl.first = R.off + t * A;
+            tl.count = std::min(A, R.n - t * A);
+            tl.idx = t;
+            per[r].push_back(tl);
+        }
+    }
+    c->n_tiles = base;
+    if (c->xcd && c->n_rep >= 8) {
+        std::vector<int> order(c->n_rep);
+        for (int r = 0; r < c->n_rep; ++r) order[r] = r;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->reps[a].n > c->reps[b].n; });
+        std::vector<long> load(8, 0);
+        std::vector<std::vector<Tile>> bins(8);
+        for (int r : order) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += c->reps[r].n;
+            bins[x].insert(bins[x].end(), per[r].begin(), per[r].end());
+        }
+        size_t len = 0;
+        for (auto& b : bins) len = std::max(len, b.size());
+        Tile pad{0, 0, 0, 0};
+        for (size_t q = 0; q < len; ++q)
+            for (int x = 0; x < 8; ++x) c->tiles.push_back(q < bins[x].size() ? bins[x][q] : pad);
+    } else {
+        for (auto& v : per) c->tiles.insert(c->tiles.end(), v.begin(), v.end());
+    }
+    OK(ensure(c, c->tiles_d, c->tiles.size() * sizeof(Tile)));
+    HIPCHK(c, hipMemcpy(c->tiles_d.p, c->tiles.data(), c->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    OK(ensure(c, c->noise_part_d, (size_t)c->n_tiles * 3 * sizeof(double)));
+    OK(ensure(c, c->energy_part_d, (size_t)c->n_tiles * 2 * sizeof(double)));
+    OK(ensure(c, c->reps_d, c->reps.size() * sizeof(RepDesc)));
+    HIPCHK(c, hipMemcpy(c->reps_d.p, c->reps.data(), c->reps.size() * sizeof(RepDesc), hipMemcpyHostToDevice));
+    return EAMFE_OK;
+}
+
+int upload_reps(eamfe_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->reps_d.p, c->reps.data(), c->reps.size() * sizeof(RepDesc), hipMemcpyHostToDevice,
+                             c->stream));
+    // the host vector may change before the copy runs: wait for it
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EAMFE_OK;
+}
+
+NeighArgs neigh_args(eamfe_ctx* c, const double* x)
+{
+    NeighArgs a{};
+    a.tiles = (const Tile*)c->tiles_d.p;
+    a.reps = (const RepDesc*)c->reps_d.p;
+    a.rep_of = (const int32_t*)c->rep_of_d.p;
+    a.cell_rep = (const int32_t*)c->cell_rep_d.p;
+    a.x = x;
+    a.xref = (double*)c->xref_d.p;
+    a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
+    a.cell_n = (int32_t*)c->cell_n_d.p;
+    a.cell_atoms = (int32_t*)c->cell_atoms_d.p;
+    a.nbr = (int32_t*)c->nbr_d.p;
+    a.nnb = (int32_t*)c->nnb_d.p;
+    a.rebuild = (int32_t*)c->rebuild_d.p;
+    a.status = (int32_t*)c->status_d.p;
+    a.N = c->N;
+    a.n_cells = c->n_cells;
+    a.ccap = c->ccap;
+    a.cap = c->cap;
+    a.rl2 = (c->r_cut + c->skin) * (c->r_cut + c->skin);
+    a.half_skin2 = 0.25 * c->skin * c->skin;
+    return a;
+}
+
+StepArgs step_args(eamfe_ctx* c)
+{
+    StepArgs a{};
+    a.tiles = (const Tile*)c->tiles_d.p;
+    a.reps = (const RepDesc*)c->reps_d.p;
+    a.x0 = (const double*)c->x0_d.p;
+    a.xref = (const double*)c->xref_d.p;
+    a.nbr = (const int32_t*)c->nbr_d.p;
+    a.nnb = (const int32_t*)c->nnb_d.p;
+    a.cap = c->cap;
+    a.Fp = c->Fp_d.p;
+    a.e_emb = (double*)c->e_emb_d.p;
+    a.xi = (double*)c->xi_d.p;
+    a.noise_part = (double*)c->noise_part_d.p;
+    a.noise_sum = (double*)c->noise_sum_d.p;
+    a.energy_part = (double*)c->energy_part_d.p;
+    a.U_rep = (double*)c->U_rep_d.p;
+    a.cnt_density = (uint32_t*)c->cnt_density_d.p;
+    a.cnt_force = (uint32_t*)c->cnt_force_d.p;
+    a.cnt_all = (uint32_t*)c->cnt_all_d.p;
+    a.rebuild = (int32_t*)c->rebuild_d.p;
+    a.status = (int32_t*)c->status_d.p;
+    a.iter = (int64_t*)c->iter_d.p;
+    a.W_state = (double*)c->W_state_d.p;
+    a.tab = tables_of(c);
+    a.N = c->N;
+    a.n_tiles = c->n_tiles;
+    a.n_grid = (int)c->tiles.size();
+    a.half_skin2 = 0.25 * c->skin * c->skin;
+    return a;
+}
+
+// Neighbour-list geometry for the current system and skin.
+int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
+{
+    const double rl = c->r_cut + skin;
+    double dens_max = 0.0, cellvol_max = 0.0;
+    int n_cells = 0;
+    std::vector<int32_t> cell_rep;
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepDesc& R = c->reps[r];
+        double V = R.L[0] * R.L[1] * R.L[2];
+        for (int d = 0; d < 3; ++d)
+            if (!(R.L[d] > 2.0 * rl))
+                return fail(c, EAMFE_EBOX, "box edge " + std::to_string(R.L[d]) + " of replica " +
+                                               std::to_string(r) + " is not larger than 2 (r_cut + skin)");
+        dens_max = std::max(dens_max, R.n / V);
+        int nc[3];
+        bool cells = true;
+        for (int d = 0; d < 3; ++d) {
+            nc[d] = (int)std::floor(R.L[d] / rl);
+            if (nc[d] < 3) cells = false;
+        }
+        R.cell_base = n_cells;
+        if (cells) {
+            for (int d = 0; d < 3; ++d) R.nc[d] = nc[d];
+            const int k = nc[0] * nc[1] * nc[2];
+            for (int q = 0; q < k; ++q) cell_rep.push_back(r);
+            n_cells += k;
+            cellvol_max = std::max(cellvol_max, V / k * (R.n / V));
+        } else {
+            R.nc[0] = R.nc[1] = R.nc[2] = 0;
+        }
+    }
+    // mean occupancy of the fullest cells, with room for clustering
+    c->ccap = std::max(32, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32);
+    if (max_neighbors <= 0) {
+        const double nmean = 4.0 / 3.0 * M_PI * rl * rl * rl * dens_max;
+        max_neighbors = (int)(std::ceil((nmean * 2.0 + 32.0) / 32.0) * 32.0);
+    }
+    c->cap = max_neighbors;
+    c->n_cells = n_cells;
+    c->skin = skin;
+    OK(ensure(c, c->nbr_d, (size_t)c->N * c->cap * sizeof(int32_t)));
+    OK(ensure(c, c->nnb_d, (size_t)c->N * sizeof(int32_t)));
+    OK(ensure(c, c->cell_cnt_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
+    OK(ensure(c, c->cell_n_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
+    OK(ensure(c, c->cell_atoms_d, (size_t)std::max(1, n_cells) * c->ccap * sizeof(int32_t)));
+    OK(ensure(c, c->cell_rep_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
+    HIPCHK(c, hipMemsetAsync(c->cell_cnt_d.p, 0, (size_t)std::max(1, n_cells) * sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->nnb_d.p, 0, (size_t)c->N * sizeof(int32_t), c->stream));
+    if (n_cells)
+        HIPCHK(c, hipMemcpy(c->cell_rep_d.p, cell_rep.data(), cell_rep.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+    OK(upload_reps(c));
+    return EAMFE_OK;
+}
+
+int status_code(int st)
+{
+    if (st & ST_NEIGH_OVERFLOW) return EAMFE_ENEIGH_OVERFLOW;
+    if (st & ST_CELL_OVERFLOW) return EAMFE_ECELL_OVERFLOW;
+    if (st & ST_NONFINITE) return EAMFE_ENONFINITE;
+    if (st & ST_TABLE_RANGE) return EAMFE_ETABLE_RANGE;
+    return EAMFE_OK;
+}
+
+int read_status(eamfe_ctx* c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int st = 0;
+    HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (st) {
+        HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
+        const int code = status_code(st);
+        const char* what = code == EAMFE_ENEIGH_OVERFLOW ? "neighbour row overflow (raise max_neighbors)"
+                           : code == EAMFE_ECELL_OVERFLOW ? "cell bin overflow"
+                           : code == EAMFE_ENONFINITE     ? "non-finite position, force or energy"
+                                                          : "density beyond rho_max";
+        return fail(c, code, what);
+    }
+    return EAMFE_OK;
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+
+int set_iter(eamfe_ctx* c, int64_t v)
+{
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, c->stream, (int64_t*)c->iter_d.p, v);
+    HIPCHK(c, hipGetLastError());
+    return EAMFE_OK;
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int set_rebuild_all(eamfe_ctx* c)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream, (int32_t*)c->rebuild_d.p,
+                       c->n_rep, 1);
+    HIPCHK(c, hipGetLastError());
+    return EAMFE_OK;
+}
+
+bool proto_equal(const eamfe_protocol& a, const eamfe_protocol& b)
+{
+    return a.mode == b.mode && a.function == b.function && a.n_eq == b.n_eq && a.n_sw == b.n_sw &&
+           a.n_hold == b.n_hold && a.n_hold2 == b.n_hold2 && a.lambda_f == b.lambda_f;
+}
+
+double lambda_fl(int function, double tau)
+{
+    if (function == 1) return tau;
+    // 9th-order smooth step with zero slope at both ends (Sec. fl_lammps, function 2)
+    const double t2 = tau * tau, t4 = t2 * t2, t5 = t4 * tau;
+    return t5 * (126.0 + tau * (-420.0 + tau * (540.0 + tau * (-315.0 + tau * 70.0))));
+}
+
+double lambda_rs(double lf, double tau) { return 1.0 / (1.0 + tau * (1.0 / lf - 1.0)); }
+
+int check_protocol(const eamfe_protocol* p)
+{
+    if (!p) return EAMFE_EINVAL;
+    if (p->mode < 0 || p->mode > 3) return EAMFE_EINVAL;
+    if (p->n_eq < 0 || p->n_sw < 1 || p->n_hold < 0 || p->n_hold2 < 0) return EAMFE_EINVAL;
+    if ((p->mode == EAMFE_MODE_FL || p->mode == EAMFE_MODE_HH) && p->function != 1 && p->function != 2)
+        return EAMFE_EINVAL;
+    if ((p->mode == EAMFE_MODE_RS || p->mode == EAMFE_MODE_EIN_RS) && !(p->lambda_f > 0.0)) return EAMFE_EINVAL;
+    if (!(p->dt > 0.0) || p->damp < 0.0) return EAMFE_EINVAL;
+    return EAMFE_OK;
+}
+
+int ensure_lambda(eamfe_ctx* c, const eamfe_protocol* p, int64_t* S_out)
+{
+    int64_t S = 0;
+    OK(eamfe_lambda_schedule(p, nullptr, &S));
+    if (!c->lam_valid || !proto_equal(c->lam_key, *p)) {
+        c->lam_h.assign(S + 1, 0.0);
+        OK(eamfe_lambda_schedule(p, c->lam_h.data(), &S));
+        OK(ensure(c, c->lam_d, (S + 1) * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->lam_d.p, c->lam_h.data(), (S + 1) * sizeof(double), hipMemcpyHostToDevice));
+        c->lam_key = *p;
+        c->lam_valid = true;
+    }
+    *S_out = S;
+    return EAMFE_OK;
+}
+
+// Per-replica thermostat amplitude for the protocol's damping.
+int set_thermostat(eamfe_ctx* c, const eamfe_protocol* p, double* c1_out)
+{
+    const double c1 = p->damp > 0.0 ? std::exp(-p->dt / p->damp) : 1.0;
+    bool changed = false;
+    for (auto& R : c->reps) {
+        const double c2 = std::sqrt((1.0 - c1 * c1) * kB * R.T * R.inv_m);
+        if (c2 != R.c2) {
+            R.c2 = c2;
+            changed = true;
+        }
+    }
+    if (changed) OK(upload_reps(c));
+    *c1_out = c1;
+    return EAMFE_OK;
+}
+
+int ensure_lists(eamfe_ctx* c, double skin, const double* x)
+{
+    if (!c->have_list || skin != c->skin) {
+        OK(plan_lists(c, skin, c->have_list ? c->cap : 0));
+        c->have_list = true;
+        OK(set_rebuild_all(c));
+    } else {
+        NeighArgs na = neigh_args(c, x);
+        LCHK(c, launch_check_displacement(na, c->stream));
+    }
+    return EAMFE_OK;
+}
+
+// Iterations it_first .. it_last of a protocol starting from positions in x.
+// Returns the buffer that holds the final positions in *final_x.
+int iterate(eamfe_ctx* c, StepArgs a, double* x, bool has_eam, int64_t it_first, int64_t it_last, double** final_x)
+{
+    double* cur = x;
+    double* nxt = (double*)c->xalt_d.p;
+    a.it_first = it_first;
+    a.it_last = it_last;
+    a.step_kernel = 1;
+    a.has_eam = has_eam ? 1 : 0;
+    OK(set_iter(c, it_first));
+    for (int64_t it = it_first; it <= it_last; ++it) {
+        if (has_eam) {
+            NeighArgs na = neigh_args(c, cur);
+            LCHK(c, launch_neigh_rebuild(na, c->stream));
+        }
+        a.x = cur;
+        a.x_next = nxt;
+        LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+        LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+        std::swap(cur, nxt);
+    }
+    *final_x = cur;
+    return EAMFE_OK;
+}
+
+bool ready(eamfe_ctx* c, bool need_pot)
+{
+    if (!c) return false;
+    if (need_pot && !c->have_pot) {
+        c->err = "eam_setup has not been called";
+        return false;
+    }
+    if (c->n_rep == 0) {
+        c->err = "eamfe_system_setup has not been called";
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
+{
+    if (!out || (precision != EAMFE_FP64 && precision != EAMFE_FP32)) return EAMFE_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EAMFE_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return EAMFE_EDEVICE;
+    eamfe_ctx* c = new (std::nothrow) eamfe_ctx();
+    if (!c) return EAMFE_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->precision = precision;
+    int r = EAMFE_OK;
+    if ((r = ensure(c, c->cnt_all_d, sizeof(uint32_t))) || (r = ensure(c, c->iter_d, sizeof(int64_t))) ||
+        (r = ensure(c, c->status_d, sizeof(int32_t)))) {
+        eamfe_destroy(c);
+        return r;
+    }
+    if (hipMemset(c->cnt_all_d.p, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->status_d.p, 0, sizeof(int32_t)) != hipSuccess) {
+        eamfe_destroy(c);
+        return EAMFE_EDEVICE;
+    }
+    *out = c;
+    return EAMFE_OK;
+}
+
+int eamfe_destroy(eamfe_ctx* c)
+{
+    if (!c) return EAMFE_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
+                      &c->xref_d, &c->xalt_d, &c->Fp_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
+                      &c->energy_part_d, &c->noise_sum_d, &c->U_rep_d, &c->W_state_d, &c->cnt_density_d,
+                      &c->cnt_force_d, &c->cnt_all_d, &c->iter_d, &c->rebuild_d, &c->status_d, &c->nbr_d,
+                      &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
+    for (DevBuf* b : bufs) release(*b);
+    delete c;
+    return EAMFE_OK;
+}
+
+const char* eamfe_last_error(const eamfe_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int eamfe_set_stream(eamfe_ctx* c, void* s)
+{
+    if (!c) return EAMFE_EINVAL;
+    c->stream = (hipStream_t)s;
+    return EAMFE_OK;
+}
+
+int eamfe_set_launch(eamfe_ctx* c, int lanes, int block)
+{
+    if (!c) return EAMFE_EINVAL;
+    if (lanes && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
+        return fail(c, EAMFE_EINVAL, "lanes_per_atom must be 1, 2, 4, 8 or 16");
+    if (block && (block < 64 || block > 1024 || block % 64))
+        return fail(c, EAMFE_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+    if (lanes) c->lanes = lanes;
+    if (block) c->block = block;
+    if (c->n_rep) {
+        (void)hipSetDevice(c->device);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return build_tiles(c);
+    }
+    return EAMFE_OK;
+}
+
+int eamfe_get_launch(const eamfe_ctx* c, int* lanes, int* block)
+{
+    if (!c) return EAMFE_EINVAL;
+    if (lanes) *lanes = c->lanes;
+    if (block) *block = c->block;
+    return EAMFE_OK;
+}
+
+int eamfe_set_xcd_affinity(eamfe_ctx* c, int on)
+{
+    if (!c) return EAMFE_EINVAL;
+    c->xcd = on ? 1 : 0;
+    if (c->n_rep) {
+        (void)hipSetDevice(c->device);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return build_tiles(c);
+    }
+    return EAMFE_OK;
+}
+
+int eamfe_check(eamfe_ctx* c)
+{
+    if (!c) return EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    return read_status(c);
+}
+
+int eam_setup(eamfe_ctx* c, int n_r, double r_cut, const double* phi, const double* rho, int n_rho, double rho_max,
+              const double* F)
+{
+    if (!c) return EAMFE_EINVAL;
+    if (n_r < 3 || n_rho < 3 || !(r_cut > 0.0) || !(rho_max > 0.0) || !phi || !rho || !F)
+        return fail(c, EAMFE_EINVAL, "eam_setup: bad table description");
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_r = n_r;
+    c->n_rho = n_rho;
+    c->r_cut = r_cut;
+    c->rho_max = rho_max;
+    c->knots_phi.assign(phi, phi + n_r);
+    c->knots_rho.assign(rho, rho + n_r);
+    c->knots_F.assign(F, F + n_rho);
+    c->c_phi = natural_spline(phi, n_r, r_cut / (n_r - 1));
+    c->c_rho = natural_spline(rho, n_r, r_cut / (n_r - 1));
+    c->c_F = natural_spline(F, n_rho, rho_max / (n_rho - 1));
+    OK(c->precision == EAMFE_FP32 ? upload_tables_t<float>(c) : upload_tables_t<double>(c));
+    c->have_pot = true;
+    c->have_list = false;   // the cutoff may have changed
+    return EAMFE_OK;
+}
+
+int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const double* x0_dev)
+{
+    if (!c) return EAMFE_EINVAL;
+    if (n_rep < 1 || !in || !x0_dev) return fail(c, EAMFE_EINVAL, "system_setup: bad arguments");
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    long N = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const eamfe_replica& q = in[r];
+        if (q.n_atoms < 1 || !(q.mass > 0.0) || !(q.T >= 0.0) || !(q.box[0] > 0 && q.box[1] > 0 && q.box[2] > 0))
+            return fail(c, EAMFE_EINVAL, "replica " + std::to_string(r) + ": bad description");
+        N += q.n_atoms;
+    }
+    if (N > (1L << 30)) return fail(c, EAMFE_EINVAL, "too many atoms");
+    c->n_rep = n_rep;
+    c->N = (int)N;
+    c->reps_in.assign(in, in + n_rep);
+    c->reps.assign(n_rep, RepDesc{});
+    std::vector<int32_t> rep_of(N);
+    int off = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        RepDesc& R = c->reps[r];
+        const eamfe_replica& q = in[r];
+        R.off = off;
+        R.n = q.n_atoms;
+        for (int d = 0; d < 3; ++d) {
+            R.L[d] = q.box[d];
+            R.invL[d] = 1.0 / q.box[d];
+        }
+        R.T = q.T;
+        R.k = q.k;
+        R.k2 = q.k2;
+        R.mass = q.mass;
+        R.inv_m = 1.0 / (q.mass * mvv2e);
+        R.sig_v = std::sqrt(kB * q.T * R.inv_m);
+        R.c2 = 0.0;
+        R.seed = q.seed;
+        for (int i = 0; i < q.n_atoms; ++i) rep_of[off + i] = r;
+        off += q.n_atoms;
+    }
+    const size_t v3 = 3 * (size_t)N * sizeof(double);
+    OK(ensure(c, c->x0_d, v3));
+    OK(ensure(c, c->xref_d, v3));
+    OK(ensure(c, c->xalt_d, v3));
+    OK(ensure(c, c->xi_d, v3));
+    OK(ensure(c, c->Fp_d, (size_t)N * sizeof(double)));
+    OK(ensure(c, c->e_emb_d, (size_t)N * sizeof(double)));
+    OK(ensure(c, c->rep_of_d, (size_t)N * sizeof(int32_t)));
+    OK(ensure(c, c->noise_sum_d, (size_t)n_rep * 3 * sizeof(double)));
+    OK(ensure(c, c->U_rep_d, (size_t)n_rep * 2 * sizeof(double)));
+    OK(ensure(c, c->W_state_d, (size_t)n_rep * sizeof(double)));
+    OK(ensure(c, c->cnt_density_d, (size_t)n_rep * sizeof(uint32_t)));
+    OK(ensure(c, c->cnt_force_d, (size_t)n_rep * sizeof(uint32_t)));
+    OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
+    HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
+    HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
+    HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
+    HIPCHK(c, hipMemset(c->Fp_d.p, 0, (size_t)N * sizeof(double)));
+    HIPCHK(c, hipMemset(c->e_emb_d.p, 0, (size_t)N * sizeof(double)));
+    HIPCHK(c, hipMemcpy(c->rep_of_d.p, rep_of.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->noise_sum_d.p, 0, (size_t)n_rep * 3 * sizeof(double)));
+    HIPCHK(c, hipMemset(c->U_rep_d.p, 0, (size_t)n_rep * 2 * sizeof(double)));
+    HIPCHK(c, hipMemset(c->W_state_d.p, 0, (size_t)n_rep * sizeof(double)));
+    HIPCHK(c, hipMemset(c->cnt_density_d.p, 0, (size_t)n_rep * sizeof(uint32_t)));
+    HIPCHK(c, hipMemset(c->cnt_force_d.p, 0, (size_t)n_rep * sizeof(uint32_t)));
+    HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
+    c->have_list = false;
+    return build_tiles(c);
+}
+
+int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
+{
+    if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!x || !(skin >= 0.0) || max_neighbors < 0) return fail(c, EAMFE_EINVAL, "neigh_build: bad arguments");
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    OK(plan_lists(c, skin, max_neighbors));
+    c->have_list = true;
+    OK(set_rebuild_all(c));
+    NeighArgs na = neigh_args(c, x);
+    LCHK(c, launch_neigh_rebuild(na, c->stream));
+    // the flags are cleared by the next density pass; clear them here too
+    hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
+                       (int32_t*)c->rebuild_d.p, c->n_rep, 0);
+    HIPCHK(c, hipGetLastError());
+    return read_status(c);
+}
+
+int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_atom)
+{
+    if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!x) return fail(c, EAMFE_EINVAL, "eam_forces: null positions");
+    (void)hipSetDevice(c->device);
+    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, x));
+    NeighArgs na = neigh_args(c, x);
+    LCHK(c, launch_neigh_rebuild(na, c->stream));
+    StepArgs a = step_args(c);
+    a.x = x;
+    a.x_next = nullptr;
+    a.v = nullptr;
+    a.has_eam = 1;
+    a.step_kernel = 0;
+    a.mode = EAMFE_MODE_FL;
+    a.f_out = f;
+    a.e_atom_out = e_atom;
+    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+    LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+    if (U)
+        HIPCHK(c, hipMemcpy2DAsync(U, sizeof(double), c->U_rep_d.p, 2 * sizeof(double), sizeof(double), c->n_rep,
+                                   hipMemcpyDeviceToDevice, c->stream));
+    return read_status(c);
+}
+
+int eamfe_init_velocities(eamfe_ctx* c, double* v, int fix_com)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!v) return fail(c, EAMFE_EINVAL, "init_velocities: null v");
+    (void)hipSetDevice(c->device);
+    StepArgs a = step_args(c);
+    a.v = v;
+    LCHK(c, launch_init_velocities(a, c->n_rep, fix_com, c->stream));
+    return EAMFE_OK;
+}
+
+int eamfe_lambda_schedule(const eamfe_protocol* p, double* lam, int64_t* n_steps)
+{
+    if (check_protocol(p)) return EAMFE_EINVAL;
+    const int64_t S = (int64_t)p->n_eq + 2 * (int64_t)p->n_sw + p->n_hold + p->n_hold2;
+    if (n_steps) *n_steps = S;
+    if (!lam) return EAMFE_OK;
+    const bool rs = p->mode == EAMFE_MODE_RS || p->mode == EAMFE_MODE_EIN_RS;
+    const double start = rs ? 1.0 : 0.0;
+    auto f = [&](double tau) { return rs ? lambda_rs(p->lambda_f, tau) : lambda_fl(p->function, tau); };
+    int64_t s = 0;
+    for (int64_t q = 0; q <= p->n_eq; ++q) lam[s++] = start;                // equilibrate at the start point
+    for (int64_t q = 1; q <= p->n_sw; ++q) lam[s++] = f((double)q / p->n_sw);  // forward
+    const double end = lam[s - 1];
+    for (int64_t q = 1; q <= p->n_hold; ++q) lam[s++] = end;                // hold at the end point
+    for (int64_t q = 1; q <= p->n_sw; ++q) lam[s++] = f(1.0 - (double)q / p->n_sw);  // backward (time reverse)
+    for (int64_t q = 1; q <= p->n_hold2; ++q) lam[s++] = start;
+    return s == S + 1 ? EAMFE_OK : EAMFE_EINVAL;
+}
+
+int run_switching(eamfe_ctx* c, const eamfe_protocol* p, int64_t s0, int64_t s1, double* x, double* v,
+                  double* lam_out, double* dHdl_out, double* W_out, int sync)
+{
+    const bool has_eam = p && (p->mode == EAMFE_MODE_FL || p->mode == EAMFE_MODE_RS);
+    if (!ready(c, has_eam)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (check_protocol(p)) return fail(c, EAMFE_EINVAL, "run_switching: bad protocol");
+    if (!x || !v) return fail(c, EAMFE_EINVAL, "run_switching: null x or v");
+    (void)hipSetDevice(c->device);
+    int64_t S = 0;
+    OK(ensure_lambda(c, p, &S));
+    if (s0 < 0 || s1 <= s0 || s1 > S) return fail(c, EAMFE_EINVAL, "run_switching: bad step range");
+    double c1 = 1.0;
+    OK(set_thermostat(c, p, &c1));
+    if (has_eam) OK(ensure_lists(c, p->skin, x));
+    if (lam_out)
+        HIPCHK(c, hipMemcpyAsync(lam_out, c->lam_d.p, (S + 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (s0 == 0) HIPCHK(c, hipMemsetAsync(c->W_state_d.p, 0, (size_t)c->n_rep * sizeof(double), c->stream));
+    StepArgs a = step_args(c);
+    a.v = v;
+    a.lam = (const double*)c->lam_d.p;
+    a.dHdl_out = dHdl_out;
+    a.W_out = W_out;
+    a.S = S;
+    a.mode = p->mode;
+    a.fix_com = p->fix_com ? 1 : 0;
+    a.dt = p->dt;
+    a.c1 = c1;
+    double* fin = nullptr;
+    OK(iterate(c, a, x, has_eam, s0, s1, &fin));
+    if (fin != x)
+        HIPCHK(c, hipMemcpyAsync(x, fin, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (sync) return read_status(c);
+    return EAMFE_OK;
+}
+
+int switch_step(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, double* x, double* v, double* W, double* dHdl)
+{
+    const bool has_eam = p && (p->mode == EAMFE_MODE_FL || p->mode == EAMFE_MODE_RS);
+    if (!ready(c, has_eam)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (check_protocol(p) || !x || !v || !W) return fail(c, EAMFE_EINVAL, "switch_step: bad arguments");
+    (void)hipSetDevice(c->device);
+    int64_t S = 0;
+    OK(ensure_lambda(c, p, &S));
+    if (step < 0 || step >= S) return fail(c, EAMFE_EINVAL, "switch_step: step out of range");
+    double c1 = 1.0;
+    OK(set_thermostat(c, p, &c1));
+    if (has_eam) OK(ensure_lists(c, p->skin, x));
+    HIPCHK(c, hipMemcpyAsync(c->W_state_d.p, W, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    StepArgs a = step_args(c);
+    a.v = v;
+    a.lam = (const double*)c->lam_d.p;
+    // one-step trace: column it - step of a [n_rep][1] array
+    a.S = 1;
+    a.trace_off = step;
+    a.dHdl_out = dHdl;
+    a.W_out = nullptr;
+    a.mode = p->mode;
+    a.fix_com = p->fix_com ? 1 : 0;
+    a.dt = p->dt;
+    a.c1 = c1;
+    double* fin = nullptr;
+    OK(iterate(c, a, x, has_eam, step, step + 1, &fin));
+    if (fin != x)
+        HIPCHK(c, hipMemcpyAsync(x, fin, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(W, c->W_state_d.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    return read_status(c);
+}
+
+int eamfe_get_work(eamfe_ctx* c, double* W)
+{
+    if (!ready(c, false) || !W) return c ? EAMFE_EINVAL : EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(W, c->W_state_d.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToHost));
+    return EAMFE_OK;
+}
+
+int eamfe_adjoint_theta(eamfe_ctx* c, const double*, double, double*)
+{
+    return fail(c, EAMFE_ESTATE, "adjoint not built yet");
+}
+
+// ---- estimators -------------------------------------------------------------
+double eamfe_einstein_free_energy(double n_eff, double T, double k, double mass)
+{
+    const double omega = std::sqrt(k / (mass * mvv2e));
+    return 3.0 * n_eff * kB * T * std::log(hbar * omega / (kB * T));
+}
+
+double eamfe_fixed_cm_correction(double N, double V, double T, double k)
+{
+    return kB * T * std::log(N / V * std::pow(2.0 * M_PI * kB * T / (N * k), 1.5));
+}
+
+int eamfe_fl_free_energy(int n, const double* Wf, const double* Wb, double n_eff, double N, double V, double T,
+                         double k, double mass, int add_cm, double* F0, double* Ediss, double* err)
+{
+    if (n < 1 || !Wf || !Wb) return EAMFE_EINVAL;
+    double mf = 0.0, mb = 0.0;
+    for (int i = 0; i < n; ++i) {
+        mf += Wf[i];
+        mb += Wb[i];
+    }
+    mf /= n;
+    mb /= n;
+    // Eq. W12 with 1 = H0 and 2 = H_E: F_E - F0 = (W_fwd - W_bwd)/2
+    const double dF = 0.5 * (mf - mb);
+    double F = eamfe_einstein_free_energy(n_eff, T, k, mass) - dF;
+    if (add_cm) F += eamfe_fixed_cm_correction(N, V, T, k);
+    if (F0) *F0 = F;
+    if (Ediss) *Ediss = 0.5 * (mf + mb);
+    if (err) {
+        double var = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double d = 0.5 * (Wf[i] - Wb[i]) - dF;
+            var += d * d;
+        }
+        *err = n > 1 ? std::sqrt(var / (n - 1) / n) : NAN;
+    }
+    return EAMFE_OK;
+}
+
+int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W, double F0_T0, double T0, double n_eff, int n_T,
+                         const double* T_grid, double* F_out)
+{
+    if (check_protocol(p) || !W || n_T < 1 || !T_grid || !F_out) return EAMFE_EINVAL;
+    const int64_t n_eq = p->n_eq, n_sw = p->n_sw, b0 = p->n_eq + p->n_sw + p->n_hold;
+    const double Tf = T0 / p->lambda_f;
+    // cumulative work after q forward (backward) steps, q = 0..n_sw
+    auto fwd = [&](int64_t q) { return q == 0 ? 0.0 : W[n_eq + q - 1] - (n_eq ? W[n_eq - 1] : 0.0); };
+    auto bwd = [&](int64_t q) { return q == 0 ? 0.0 : W[b0 + q - 1] - W[b0 - 1]; };
+    auto interp = [&](auto&& g, double pos) {
+        if (pos <= 0.0) return g(0);
+        if (pos >= (double)n_sw) return g(n_sw);
+        const int64_t q = (int64_t)std::floor(pos);
+        const double w = pos - q;
+        return (1.0 - w) * g(q) + w * g(q + 1);
+    };
+    const double wb_total = bwd(n_sw);
+    for (int k = 0; k < n_T; ++k) {
+        const double T = T_grid[k];
+        if (!(T >= T0 * (1 - 1e-12) && T <= Tf * (1 + 1e-12))) return EAMFE_EINVAL;
+        const double lam = T0 / T;
+        const double tau = (T - T0) / (Tf - T0);
+        const double w1 = interp(fwd, tau * n_sw);                         // W_{1 -> lambda}
+        const double w2 = wb_total - interp(bwd, (1.0 - tau) * n_sw);      // W_{lambda -> 1}
+        F_out[k] = F0_T0 / lam + 1.5 * n_eff * kB * T0 * std::log(lam) / lam + (w1 - w2) / (2.0 * lam);
+    }
+    return EAMFE_OK;
+}
+
+}  // extern "C"

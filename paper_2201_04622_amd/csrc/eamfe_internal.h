@@ -1,0 +1,159 @@
+// Internal declarations shared by the host orchestration (eamfe_host.cpp) and
+// the gfx950 kernels (eamfe_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace eamfe {
+
+// Units: LAMMPS metal.
+constexpr double kB = 8.617333262e-5;      // eV/K
+constexpr double hbar = 6.582119569e-4;    // eV ps
+constexpr double mvv2e = 1.0364269e-4;     // eV per amu A^2/ps^2
+
+// Device status bits (latched with atomicOr, mapped to EAMFE_E* on read).
+enum : int {
+    ST_NEIGH_OVERFLOW = 1,
+    ST_CELL_OVERFLOW = 2,
+    ST_TABLE_RANGE = 4,
+    ST_NONFINITE = 8,
+};
+
+enum : int { MODE_FL = 0, MODE_RS = 1, MODE_HH = 2, MODE_EIN_RS = 3 };
+
+// Fixed-point quantum of the FP32 accumulators: sums are carried as exact
+// integers (multiples of 2^-32) inside float64, so addition is associative.
+constexpr double kFixScale = 4294967296.0;          // 2^32
+constexpr double kFixInv = 2.3283064365386963e-10;  // 2^-32
+
+// Replica descriptor as the kernels see it.
+struct RepDesc {
+    int32_t off;        // first global atom
+    int32_t n;          // atoms
+    int32_t tile_base;  // first slot of this replica in per-tile partial arrays
+    int32_t n_tiles;
+    int32_t cell_base;  // first global cell
+    int32_t nc[3];      // cells per edge; nc[0] == 0 selects all-pairs lists
+    double L[3];
+    double invL[3];
+    double T, k, k2, mass;
+    double inv_m;       // 1 / (m mvv2e): (A/ps^2) per (eV/A)
+    double sig_v;       // sqrt(kB T / (m mvv2e)), A/ps
+    double c2;          // thermostat noise amplitude of the current protocol
+    uint64_t seed;
+};
+
+// A tile is a contiguous run of atoms of one replica handled by one block.
+struct Tile {
+    int32_t rep;
+    int32_t first;   // global atom index of the first atom
+    int32_t count;   // atoms in the tile (0 for padding tiles)
+    int32_t idx;     // tile index within its replica
+};
+
+// Spline tables (device pointers, element type set by precision).
+// pair[m]: {phi a, b, c, d, rho' b/h, 2c/h, 3d/h, 0}; rho[m], F[m]: {a, b, c, d}
+struct Tables {
+    const void* pair;
+    const void* rho;
+    const void* F;
+    int n_r, n_rho;
+    double r_cut, rc2, inv_h_r, inv_h_rho, rho_max;
+};
+
+struct NeighArgs {
+    const Tile* tiles;
+    const RepDesc* reps;
+    const int32_t* rep_of;      // [N] replica of each atom
+    const int32_t* cell_rep;    // [n_cells] replica of each cell
+    const double* x;            // SoA [3][N]
+    double* xref;               // SoA [3][N]
+    int32_t* cell_cnt;          // [n_cells]
+    int32_t* cell_n;            // [n_cells] sorted occupancy
+    int32_t* cell_atoms;        // [n_cells][ccap] local atom ids
+    int32_t* nbr;               // [N][cap] global atom ids
+    int32_t* nnb;               // [N]
+    int32_t* rebuild;           // [n_rep] flags
+    int32_t* status;
+    int N, n_cells, ccap, cap;
+    double rl2;                 // (r_cut + skin)^2
+    double half_skin2;          // (skin/2)^2
+};
+
+// Everything one MD iteration's kernels need.
+struct StepArgs {
+    const Tile* tiles;
+    const RepDesc* reps;
+    const double* x;        // positions at the start of the iteration (SoA)
+    double* x_next;         // positions after the step (SoA)
+    double* v;              // SoA, in place
+    const double* x0;       // SoA
+    const double* xref;     // SoA, list reference positions
+    const int32_t* nbr;
+    const int32_t* nnb;
+    int cap;
+    void* Fp;               // [N] F'(rho_i), element type = precision
+    double* e_emb;          // [N] F(rho_i)
+    double* xi;             // [3][N] thermostat noise of this step
+    double* noise_part;     // [tiles][3]
+    double* noise_sum;      // [n_rep][3]
+    double* energy_part;    // [tiles][2]
+    double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
+    uint32_t* cnt_density;  // [n_rep]
+    uint32_t* cnt_force;    // [n_rep]
+    uint32_t* cnt_all;      // [1]
+    int32_t* rebuild;       // [n_rep]
+    int32_t* status;
+    const double* lam;      // lambda table [S+1]
+    int64_t* iter;          // device iteration counter (global step index)
+    int64_t it_first;       // first iteration of this launch sequence: no closing kick
+    int64_t it_last;        // last iteration: no new step (only the closing kick)
+    double* dHdl_out;       // [n_rep][S] or null
+    double* W_out;          // [n_rep][S] or null
+    int64_t S;              // row stride of the traces
+    int64_t trace_off;      // trace column = it - trace_off
+    double* W_state;        // [n_rep]
+    double* f_out;          // SoA [3][N] EAM forces or null
+    double* e_atom_out;     // [N] per-atom EAM energy or null
+    Tables tab;
+    int N;
+    int mode;
+    int fix_com;
+    int has_eam;
+    int n_tiles;            // real (non-padding) tiles
+    int n_grid;             // launched blocks = tiles including padding
+    int step_kernel;        // 1: integrate; 0: evaluate only (eam_forces)
+    double dt;
+    double c1;
+    double half_skin2;
+};
+
+struct AdjointArgs {
+    const Tile* tiles;
+    const RepDesc* reps;
+    const double* x;
+    const int32_t* nbr;
+    const int32_t* nnb;
+    int cap;
+    const void* Fp;
+    const double* rho;        // [N] densities (float64)
+    unsigned long long* bins; // [n_rep][3][n-1][4] fixed-point sums (2^-32 quanta, two's complement)
+    Tables tab;
+    int N;
+    int n_tiles;
+};
+
+// Launchers (eamfe_kernels.hip).  Each returns a hipError_t as int.
+int launch_check_displacement(const NeighArgs& a, hipStream_t s);
+int launch_neigh_rebuild(const NeighArgs& a, hipStream_t s);
+int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
+int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
+int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);
+int launch_adjoint(const AdjointArgs& a, const StepArgs& d, int precision, int lanes, int block, hipStream_t s);
+int launch_adjoint_finish(const unsigned long long* bins, int n_rep, int n, double scale, double* coef_grad,
+                          hipStream_t s);
+int launch_rho_dump(const StepArgs& a, double* rho_out, int precision, int lanes, int block, hipStream_t s);
+
+}  // namespace eamfe

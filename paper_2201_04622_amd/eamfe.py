@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in include/eamfe.h (ctypes; argument marshalling only).
+
+Device arrays are torch tensors on a ROCm device, float64, SoA [3, N]
+(positions, velocities, forces) or flat; the library reads and writes them
+through data_ptr() on torch's current HIP stream.  Every computation happens
+in the HIP library; if it is not built this module raises on import of the
+library (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeamfe.so")
+
+FP64, FP32 = 0, 1
+MODES = {"fl": 0, "rs": 1, "hh": 2, "ein_rs": 3}
+ERRORS = {
+    0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EBOX",
+    6: "ENEIGH_OVERFLOW", 7: "ECELL_OVERFLOW", 8: "ETABLE_RANGE", 9: "ENONFINITE",
+}
+
+
+class EamfeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Replica(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("pad_", C.c_int32), ("box", C.c_double * 3), ("T", C.c_double),
+                ("k", C.c_double), ("k2", C.c_double), ("mass", C.c_double), ("seed", C.c_uint64)]
+
+
+class Protocol(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("function", C.c_int32), ("fix_com", C.c_int32), ("n_eq", C.c_int32),
+                ("n_sw", C.c_int32), ("n_hold", C.c_int32), ("n_hold2", C.c_int32), ("pad_", C.c_int32),
+                ("dt", C.c_double), ("damp", C.c_double), ("lambda_f", C.c_double), ("skin", C.c_double)]
+
+
+_dp = C.POINTER(C.c_double)
+_lib = None
+
+
+def lib():
+    """Load the built library; raise if it is missing (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "eamfe_create": (i32, [C.POINTER(vp), i32, vp, i32]),
+        "eamfe_destroy": (i32, [vp]),
+        "eamfe_last_error": (C.c_char_p, [vp]),
+        "eamfe_set_stream": (i32, [vp, vp]),
+        "eamfe_set_launch": (i32, [vp, i32, i32]),
+        "eamfe_get_launch": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "eamfe_set_xcd_affinity": (i32, [vp, i32]),
+        "eamfe_check": (i32, [vp]),
+        "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
+        "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
+        "neigh_build": (i32, [vp, vp, dbl, i32]),
+        "eam_forces": (i32, [vp, vp, vp, vp, vp]),
+        "eamfe_init_velocities": (i32, [vp, vp, i32]),
+        "eamfe_lambda_schedule": (i32, [C.POINTER(Protocol), _dp, C.POINTER(i64)]),
+        "run_switching": (i32, [vp, C.POINTER(Protocol), i64, i64, vp, vp, vp, vp, vp, i32]),
+        "switch_step": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, vp, vp]),
+        "eamfe_get_work": (i32, [vp, _dp]),
+        "eamfe_adjoint_theta": (i32, [vp, vp, dbl, vp]),
+        "eamfe_einstein_free_energy": (dbl, [dbl, dbl, dbl, dbl]),
+        "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
+        "eamfe_fl_free_energy": (i32, [i32, _dp, _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp, _dp]),
+        "eamfe_rs_free_energy": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, i32, _dp, _dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def protocol(mode="fl", n_eq=0, n_sw=1, n_hold=0, n_hold2=0, function=2, lambda_f=1.0, dt=0.001, damp=0.1,
+             fix_com=True, skin=0.3) -> Protocol:
+    return Protocol(MODES[mode] if isinstance(mode, str) else int(mode), int(function), int(bool(fix_com)),
+                    int(n_eq), int(n_sw), int(n_hold), int(n_hold2), 0, float(dt), float(damp), float(lambda_f),
+                    float(skin))
+
+
+def protocol_from_schedule(sch, skin=0.3) -> Protocol:
+    """From paper_2201_04622_amd.inputs.Schedule."""
+    return protocol(sch.mode, sch.n_eq, sch.n_sw, sch.n_hold, sch.n_hold2, sch.function, sch.lambda_f, sch.dt,
+                    sch.damp, sch.fix_com, skin)
+
+
+def lambda_schedule(p: Protocol) -> np.ndarray:
+    S = C.c_int64()
+    _chk(None, lib().eamfe_lambda_schedule(C.byref(p), None, C.byref(S)))
+    lam = np.zeros(S.value + 1)
+    _chk(None, lib().eamfe_lambda_schedule(C.byref(p), lam.ctypes.data_as(_dp), C.byref(S)))
+    return lam
+
+
+def einstein_free_energy(n_eff, T, k, mass):
+    return lib().eamfe_einstein_free_energy(float(n_eff), float(T), float(k), float(mass))
+
+
+def fixed_cm_correction(N, V, T, k):
+    return lib().eamfe_fixed_cm_correction(float(N), float(V), float(T), float(k))
+
+
+def fl_free_energy(W_fwd, W_bwd, n_eff, T, k, mass, N=None, V=None):
+    Wf = np.ascontiguousarray(W_fwd, dtype=np.float64)
+    Wb = np.ascontiguousarray(W_bwd, dtype=np.float64)
+    F0, Ed, err = C.c_double(), C.c_double(), C.c_double()
+    add = N is not None and V is not None
+    _chk(None, lib().eamfe_fl_free_energy(len(Wf), Wf.ctypes.data_as(_dp), Wb.ctypes.data_as(_dp), float(n_eff),
+                                          float(N or 0), float(V or 0), float(T), float(k), float(mass), int(add),
+                                          C.byref(F0), C.byref(Ed), C.byref(err)))
+    return F0.value, Ed.value, err.value
+
+
+def rs_free_energy(p: Protocol, W_trace, F0_T0, T0, n_eff, T_grid):
+    W = np.ascontiguousarray(W_trace, dtype=np.float64)
+    Tg = np.ascontiguousarray(T_grid, dtype=np.float64)
+    out = np.zeros_like(Tg)
+    _chk(None, lib().eamfe_rs_free_energy(C.byref(p), W.ctypes.data_as(_dp), float(F0_T0), float(T0), float(n_eff),
+                                          len(Tg), Tg.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+    return out
+
+
+def _chk(ctx, code, what=""):
+    if code != 0:
+        msg = lib().eamfe_last_error(ctx).decode() if ctx else what
+        raise EamfeError(code, msg or what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "device float64 contiguous tensor expected"
+    return C.c_void_p(t.data_ptr())
+
+
+def to_soa(x_aos, device="cuda"):
+    """[N, 3] host array -> float64 [3, N] device tensor."""
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(x_aos, dtype=np.float64).T), device=device).contiguous()
+
+
+def from_soa(t) -> np.ndarray:
+    return t.detach().cpu().numpy().T.copy()
+
+
+class Context:
+    """An eamfe_ctx on one device.  Methods are the ABI entry points."""
+
+    def __init__(self, device: int = 0, precision: int = FP64, stream=None):
+        import torch
+        self._lib = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        code = self._lib.eamfe_create(C.byref(h), int(device), C.c_void_p(stream), int(precision))
+        if code:
+            raise EamfeError(code, "eamfe_create failed")
+        self._h = h
+        self.precision = precision
+        self.n_rep = 0
+        self.N = 0
+        self.offsets = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.eamfe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, code):
+        _chk(self._h, code)
+
+    # -- configuration -------------------------------------------------------
+    def set_launch(self, lanes_per_atom=0, block_threads=0):
+        self._c(self._lib.eamfe_set_launch(self._h, int(lanes_per_atom), int(block_threads)))
+
+    def get_launch(self):
+        a, b = C.c_int(), C.c_int()
+        self._c(self._lib.eamfe_get_launch(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_xcd_affinity(self, on: bool):
+        self._c(self._lib.eamfe_set_xcd_affinity(self._h, int(bool(on))))
+
+    def check(self):
+        self._c(self._lib.eamfe_check(self._h))
+
+    # -- ABI -----------------------------------------------------------------
+    def eam_setup(self, knots):
+        """knots: paper_2201_04622_amd.inputs.PotentialKnots."""
+        phi = np.ascontiguousarray(knots.phi, dtype=np.float64)
+        rho = np.ascontiguousarray(knots.rho, dtype=np.float64)
+        F = np.ascontiguousarray(knots.embed, dtype=np.float64)
+        self._c(self._lib.eam_setup(self._h, len(phi), float(knots.r_cut), phi.ctypes.data_as(_dp),
+                                    rho.ctypes.data_as(_dp), len(F), float(knots.rho_max), F.ctypes.data_as(_dp)))
+
+    def system_setup(self, replicas: Sequence, x0_soa):
+        """replicas: inputs.Replica list; x0_soa: device float64 [3, N_tot]."""
+        arr = (Replica * len(replicas))()
+        for q, r in zip(arr, replicas):
+            q.n_atoms = r.natoms
+            for d in range(3):
+                q.box[d] = float(r.box[d])
+            q.T, q.k, q.k2, q.mass, q.seed = float(r.T), float(r.k), float(r.k2), float(r.mass), int(r.seed)
+        self._c(self._lib.eamfe_system_setup(self._h, len(replicas), arr, _ptr(x0_soa)))
+        self.n_rep = len(replicas)
+        self.N = int(x0_soa.shape[1])
+        self.offsets = np.concatenate([[0], np.cumsum([r.natoms for r in replicas])])
+
+    def neigh_build(self, x, skin=0.3, max_neighbors=0):
+        self._c(self._lib.neigh_build(self._h, _ptr(x), float(skin), int(max_neighbors)))
+
+    def eam_forces(self, x, f=None, U=None, e_atom=None):
+        self._c(self._lib.eam_forces(self._h, _ptr(x), _ptr(f), _ptr(U), _ptr(e_atom)))
+
+    def init_velocities(self, v, fix_com=True):
+        self._c(self._lib.eamfe_init_velocities(self._h, _ptr(v), int(bool(fix_com))))
+
+    def run_switching(self, p: Protocol, x, v, step_begin=0, step_end=None, lam_out=None, dHdl_out=None, W_out=None,
+                      sync=True):
+        if step_end is None:
+            S = C.c_int64()
+            _chk(None, self._lib.eamfe_lambda_schedule(C.byref(p), None, C.byref(S)))
+            step_end = S.value
+        self._c(self._lib.run_switching(self._h, C.byref(p), int(step_begin), int(step_end), _ptr(x), _ptr(v),
+                                        _ptr(lam_out), _ptr(dHdl_out), _ptr(W_out), int(bool(sync))))
+
+    def switch_step(self, p: Protocol, step, x, v, W, dHdl=None):
+        self._c(self._lib.switch_step(self._h, C.byref(p), int(step), _ptr(x), _ptr(v), _ptr(W), _ptr(dHdl)))
+
+    def get_work(self):
+        W = np.zeros(self.n_rep)
+        self._c(self._lib.eamfe_get_work(self._h, W.ctypes.data_as(_dp)))
+        return W
+
+    def adjoint_theta(self, x, dtheta, scale=1.0):
+        self._c(self._lib.eamfe_adjoint_theta(self._h, _ptr(x), float(scale), _ptr(dtheta)))

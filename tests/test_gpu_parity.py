@@ -1,0 +1,251 @@
+"""GPU <-> oracle parity through the C ABI.
+
+Forces and energies (FP64 to 1e-12, FP32 to 1e-5, normwise and per
+component against the rms force), neighbour-list edge cases, bit-identical
+FP32 results across launch shapes, same-noise trajectories step by step,
+initial velocities, the harmonic -> harmonic closed form run on the GPU, and
+the error paths the host can force."""
+import numpy as np
+import pytest
+
+from gpu_common import make_ctx, rel_norm, say, split
+from paper_2201_04622_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOL = {FP64: 1e-12, FP32: 1e-5}
+ETOL = {FP64: 1e-13, FP32: 1e-6}
+
+
+def _mixed_batch():
+    # uneven sizes, both lattices, verbatim and stable densities, all-pairs and cell lists
+    return [
+        I.Replica("bcc", 4, I.A_BCC_VERBATIM, 300.0, 5.0, 1),    # 128 atoms, L = 11.42 -> all-pairs
+        I.Replica("fcc", 5, I.A_FCC_VERBATIM, 600.0, 5.0, 2),    # 500, cells 3^3
+        I.Replica("bcc", 7, I.A_BCC_STABLE, 900.0, 5.0, 3),      # 686 at high density
+        I.Replica("fcc", 5, I.A_FCC_STABLE, 1200.0, 3.0, 4),     # 500 at high density
+        I.Replica("bcc", 9, I.A_BCC_VERBATIM, 100.0, 5.0, 5),    # 1458, cells 4^3
+    ]
+
+
+def _oracle_forces(opot, reps, x_aos, offsets):
+    out = []
+    for r, xr in zip(reps, split(x_aos, offsets)):
+        out.append(opot.eam(xr, r.box))
+    return out
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("lanes,block", [(1, 64), (4, 256), (16, 1024), (8, 128)])
+def test_forces_and_energies_batched(opot, prec, lanes, block):
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    say(f"forces: prec={prec} lanes={lanes} block={block}")
+    reps = _mixed_batch()
+    ctx, x0, arrs = make_ctx(reps, prec, lanes, block)
+    x = I.displaced(arrs["x0"], 0.05, seed=11)
+    xd = E.to_soa(x)
+    ctx.neigh_build(xd, 0.3, 0)
+    f = torch.zeros_like(xd)
+    U = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+    ea = torch.zeros(xd.shape[1], dtype=torch.float64, device="cuda")
+    ctx.eam_forces(xd, f, U, ea)
+    fg = E.from_soa(f)
+    eg = ea.cpu().numpy()
+    ref = _oracle_forces(opot, reps, x, ctx.offsets)
+    for r, (fr, er, o) in enumerate(zip(split(fg, ctx.offsets), split(eg, ctx.offsets), ref)):
+        rms = np.sqrt((o["f"] ** 2).mean())
+        assert rel_norm(fr, o["f"]) <= TOL[prec], (r, rel_norm(fr, o["f"]))
+        assert np.abs(fr - o["f"]).max() <= TOL[prec] * rms * 10, r
+        assert abs(U[r].item() - o["U"]) <= ETOL[prec] * abs(o["U"]), (r, U[r].item(), o["U"])
+        assert np.abs(er - o["e_atom"]).max() <= ETOL[prec] * 100 * np.abs(o["e_atom"]).max()
+    ctx.close()
+
+
+def test_fp32_bitwise_identical_across_launch_shapes():
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()
+    x = None
+    outs = []
+    for lanes, block in ((1, 64), (2, 256), (4, 512), (8, 1024), (16, 256)):
+        say(f"fp32 shape {lanes}x{block}")
+        ctx, x0, arrs = make_ctx(reps, FP32, lanes, block)
+        if x is None:
+            x = I.displaced(arrs["x0"], 0.06, seed=3)
+        xd = E.to_soa(x)
+        ctx.neigh_build(xd, 0.3, 0)
+        f = torch.zeros_like(xd)
+        U = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+        ctx.eam_forces(xd, f, U)
+        outs.append((f.cpu().numpy(), U.cpu().numpy()))
+        ctx.close()
+    for f, U in outs[1:]:
+        assert np.array_equal(f, outs[0][0])
+        assert np.array_equal(U, outs[0][1])
+
+
+def test_lists_rebuild_after_large_moves_and_skin_zero(opot):
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = [I.Replica("fcc", 6, I.A_FCC_VERBATIM, 300.0, 5.0, 9)]
+    ctx, x0, arrs = make_ctx(reps, FP64)
+    ctx.neigh_build(x0, 0.0, 0)       # skin 0: any motion forces a rebuild
+    for seed in (1, 2, 3):
+        x = I.displaced(arrs["x0"], 0.4, seed=seed) + 7.3   # big moves, shifted out of the box (unwrapped)
+        xd = E.to_soa(x)
+        f = torch.zeros_like(xd)
+        U = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.eam_forces(xd, f, U)
+        o = opot.eam(x, reps[0].box)
+        assert rel_norm(E.from_soa(f), o["f"]) < 1e-12
+        assert U.item() == pytest.approx(o["U"], rel=1e-13)
+    ctx.close()
+
+
+def test_neighbor_overflow_reported():
+    import paper_2201_04622_amd.eamfe as E
+    reps = [I.Replica("bcc", 6, I.A_BCC_VERBATIM, 300.0, 5.0, 9)]
+    ctx, x0, arrs = make_ctx(reps, FP64)
+    with pytest.raises(E.EamfeError) as e:
+        ctx.neigh_build(x0, 0.3, 8)     # 58 neighbours per atom do not fit in 8
+    assert e.value.code == 6
+    ctx.close()
+
+
+def test_small_box_rejected():
+    import paper_2201_04622_amd.eamfe as E
+    reps = [I.Replica("bcc", 3, I.A_BCC_VERBATIM, 300.0, 5.0, 9)]   # L = 8.57 < 2 (5.3 + 0.3)
+    ctx, x0, arrs = make_ctx(reps, FP64)
+    with pytest.raises(E.EamfeError) as e:
+        ctx.neigh_build(x0, 0.3, 0)
+    assert e.value.code == 5
+    ctx.close()
+
+
+def test_init_velocities_match_oracle(oracle_lib):
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()
+    ctx, x0, arrs = make_ctx(reps, FP64)
+    for fix in (True, False):
+        v = torch.zeros_like(x0)
+        ctx.init_velocities(v, fix)
+        vg = E.from_soa(v)
+        for r, vr in zip(reps, split(vg, ctx.offsets)):
+            p = oracle_lib.RunParams(T=r.T, seed=r.seed, fix_com=fix, mass=r.mass)
+            vo = oracle_lib.init_velocities(p, r.natoms)
+            assert np.abs(vr - vo).max() < 1e-12 * np.abs(vo).max()
+    ctx.close()
+
+
+def _oracle_traj(oracle_lib, opot, r, x, v, lam, mode, fix_com, step0=0):
+    p = oracle_lib.RunParams(mode=mode, T=r.T, k=r.k, k2=r.k2, seed=r.seed, fix_com=fix_com, mass=r.mass)
+    xo, vo = x.copy(), v.copy()
+    dH, W, _, _ = oracle_lib.run(opot if mode in ("fl", "rs") else None, p, r.sites(), r.box, xo, vo, lam,
+                                 step0=step0)
+    return xo, vo, dH, W
+
+
+@pytest.mark.parametrize("prec,mode", [(FP64, "fl"), (FP64, "rs"), (FP32, "fl")])
+def test_same_noise_trajectory(oracle_lib, opot, prec, mode):
+    """Every replica's x, v, dH/dl and W follow the oracle step by step."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    say(f"trajectory prec={prec} mode={mode}")
+    reps = _mixed_batch()[:4]
+    ctx, x0, arrs = make_ctx(reps, prec, 4, 256)
+    n_eq, n_sw, n_hold, n_hold2 = 10, 30, 5, 5
+    p = E.protocol(mode, n_eq, n_sw, n_hold, n_hold2, function=2, lambda_f=0.5)
+    S = n_eq + 2 * n_sw + n_hold + n_hold2
+    x = x0.clone()
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, True)
+    v_init = E.from_soa(v)
+    dH = torch.zeros(len(reps), S, dtype=torch.float64, device="cuda")
+    W = torch.zeros_like(dH)
+    # two calls: the protocol can be split anywhere
+    ctx.run_switching(p, x, v, 0, 37, None, dH, W)
+    ctx.run_switching(p, x, v, 37, S, None, dH, W)
+    lam = oracle_lib.schedule(mode, n_eq, n_sw, n_hold, n_hold2, function=2, lambda_f=0.5)
+    xg, vg = E.from_soa(x), E.from_soa(v)
+    dHg, Wg = dH.cpu().numpy(), W.cpu().numpy()
+    tol = 1e-9 if prec == FP64 else 2e-3
+    for r, (rep, xr, vr, vi) in enumerate(zip(reps, split(xg, ctx.offsets), split(vg, ctx.offsets),
+                                               split(v_init, ctx.offsets))):
+        xo, vo, dHo, Wo = _oracle_traj(oracle_lib, opot, rep, rep.sites(), vi, lam, mode, True)
+        scale_w = max(1.0, np.abs(dHo).max())
+        assert np.abs(xr - xo).max() < tol, (r, np.abs(xr - xo).max())
+        assert np.abs(vr - vo).max() < tol * 100, (r, np.abs(vr - vo).max())
+        assert np.abs(dHg[r] - dHo).max() < tol * scale_w, (r, np.abs(dHg[r] - dHo).max())
+        assert np.abs(Wg[r] - Wo).max() < tol * scale_w, (r, np.abs(Wg[r] - Wo).max())
+    ctx.close()
+
+
+def test_switch_step_matches_run_switching():
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()[:3]
+    p = E.protocol("fl", 3, 6, 2, 1)
+    res = []
+    for how in ("run", "step"):
+        ctx, x0, arrs = make_ctx(reps, FP64)
+        x = x0.clone()
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        if how == "run":
+            W = torch.zeros(len(reps), 18, dtype=torch.float64, device="cuda")
+            ctx.run_switching(p, x, v, 0, 18, None, None, W)
+            w = W[:, -1].clone()
+        else:
+            w = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+            dh = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+            for s in range(18):
+                ctx.switch_step(p, s, x, v, w, dh)
+        res.append((x.cpu().numpy(), v.cpu().numpy(), w.cpu().numpy()))
+        ctx.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+def test_harmonic_switching_on_gpu_reaches_closed_form(oracle_lib):
+    """H(l) = (1-l) U_E(k1) + l U_E(k2): the forward/backward estimate run on the
+    GPU reaches (3(N-1)/2) kT ln(k2/k1), and every replica's work trace equals
+    the oracle's for the same noise."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    from oracle import estimators as OE
+    kB = 8.617333262e-5
+    T, k1, k2 = 300.0, 2.0, 8.0
+    reps = [I.Replica("bcc", 3, 3.0, T, k1, 100 + s, k2=k2) for s in range(32)]   # 54 atoms each
+    ctx, x0, arrs = make_ctx(reps, FP64)
+    n_eq, n_sw = 1500, 6000
+    p = E.protocol("hh", n_eq, n_sw, n_eq, 0)
+    S = n_eq * 2 + 2 * n_sw
+    x = x0.clone()
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, True)
+    v0 = E.from_soa(v)
+    W = torch.zeros(len(reps), S, dtype=torch.float64, device="cuda")
+    ctx.run_switching(p, x, v, 0, S, None, None, W)
+    Wg = W.cpu().numpy()
+    Wf = Wg[:, n_eq + n_sw - 1]
+    Wb = Wg[:, -1] - Wf
+    dF, ediss, err = OE.forward_backward(Wf, Wb)
+    N = reps[0].natoms
+    exact = 1.5 * (N - 1) * kB * T * np.log(k2 / k1)
+    assert abs(dF - exact) < 4 * err
+    lam = oracle_lib.schedule("hh", n_eq, n_sw, n_eq, 0)
+    for r in (0, 7, 31):
+        _, _, _, Wo = _oracle_traj(oracle_lib, None, reps[r], reps[r].sites(), split(v0, ctx.offsets)[r], lam, "hh",
+                                   True)
+        assert np.abs(Wg[r] - Wo).max() < 1e-9
+    ctx.close()
