@@ -1,0 +1,210 @@
+#!/usr/bin/env python
+"""Throughput of batched EAM switching MD on one MI355X.
+
+Default workload: 64 independent Frenkel--Ladd switching replicas of uneven
+size (bcc 6..12^3 and fcc 5..10^3 cubic supercells, 113,090 atoms, T on a
+16-point grid over 100..1600 K, k = 5 eV/A^2, 20k forward + 20k backward
+steps with 2k-step holds), FP32 pair arithmetic with FP64 positions,
+energies and work, one launch per pass over all replicas.
+
+A "step" is one MD step of every replica: neighbour-list upkeep, density
+pass, force pass with the fused spring/blend/BAOAB update and the work
+increment.  The metric is atom-steps/s over the K timed steps (inputs
+resident on the device, protocol continued from the W warm-up steps).
+
+Also reported: the plain single-replica FP64 path (bcc 10^3, 2000 atoms),
+the dominant kernel's roofline figure from HIP events recorded on its
+stream, and the FP64 CPU oracle timed on a bounded sample on the host.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def force_bytes_per_atom(n_list, prec):
+    """Algorithmic bytes of the force pass per atom: x read and written,
+    v read and written, x0 read (3 x 8 B each), own F' (4 or 8 B), the row
+    length (4 B) and the row of n_list int32 neighbour ids.  Neighbour
+    positions and F' gathers are reuse of data already counted."""
+    fp = 4 if prec == "fp32" else 8
+    return 24 * 2 + 24 * 2 + 24 + fp + 4 + 4 * n_list
+
+
+def density_bytes_per_atom(n_list, prec):
+    """x read, row length and row, F' and F written."""
+    fp = 4 if prec == "fp32" else 8
+    return 24 + 4 + 4 * n_list + fp + 8
+
+
+def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None):
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    from paper_2201_04622_amd import inputs as I
+
+    wl = I.workload(workload)
+    sch = wl.schedule
+    # extend the trailing hold so the protocol covers warm-up + timed steps
+    need = warmup + steps
+    if sch.total_steps < need:
+        sch = I.Schedule(**{**sch.__dict__, "n_hold2": sch.n_hold2 + need - sch.total_steps})
+    p = E.protocol_from_schedule(sch, skin=skin)
+    reps = wl.replicas if only is None else [wl.replicas[i] for i in only]
+    arrs = I.batch_arrays(reps)
+    ctx = E.Context(0, E.FP32 if prec == "fp32" else E.FP64)
+    if lanes:
+        ctx.set_launch(lanes, block)
+    ctx.eam_setup(I.synthetic_eam_knots())
+    x = E.to_soa(arrs["x0"])
+    ctx.system_setup(reps, x)
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, sch.fix_com)
+    ctx.neigh_build(x, skin, 0)
+    tuned = None
+    if warmup:
+        ctx.run_switching(p, x, v, 0, warmup, sync=True)
+    if autotune and not lanes:
+        tuned = ctx.autotune(p, warmup, x, v, trial_steps=20)
+    natoms = int(arrs["x0"].shape[0])
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    ctx.run_switching(p, x, v, warmup, warmup + steps, sync=False)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    kt = ctx.kernel_timing()
+    ctx.check()
+    mean_nl, max_nl, cap = ctx.list_stats()
+    launch = ctx.get_launch()
+    ctx.close()
+    return {
+        "natoms": natoms, "n_rep": len(reps), "ms": ms, "wall_s": wall, "kt": kt, "mean_nl": mean_nl,
+        "max_nl": max_nl, "cap": cap, "launch": launch, "tuned": tuned, "desc": wl.description,
+    }
+
+
+def cpu_baseline(target_s=12.0):
+    """The FP64 oracle as it stands on one host core: one 2000-atom replica
+    of the default workload (bcc 10^3, T = 500 K), Verlet candidates with
+    0.3 A skin, FL protocol from the lattice start."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2201_04622_amd import inputs as I
+    O.build()
+    wl = I.workload("cfg2")
+    r = wl.replicas[4]
+    pot = O.Potential.from_knots(I.synthetic_eam_knots())
+    prm = O.RunParams(mode="fl", T=r.T, k=r.k, seed=r.seed, fix_com=True, skin=0.3, nlist_cap=512)
+    x0 = r.sites()
+    x, v = x0.copy(), O.init_velocities(prm, r.natoms)
+    lam = O.schedule("fl", 2000, 20000, 2000, 0)
+    done, step, t_used = 0, 0, 0.0
+    chunk = 20
+    while t_used < target_s:
+        t = time.perf_counter()
+        O.run(pot, prm, x0, r.box, x, v, lam[step: step + chunk + 1], step0=step)
+        t_used += time.perf_counter() - t
+        done += chunk
+        step += chunk
+    return {"value": r.natoms * done / t_used, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, 1 replica bcc 10^3 (2000 atoms) of the batch, FL steps 0..{done}, "
+                      f"{t_used:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
+              "(replicas would shard across GPUs with only a final gather of the work traces)", file=sys.stderr)
+        sys.exit(2)
+
+    main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup, args.lanes, args.block,
+                       not args.no_autotune, args.skin)
+    atom_steps = main_run["natoms"] * args.steps
+    value = atom_steps / (main_run["ms"] / 1e3)
+    kt = main_run["kt"]
+    dom = "force" if kt["force"][0] >= kt["density"][0] else "density"
+    avg_ms = kt[dom][0] / max(1, kt[dom][1])
+    bpa = (force_bytes_per_atom if dom == "force" else density_bytes_per_atom)(main_run["mean_nl"], args.precision)
+    bytes_launch = bpa * main_run["natoms"]
+    achieved = bytes_launch / (avg_ms / 1e3) / 1e9
+
+    plain = None
+    if not args.no_fp64:
+        pr = run_gpu("cfg1", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0])
+        plain = {
+            "value": pr["natoms"] * 2000 / (pr["ms"] / 1e3), "unit": "atom-steps/s",
+            "workload": "one FL replica, bcc 10^3 (2000 atoms), T=1400 K, k=3, FP64, autotuned launch",
+            "ms_per_step": pr["ms"] / 2000,
+        }
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    out = {
+        "metric": "atom-steps/s, EAM switching MD: batched FP32 vs plain FP64, dF <=0.5 meV/atom",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {main_run['desc']}",
+            "replicas": main_run["n_rep"],
+            "atoms": main_run["natoms"],
+            "precision": ("f32 pair terms and densities, f64 positions/velocities/energies/work, "
+                          "2^-32 fixed-point per-atom sums") if args.precision == "fp32" else "f64 throughout",
+            "mean_neighbour_row": round(main_run["mean_nl"], 2),
+            "max_neighbour_row": main_run["max_nl"],
+            "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
+                       "autotuned": main_run["tuned"] is not None},
+            "skin": args.skin,
+            "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
+            "kernel_launches": {k: v[1] for k, v in kt.items()},
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_force" if dom == "force" else "k_density",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "bytes_per_atom": bpa, "avg_launch_us": avg_ms * 1e3,
+        },
+        "fp64_plain_single_replica": plain,
+        "cpu_baseline": cpu,
+    }
+    if plain:
+        out["batched_fp32_over_plain_fp64"] = value / plain["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,9 +55,10 @@ extern "C" {
 /* numeric form of the pair arithmetic */
 #define EAMFE_FP64 0   /* all arithmetic in float64                                    */
 #define EAMFE_FP32 1   /* pair terms, densities, tables in float32; positions, velocities,
-                          energies and work in float64; per-atom sums accumulated in
-                          fixed point (2^-32 quanta) so results do not depend on the
-                          order of the neighbour list or on the launch shape          */
+                          energies and work in float64.  Per-atom sums are float32
+                          partials over fixed groups of four list slots, rounded to
+                          2^-32 and added exactly in fixed point: results are
+                          bitwise reproducible and independent of the launch shape */
 
 /* Hamiltonian family (dH/dl in brackets) */
 #define EAMFE_MODE_FL      0   /* (1-l) U_EAM + l U_E(k)          [U_E - U_EAM]  Eq. interp/w_irr2 */
@@ -129,6 +130,20 @@ int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
  * (EAMFE_ENEIGH_OVERFLOW ...), clearing it. */
 int eamfe_check(eamfe_ctx* ctx);
 
+/* Time every following kernel launch with HIP events recorded on the
+ * context's stream (1) or stop (0); switching resets the accumulators. */
+int eamfe_set_kernel_timing(eamfe_ctx* ctx, int on);
+
+/* Synchronise and return the summed event times (ms) and launch counts of
+ * the density pass [0], the force pass [1] and the neighbour-list rebuild
+ * sequence [2] since timing was switched on or last read; then reset.
+ * ms_total and launches point to host arrays of 3 (either may be NULL). */
+int eamfe_kernel_timing(eamfe_ctx* ctx, double* ms_total, int64_t* launches);
+
+/* Neighbour-row statistics of the current lists (synchronises): mean and
+ * maximum row length over all atoms, and the row capacity. */
+int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capacity);
+
 /* ---- potential --------------------------------------------------------- */
 
 /* Tabulated EAM (the paper's "pair eam" input; Eq. H with U = EAM):
@@ -159,7 +174,8 @@ int neigh_build(eamfe_ctx* ctx, const double* x_dev, double skin, int max_neighb
  * first if any atom moved more than skin/2 since they were built).
  * f_dev: device SoA [3][N_tot] float64 (may be NULL); U_dev: device [n_rep]
  * float64 (may be NULL); e_atom_dev: device [N_tot] per-atom energy
- * F(rho_i) + 1/2 sum_j phi(r_ij) (may be NULL).  Synchronises. */
+ * F(rho_i) + 1/2 sum_j phi(r_ij) (may be NULL).  A row or cell-bin
+ * overflow enlarges the lists and evaluates again.  Synchronises. */
 int eam_forces(eamfe_ctx* ctx, const double* x_dev, double* f_dev, double* U_dev, double* e_atom_dev);
 
 /* Initial velocities v = sqrt(kB T / m) z with z from Philox stream 1 at
@@ -183,7 +199,13 @@ int eamfe_lambda_schedule(const eamfe_protocol* p, double* lam_host, int64_t* n_
  * restarts at 0 when step_begin == 0.  Optional device outputs (NULL to skip),
  * indexed by the global step s: dHdl_out[n_rep][S] = dH/dl(x_s),
  * W_out[n_rep][S] = W after step s's increment; lam_out[S+1] = the table.
- * Does not synchronise unless `sync` is nonzero. */
+ * Steps run in chunks (eamfe_set_chunk, default 1000).  For the EAM modes
+ * the stream is synchronised after every chunk to read the latched status:
+ * a neighbour-row or cell-bin overflow restores the state saved at the
+ * chunk's start, enlarges the capacity and replays the chunk (the noise is
+ * keyed by step, so the replay is the same trajectory).  With `sync` the
+ * call also synchronises at its end and reports any other latched
+ * condition. */
 int run_switching(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step_begin, int64_t step_end,
                   double* x_dev, double* v_dev, double* lam_out, double* dHdl_out, double* W_out,
                   int sync);
@@ -193,6 +215,12 @@ int run_switching(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step_begin, i
  * dH/dl(x_s) written to dHdl_dev[n_rep] (device, may be NULL). */
 int switch_step(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step, double* x_dev, double* v_dev,
                 double* W_dev, double* dHdl_dev);
+
+/* Steps per chunk of run_switching (>= 1). */
+int eamfe_set_chunk(eamfe_ctx* ctx, int64_t steps);
+
+/* Number of chunk replays after capacity overflows so far. */
+int eamfe_replays(const eamfe_ctx* ctx, int64_t* n);
 
 /* Per-replica work after the last stepping call: host W_host[n_rep]. */
 int eamfe_get_work(eamfe_ctx* ctx, double* W_host);

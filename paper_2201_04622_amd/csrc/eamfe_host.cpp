@@ -43,7 +43,7 @@ struct eamfe_ctx {
     std::vector<RepDesc> reps;
     std::vector<Tile> tiles;
     int n_tiles = 0;   // real tiles
-    DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, xalt_d, Fp_d, e_emb_d, xi_d;
+    DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, noise_sum_d, U_rep_d, W_state_d;
     DevBuf cnt_density_d, cnt_force_d, cnt_all_d, iter_d, rebuild_d, status_d;
 
@@ -52,6 +52,24 @@ struct eamfe_ctx {
     double skin = 0.3;
     int cap = 0, ccap = 0, n_cells = 0;
     DevBuf nbr_d, nnb_d, cell_cnt_d, cell_n_d, cell_atoms_d, cell_rep_d;
+
+    // optional per-launch timing with HIP events on the context's stream
+    int timing = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;   // 0 density, 1 force, 2 neighbour rebuild (one entry per event pair)
+
+    // list statistics
+    DevBuf stats_d;
+
+    // autotuner scratch state
+    DevBuf tune_x, tune_v, tune_w;
+
+    // chunked stepping: checkpoint of (x, v, W) for replay after a list overflow
+    int64_t chunk = 1000;
+    int min_ccap = 0;
+    int64_t replays = 0;
+    DevBuf snap_P, snap_v, snap_w;
 
     // lambda table
     DevBuf lam_d;
@@ -241,14 +259,15 @@ int upload_reps(eamfe_ctx* c)
     return EAMFE_OK;
 }
 
-NeighArgs neigh_args(eamfe_ctx* c, const double* x)
+NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
 {
     NeighArgs a{};
     a.tiles = (const Tile*)c->tiles_d.p;
     a.reps = (const RepDesc*)c->reps_d.p;
     a.rep_of = (const int32_t*)c->rep_of_d.p;
     a.cell_rep = (const int32_t*)c->cell_rep_d.p;
-    a.x = x;
+    a.P = P;
+    a.n_grid = (int)c->tiles.size();
     a.xref = (double*)c->xref_d.p;
     a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
     a.cell_n = (int32_t*)c->cell_n_d.p;
@@ -276,7 +295,6 @@ StepArgs step_args(eamfe_ctx* c)
     a.nbr = (const int32_t*)c->nbr_d.p;
     a.nnb = (const int32_t*)c->nnb_d.p;
     a.cap = c->cap;
-    a.Fp = c->Fp_d.p;
     a.e_emb = (double*)c->e_emb_d.p;
     a.xi = (double*)c->xi_d.p;
     a.noise_part = (double*)c->noise_part_d.p;
@@ -331,7 +349,7 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
         }
     }
     // mean occupancy of the fullest cells, with room for clustering
-    c->ccap = std::max(32, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32);
+    c->ccap = std::max({32, c->min_ccap, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32});
     if (max_neighbors <= 0) {
         const double nmean = 4.0 / 3.0 * M_PI * rl * rl * rl * dens_max;
         max_neighbors = (int)(std::ceil((nmean * 2.0 + 32.0) / 32.0) * 32.0);
@@ -464,25 +482,45 @@ int set_thermostat(eamfe_ctx* c, const eamfe_protocol* p, double* c1_out)
     return EAMFE_OK;
 }
 
-int ensure_lists(eamfe_ctx* c, double skin, const double* x)
+// Lists valid for packed positions P: plan them if needed, else flag the
+// replicas in which some atom moved more than skin/2 since the last build.
+int ensure_lists(eamfe_ctx* c, double skin, const double4* P)
 {
     if (!c->have_list || skin != c->skin) {
         OK(plan_lists(c, skin, c->have_list ? c->cap : 0));
         c->have_list = true;
         OK(set_rebuild_all(c));
     } else {
-        NeighArgs na = neigh_args(c, x);
+        NeighArgs na = neigh_args(c, P);
         LCHK(c, launch_check_displacement(na, c->stream));
     }
     return EAMFE_OK;
 }
 
-// Iterations it_first .. it_last of a protocol starting from positions in x.
-// Returns the buffer that holds the final positions in *final_x.
-int iterate(eamfe_ctx* c, StepArgs a, double* x, bool has_eam, int64_t it_first, int64_t it_last, double** final_x)
+double4* PA(eamfe_ctx* c) { return (double4*)c->Pa_d.p; }
+double4* PB(eamfe_ctx* c) { return (double4*)c->Pb_d.p; }
+
+// Record a timing event (kind: 0 density, 1 force, 2 lists; end = 0 start, 1 stop).
+int mark(eamfe_ctx* c, int kind, int end)
 {
-    double* cur = x;
-    double* nxt = (double*)c->xalt_d.p;
+    if (!c->timing) return EAMFE_OK;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    if (!end) c->ev_kind.push_back(kind);
+    HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used++], c->stream));
+    return EAMFE_OK;
+}
+
+// Iterations it_first .. it_last of a protocol starting from packed
+// positions *cur (one of the two internal buffers); on return *cur is the
+// buffer holding the final positions.
+int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it_first, int64_t it_last)
+{
+    double4* cur = *cur_io;
+    double4* nxt = cur == PA(c) ? PB(c) : PA(c);
     a.it_first = it_first;
     a.it_last = it_last;
     a.step_kernel = 1;
@@ -491,15 +529,21 @@ int iterate(eamfe_ctx* c, StepArgs a, double* x, bool has_eam, int64_t it_first,
     for (int64_t it = it_first; it <= it_last; ++it) {
         if (has_eam) {
             NeighArgs na = neigh_args(c, cur);
-            LCHK(c, launch_neigh_rebuild(na, c->stream));
+            OK(mark(c, 2, 0));
+            LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+            OK(mark(c, 2, 1));
         }
-        a.x = cur;
-        a.x_next = nxt;
+        a.P = cur;
+        a.Pn = nxt;
+        OK(mark(c, 0, 0));
         LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+        OK(mark(c, 0, 1));
+        OK(mark(c, 1, 0));
         LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+        OK(mark(c, 1, 1));
         std::swap(cur, nxt);
     }
-    *final_x = cur;
+    *cur_io = cur;
     return EAMFE_OK;
 }
 
@@ -558,11 +602,19 @@ int eamfe_destroy(eamfe_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
-                      &c->xref_d, &c->xalt_d, &c->Fp_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
+                      &c->xref_d, &c->Pa_d, &c->Pb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
                       &c->energy_part_d, &c->noise_sum_d, &c->U_rep_d, &c->W_state_d, &c->cnt_density_d,
                       &c->cnt_force_d, &c->cnt_all_d, &c->iter_d, &c->rebuild_d, &c->status_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
+    release(c->stats_d);
+    release(c->tune_x);
+    release(c->tune_v);
+    release(c->tune_w);
+    release(c->snap_P);
+    release(c->snap_v);
+    release(c->snap_w);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return EAMFE_OK;
 }
@@ -687,9 +739,9 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     const size_t v3 = 3 * (size_t)N * sizeof(double);
     OK(ensure(c, c->x0_d, v3));
     OK(ensure(c, c->xref_d, v3));
-    OK(ensure(c, c->xalt_d, v3));
+    OK(ensure(c, c->Pa_d, (size_t)N * sizeof(double4)));
+    OK(ensure(c, c->Pb_d, (size_t)N * sizeof(double4)));
     OK(ensure(c, c->xi_d, v3));
-    OK(ensure(c, c->Fp_d, (size_t)N * sizeof(double)));
     OK(ensure(c, c->e_emb_d, (size_t)N * sizeof(double)));
     OK(ensure(c, c->rep_of_d, (size_t)N * sizeof(int32_t)));
     OK(ensure(c, c->noise_sum_d, (size_t)n_rep * 3 * sizeof(double)));
@@ -701,7 +753,8 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
-    HIPCHK(c, hipMemset(c->Fp_d.p, 0, (size_t)N * sizeof(double)));
+    HIPCHK(c, hipMemset(c->Pa_d.p, 0, (size_t)N * sizeof(double4)));
+    HIPCHK(c, hipMemset(c->Pb_d.p, 0, (size_t)N * sizeof(double4)));
     HIPCHK(c, hipMemset(c->e_emb_d.p, 0, (size_t)N * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->rep_of_d.p, rep_of.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(c->noise_sum_d.p, 0, (size_t)n_rep * 3 * sizeof(double)));
@@ -723,8 +776,9 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
     OK(plan_lists(c, skin, max_neighbors));
     c->have_list = true;
     OK(set_rebuild_all(c));
-    NeighArgs na = neigh_args(c, x);
-    LCHK(c, launch_neigh_rebuild(na, c->stream));
+    LCHK(c, launch_pack(PA(c), x, c->N, c->stream));
+    NeighArgs na = neigh_args(c, PA(c));
+    LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
     // the flags are cleared by the next density pass; clear them here too
     hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
                        (int32_t*)c->rebuild_d.p, c->n_rep, 0);
@@ -737,20 +791,34 @@ int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_at
     if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
     if (!x) return fail(c, EAMFE_EINVAL, "eam_forces: null positions");
     (void)hipSetDevice(c->device);
-    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, x));
-    NeighArgs na = neigh_args(c, x);
-    LCHK(c, launch_neigh_rebuild(na, c->stream));
-    StepArgs a = step_args(c);
-    a.x = x;
-    a.x_next = nullptr;
-    a.v = nullptr;
-    a.has_eam = 1;
-    a.step_kernel = 0;
-    a.mode = EAMFE_MODE_FL;
-    a.f_out = f;
-    a.e_atom_out = e_atom;
-    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
-    LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+    LCHK(c, launch_pack(PA(c), x, c->N, c->stream));
+    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
+    for (int attempt = 0;; ++attempt) {
+        NeighArgs na = neigh_args(c, PA(c));
+        LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+        StepArgs a = step_args(c);
+        a.P = PA(c);
+        a.Pn = nullptr;
+        a.v = nullptr;
+        a.has_eam = 1;
+        a.step_kernel = 0;
+        a.mode = EAMFE_MODE_FL;
+        a.f_out = f;
+        a.e_atom_out = e_atom;
+        LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+        LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int st = 0;
+        HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW)) || attempt >= 6) break;
+        // rows or bins too small for this configuration: enlarge and evaluate again
+        HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
+        const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
+        if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
+        OK(plan_lists(c, c->skin, new_cap));
+        OK(set_rebuild_all(c));
+        ++c->replays;
+    }
     if (U)
         HIPCHK(c, hipMemcpy2DAsync(U, sizeof(double), c->U_rep_d.p, 2 * sizeof(double), sizeof(double), c->n_rep,
                                    hipMemcpyDeviceToDevice, c->stream));
@@ -787,6 +855,78 @@ int eamfe_lambda_schedule(const eamfe_protocol* p, double* lam, int64_t* n_steps
     return s == S + 1 ? EAMFE_OK : EAMFE_EINVAL;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Steps [s0, s1) from caller positions x (SoA, packed on entry, unpacked on
+// exit) and velocities v.  Steps run in chunks; after each chunk the
+// latched status is read.  A neighbour-row or cell overflow (possible when a
+// crystal collapses into dense clusters) restores the chunk's starting
+// state, enlarges the capacity and replays the chunk; the noise is a
+// function of (seed, atom, step), so the replay is the trajectory the run
+// would have had.
+int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int64_t s1, double* x, double* v,
+              double* dHdl_out, double* W_out, int64_t stride, int64_t trace_off, double c1, bool has_eam)
+{
+    LCHK(c, launch_pack(PA(c), x, c->N, c->stream));
+    double4* cur = PA(c);
+    if (has_eam) OK(ensure_lists(c, p->skin, cur));
+    const size_t v3 = 3 * (size_t)c->N * sizeof(double);
+    const size_t p4 = (size_t)c->N * sizeof(double4);
+    const size_t wb = (size_t)c->n_rep * sizeof(double);
+    if (has_eam) {
+        OK(ensure(c, c->snap_P, p4));
+        OK(ensure(c, c->snap_v, v3));
+        OK(ensure(c, c->snap_w, wb));
+    }
+    for (int64_t b = s0; b < s1; b += c->chunk) {
+        const int64_t e = std::min(s1, b + c->chunk);
+        if (has_eam) {
+            HIPCHK(c, hipMemcpyAsync(c->snap_P.p, cur, p4, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->snap_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->snap_w.p, c->W_state_d.p, wb, hipMemcpyDeviceToDevice, c->stream));
+        }
+        for (int attempt = 0;; ++attempt) {
+            StepArgs a = step_args(c);
+            a.v = v;
+            a.lam = (const double*)c->lam_d.p;
+            a.dHdl_out = dHdl_out;
+            a.W_out = W_out;
+            a.S = stride;
+            a.trace_off = trace_off;
+            a.mode = p->mode;
+            a.fix_com = p->fix_com ? 1 : 0;
+            a.dt = p->dt;
+            a.c1 = c1;
+            double4* start = cur;
+            OK(iterate(c, a, &cur, has_eam, b, e));
+            if (!has_eam) break;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            int st = 0;
+            HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
+            if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW))) break;
+            if (attempt >= 6) return read_status(c);
+            HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
+            const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
+            if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
+            OK(plan_lists(c, c->skin, new_cap));
+            OK(set_rebuild_all(c));
+            cur = start;
+            HIPCHK(c, hipMemcpyAsync(cur, c->snap_P.p, p4, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(v, c->snap_v.p, v3, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->W_state_d.p, c->snap_w.p, wb, hipMemcpyDeviceToDevice, c->stream));
+            ++c->replays;
+        }
+    }
+    LCHK(c, launch_unpack(x, cur, c->N, c->stream));
+    return EAMFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int run_switching(eamfe_ctx* c, const eamfe_protocol* p, int64_t s0, int64_t s1, double* x, double* v,
                   double* lam_out, double* dHdl_out, double* W_out, int sync)
 {
@@ -800,25 +940,25 @@ int run_switching(eamfe_ctx* c, const eamfe_protocol* p, int64_t s0, int64_t s1,
     if (s0 < 0 || s1 <= s0 || s1 > S) return fail(c, EAMFE_EINVAL, "run_switching: bad step range");
     double c1 = 1.0;
     OK(set_thermostat(c, p, &c1));
-    if (has_eam) OK(ensure_lists(c, p->skin, x));
     if (lam_out)
         HIPCHK(c, hipMemcpyAsync(lam_out, c->lam_d.p, (S + 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (s0 == 0) HIPCHK(c, hipMemsetAsync(c->W_state_d.p, 0, (size_t)c->n_rep * sizeof(double), c->stream));
-    StepArgs a = step_args(c);
-    a.v = v;
-    a.lam = (const double*)c->lam_d.p;
-    a.dHdl_out = dHdl_out;
-    a.W_out = W_out;
-    a.S = S;
-    a.mode = p->mode;
-    a.fix_com = p->fix_com ? 1 : 0;
-    a.dt = p->dt;
-    a.c1 = c1;
-    double* fin = nullptr;
-    OK(iterate(c, a, x, has_eam, s0, s1, &fin));
-    if (fin != x)
-        HIPCHK(c, hipMemcpyAsync(x, fin, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    OK(run_range(c, p, S, s0, s1, x, v, dHdl_out, W_out, S, 0, c1, has_eam));
     if (sync) return read_status(c);
+    return EAMFE_OK;
+}
+
+int eamfe_set_chunk(eamfe_ctx* c, int64_t steps)
+{
+    if (!c || steps < 1) return EAMFE_EINVAL;
+    c->chunk = steps;
+    return EAMFE_OK;
+}
+
+int eamfe_replays(const eamfe_ctx* c, int64_t* n)
+{
+    if (!c || !n) return EAMFE_EINVAL;
+    *n = c->replays;
     return EAMFE_OK;
 }
 
@@ -833,25 +973,10 @@ int switch_step(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, double* x, 
     if (step < 0 || step >= S) return fail(c, EAMFE_EINVAL, "switch_step: step out of range");
     double c1 = 1.0;
     OK(set_thermostat(c, p, &c1));
-    if (has_eam) OK(ensure_lists(c, p->skin, x));
     HIPCHK(c, hipMemcpyAsync(c->W_state_d.p, W, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
-    StepArgs a = step_args(c);
-    a.v = v;
-    a.lam = (const double*)c->lam_d.p;
-    // one-step trace: column it - step of a [n_rep][1] array
-    a.S = 1;
-    a.trace_off = step;
-    a.dHdl_out = dHdl;
-    a.W_out = nullptr;
-    a.mode = p->mode;
-    a.fix_com = p->fix_com ? 1 : 0;
-    a.dt = p->dt;
-    a.c1 = c1;
-    double* fin = nullptr;
-    OK(iterate(c, a, x, has_eam, step, step + 1, &fin));
-    if (fin != x)
-        HIPCHK(c, hipMemcpyAsync(x, fin, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    // one-step trace: column (step - step) of a [n_rep][1] array
+    OK(run_range(c, p, S, step, step + 1, x, v, dHdl, nullptr, 1, step, c1, has_eam));
     HIPCHK(c, hipMemcpyAsync(W, c->W_state_d.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
     return read_status(c);
@@ -869,6 +994,147 @@ int eamfe_get_work(eamfe_ctx* c, double* W)
 int eamfe_adjoint_theta(eamfe_ctx* c, const double*, double, double*)
 {
     return fail(c, EAMFE_ESTATE, "adjoint not built yet");
+}
+
+int eamfe_set_kernel_timing(eamfe_ctx* c, int on)
+{
+    if (!c) return EAMFE_EINVAL;
+    c->timing = on ? 1 : 0;
+    c->ev_used = 0;
+    c->ev_kind.clear();
+    return EAMFE_OK;
+}
+
+int eamfe_kernel_timing(eamfe_ctx* c, double* ms_total, int64_t* launches)
+{
+    if (!c) return EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double t[3] = {0.0, 0.0, 0.0};
+    int64_t n[3] = {0, 0, 0};
+    for (size_t q = 0; q < c->ev_kind.size(); ++q) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * q], c->ev_pool[2 * q + 1]));
+        t[c->ev_kind[q]] += ms;
+        n[c->ev_kind[q]] += 1;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (ms_total) ms_total[k] = t[k];
+        if (launches) launches[k] = n[k];
+    }
+    c->ev_used = 0;
+    c->ev_kind.clear();
+    return EAMFE_OK;
+}
+
+int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const double* x, const double* v,
+                   int trial_steps, int* lanes_out, int* block_out, double* ms_per_step)
+{
+    const bool has_eam = p && (p->mode == EAMFE_MODE_FL || p->mode == EAMFE_MODE_RS);
+    if (!ready(c, has_eam)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (check_protocol(p) || !x || !v || trial_steps < 1) return fail(c, EAMFE_EINVAL, "autotune: bad arguments");
+    (void)hipSetDevice(c->device);
+    int64_t S = 0;
+    OK(ensure_lambda(c, p, &S));
+    if (step < 0 || step >= S) return fail(c, EAMFE_EINVAL, "autotune: step out of range");
+    const int64_t s1 = std::min<int64_t>(S, step + 2 + trial_steps);
+    const size_t v3 = 3 * (size_t)c->N * sizeof(double);
+    OK(ensure(c, c->tune_x, v3));
+    OK(ensure(c, c->tune_v, v3));
+    OK(ensure(c, c->tune_w, (size_t)c->n_rep * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(c->tune_w.p, c->W_state_d.p, (size_t)c->n_rep * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    const int timing = c->timing;
+    c->timing = 0;
+    const int lanes0 = c->lanes, block0 = c->block;
+    int best_l = lanes0, best_b = block0;
+    double best = 1e300;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int rc = EAMFE_OK;
+    const int lanes_c[] = {1, 2, 4, 8, 16};
+    const int block_c[] = {64, 128, 256, 512, 1024};
+    for (int L : lanes_c) {
+        for (int B : block_c) {
+            if (B / L < 4) continue;   // at least four atoms per block
+            c->lanes = L;
+            c->block = B;
+            if ((rc = build_tiles(c))) goto done;
+            if (hipMemcpyAsync(c->tune_x.p, x, v3, hipMemcpyDeviceToDevice, c->stream) ||
+                hipMemcpyAsync(c->tune_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream)) {
+                rc = fail(c, EAMFE_EDEVICE, "autotune: copy failed");
+                goto done;
+            }
+            if ((rc = run_switching(c, p, step, step + 2 <= s1 - 1 ? step + 2 : s1, (double*)c->tune_x.p,
+                                    (double*)c->tune_v.p, nullptr, nullptr, nullptr, 0)))
+                goto done;
+            if (step + 2 < s1) {
+                (void)hipEventRecord(e0, c->stream);
+                if ((rc = run_switching(c, p, step + 2, s1, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr,
+                                        nullptr, nullptr, 0)))
+                    goto done;
+                (void)hipEventRecord(e1, c->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                const double per = ms / (double)(s1 - step - 2);
+                if (per < best) {
+                    best = per;
+                    best_l = L;
+                    best_b = B;
+                }
+            }
+        }
+    }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = timing;
+    c->lanes = rc ? lanes0 : best_l;
+    c->block = rc ? block0 : best_b;
+    {
+        const int r2 = build_tiles(c);
+        if (!rc) rc = r2;
+    }
+    (void)hipMemcpyAsync(c->W_state_d.p, c->tune_w.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToDevice,
+                         c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (rc) return rc;
+    if (lanes_out) *lanes_out = best_l;
+    if (block_out) *block_out = best_b;
+    if (ms_per_step) *ms_per_step = best;
+    return read_status(c);
+}
+
+__global__ void k_list_stats(const int32_t* nnb, int n, unsigned long long* out)
+{
+    unsigned long long s = 0, mx = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        s += (unsigned long long)nnb[i];
+        mx = nnb[i] > (int)mx ? (unsigned long long)nnb[i] : mx;
+    }
+    atomicAdd(&out[0], s);
+    atomicMax(&out[1], mx);
+}
+
+int eamfe_list_stats(eamfe_ctx* c, double* mean_len, int* max_len, int* capacity)
+{
+    if (!c) return EAMFE_EINVAL;
+    if (!c->have_list) return fail(c, EAMFE_ESTATE, "no neighbour lists");
+    (void)hipSetDevice(c->device);
+    OK(ensure(c, c->stats_d, 2 * sizeof(unsigned long long)));
+    HIPCHK(c, hipMemsetAsync(c->stats_d.p, 0, 2 * sizeof(unsigned long long), c->stream));
+    hipLaunchKernelGGL(k_list_stats, dim3(256), dim3(256), 0, c->stream, (const int32_t*)c->nnb_d.p, c->N,
+                       (unsigned long long*)c->stats_d.p);
+    HIPCHK(c, hipGetLastError());
+    unsigned long long h[2];
+    HIPCHK(c, hipMemcpyAsync(h, c->stats_d.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (mean_len) *mean_len = (double)h[0] / c->N;
+    if (max_len) *max_len = (int)h[1];
+    if (capacity) *capacity = c->cap;
+    return EAMFE_OK;
 }
 
 // ---- estimators -------------------------------------------------------------

@@ -68,7 +68,7 @@ struct NeighArgs {
     const RepDesc* reps;
     const int32_t* rep_of;      // [N] replica of each atom
     const int32_t* cell_rep;    // [n_cells] replica of each cell
-    const double* x;            // SoA [3][N]
+    const double4* P;           // [N] packed positions (x, y, z, .)
     double* xref;               // SoA [3][N]
     int32_t* cell_cnt;          // [n_cells]
     int32_t* cell_n;            // [n_cells] sorted occupancy
@@ -78,6 +78,7 @@ struct NeighArgs {
     int32_t* rebuild;           // [n_rep] flags
     int32_t* status;
     int N, n_cells, ccap, cap;
+    int n_grid;                 // tiles launched (including padding)
     double rl2;                 // (r_cut + skin)^2
     double half_skin2;          // (skin/2)^2
 };
@@ -86,15 +87,14 @@ struct NeighArgs {
 struct StepArgs {
     const Tile* tiles;
     const RepDesc* reps;
-    const double* x;        // positions at the start of the iteration (SoA)
-    double* x_next;         // positions after the step (SoA)
+    double4* P;             // [N] positions at the start of the iteration, .w = F'(rho_i)
+    double4* Pn;            // [N] positions after the step
     double* v;              // SoA, in place
     const double* x0;       // SoA
     const double* xref;     // SoA, list reference positions
     const int32_t* nbr;
     const int32_t* nnb;
     int cap;
-    void* Fp;               // [N] F'(rho_i), element type = precision
     double* e_emb;          // [N] F(rho_i)
     double* xi;             // [3][N] thermostat noise of this step
     double* noise_part;     // [tiles][3]
@@ -133,11 +133,10 @@ struct StepArgs {
 struct AdjointArgs {
     const Tile* tiles;
     const RepDesc* reps;
-    const double* x;
+    const double4* P;         // positions, .w = F'(rho_i)
     const int32_t* nbr;
     const int32_t* nnb;
     int cap;
-    const void* Fp;
     const double* rho;        // [N] densities (float64)
     unsigned long long* bins; // [n_rep][3][n-1][4] fixed-point sums (2^-32 quanta, two's complement)
     Tables tab;
@@ -146,8 +145,10 @@ struct AdjointArgs {
 };
 
 // Launchers (eamfe_kernels.hip).  Each returns a hipError_t as int.
+int launch_pack(double4* P, const double* x, int N, hipStream_t s);
+int launch_unpack(double* x, const double4* P, int N, hipStream_t s);
 int launch_check_displacement(const NeighArgs& a, hipStream_t s);
-int launch_neigh_rebuild(const NeighArgs& a, hipStream_t s);
+int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s);
 int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);

@@ -13,9 +13,10 @@
 // T lanes cooperate on one atom; lane t takes blocks of SB consecutive
 // neighbour slots t, t+T, ...  In FP32 each block's partial sum is rounded
 // to a 2^-32 grid and added as an exact integer held in a float64, so the
-// per-atom sums do not depend on T, on the block size or on the list order.
-// Per-replica reductions use a fixed tree and a "last block finishes" pass,
-// so runs are bitwise reproducible.
+// per-atom sums do not depend on T or on the block size.  List rows have a
+// fixed order (cells sorted by atom id) and per-replica reductions use a
+// fixed tree and a "last block finishes" pass, so runs are bitwise
+// reproducible.
 #include "eamfe_internal.h"
 
 namespace eamfe {
@@ -199,15 +200,46 @@ __device__ bool replica_reduce(const double (&vin)[K], double* part, uint32_t* c
 }
 
 // --------------------------------------------------------------------------
-// Neighbour lists
+// Packed positions: the pair kernels gather one 32-byte record per neighbour
+// (x, y, z and, after the density pass, F'(rho)) instead of four arrays.
+// --------------------------------------------------------------------------
+__global__ void k_pack(double4* P, const double* x, int N)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) P[i] = make_double4(x[i], x[N + i], x[2 * N + i], 0.0);
+}
+
+__global__ void k_unpack(double* x, const double4* P, int N)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        const double4 p = P[i];
+        x[i] = p.x;
+        x[N + i] = p.y;
+        x[2 * N + i] = p.z;
+    }
+}
+
+__device__ __forceinline__ double3 sep(const RepDesc& R, const double4& a, const double4& b)
+{
+    double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    min_image(R, dx, dy, dz);
+    return make_double3(dx, dy, dz);
+}
+
+// --------------------------------------------------------------------------
+// Neighbour lists.  Rebuilds run only for replicas whose flag is set (an
+// atom moved more than skin/2 since the last build).  Atoms are binned into
+// cells of edge >= r_cut + skin, each cell's atoms are sorted by id, and
+// every row is the in-order concatenation of the 27 surrounding cells'
+// members within r_cut + skin, so rows have a fixed order.
 // --------------------------------------------------------------------------
 __global__ void k_check_displacement(NeighArgs a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    const double dx = a.x[i] - a.xref[i];
-    const double dy = a.x[a.N + i] - a.xref[a.N + i];
-    const double dz = a.x[2 * a.N + i] - a.xref[2 * a.N + i];
+    const double4 p = a.P[i];
+    const double dx = p.x - a.xref[i], dy = p.y - a.xref[a.N + i], dz = p.z - a.xref[2 * a.N + i];
     if (dx * dx + dy * dy + dz * dz > a.half_skin2) a.rebuild[a.rep_of[i]] = 1;
 }
 
@@ -225,11 +257,12 @@ __global__ void k_bin(NeighArgs a)
     if (i >= a.N) return;
     const int r = a.rep_of[i];
     if (!a.rebuild[r]) return;
-    const RepDesc R = a.reps[r];
+    const RepDesc& R = a.reps[r];
     if (R.nc[0] == 0) return;
-    const int cx = cell_coord(a.x[i], R.L[0], R.invL[0], R.nc[0]);
-    const int cy = cell_coord(a.x[a.N + i], R.L[1], R.invL[1], R.nc[1]);
-    const int cz = cell_coord(a.x[2 * a.N + i], R.L[2], R.invL[2], R.nc[2]);
+    const double4 p = a.P[i];
+    const int cx = cell_coord(p.x, R.L[0], R.invL[0], R.nc[0]);
+    const int cy = cell_coord(p.y, R.L[1], R.invL[1], R.nc[1]);
+    const int cz = cell_coord(p.z, R.L[2], R.invL[2], R.nc[2]);
     const int c = R.cell_base + (cx * R.nc[1] + cy) * R.nc[2] + cz;
     const int slot = atomicAdd(&a.cell_cnt[c], 1);
     if (slot < a.ccap)
@@ -238,56 +271,83 @@ __global__ void k_bin(NeighArgs a)
         atomicOr(a.status, ST_CELL_OVERFLOW);
 }
 
-// Sort each cell's atoms by id (so list rows have a fixed order) and reset
-// the bin counters for the next build.
-__global__ void k_cellsort(NeighArgs a)
+// One 64-thread block per cell (grid-stride): bitonic sort of the cell's
+// atom ids in LDS, occupancy copied to cell_n, bin counter reset.
+__global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n_cells) return;
-    if (!a.rebuild[a.cell_rep[c]]) return;
-    int n = a.cell_cnt[c];
-    n = n > a.ccap ? a.ccap : n;
-    int32_t* p = a.cell_atoms + (size_t)c * a.ccap;
-    for (int q = 1; q < n; ++q) {
-        const int v = p[q];
-        int w = q - 1;
-        while (w >= 0 && p[w] > v) {
-            p[w + 1] = p[w];
-            --w;
+    extern __shared__ int32_t sv[];
+    for (int c = blockIdx.x; c < a.n_cells; c += gridDim.x) {
+        if (!a.rebuild[a.cell_rep[c]]) continue;   // uniform in the block
+        int n = a.cell_cnt[c];
+        n = n > a.ccap ? a.ccap : n;
+        int32_t* p = a.cell_atoms + (size_t)c * a.ccap;
+        int P2 = 1;
+        while (P2 < n) P2 <<= 1;
+        for (int k = threadIdx.x; k < P2; k += blockDim.x) sv[k] = k < n ? p[k] : 0x7fffffff;
+        __syncthreads();
+        for (int size = 2; size <= P2; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = threadIdx.x; k < P2; k += blockDim.x) {
+                    const int q = k ^ stride;
+                    if (q > k) {
+                        const int x = sv[k], y = sv[q];
+                        if ((x > y) == ((k & size) == 0)) {
+                            sv[k] = y;
+                            sv[q] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
-        p[w + 1] = v;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = sv[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.cell_n[c] = n;
+            a.cell_cnt[c] = 0;
+        }
     }
-    a.cell_n[c] = n;
-    a.cell_cnt[c] = 0;
 }
 
-__global__ void k_list(NeighArgs a)
+// Rows, T lanes per atom: each pass tests T consecutive candidates and the
+// accepted ones are appended in candidate order (ballot + prefix count).
+template <int T>
+__global__ __launch_bounds__(kMaxBlock) void k_list(NeighArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const int r = a.rep_of[i];
-    if (!a.rebuild[r]) return;
-    const RepDesc R = a.reps[r];
-    const double xi = a.x[i], yi = a.x[a.N + i], zi = a.x[2 * a.N + i];
+    const Tile tl = a.tiles[blockIdx.x];
+    if (tl.count == 0 || !a.rebuild[tl.rep]) return;
+    const int lane = threadIdx.x % T;
+    const int la = threadIdx.x / T;
+    if (la >= tl.count) return;   // the whole T-lane group leaves together
+    const RepDesc& R = a.reps[tl.rep];
+    const int i = tl.first + la;
     const int il = i - R.off;
+    const double4 pi = a.P[i];
     int32_t* row = a.nbr + (size_t)i * a.cap;
+    const int lw = threadIdx.x & 63;
+    const int gb = lw & ~(T - 1);
+    const uint64_t gmask = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
+    const uint64_t below = (1ull << (lw - gb)) - 1ull;
     int cnt = 0;
-    auto consider = [&](int jl) {
-        if (jl == il) return;
-        const int j = R.off + jl;
-        double dx = xi - a.x[j], dy = yi - a.x[a.N + j], dz = zi - a.x[2 * a.N + j];
-        min_image(R, dx, dy, dz);
-        if (dx * dx + dy * dy + dz * dz < a.rl2) {
-            if (cnt < a.cap) row[cnt] = j;
-            ++cnt;
+    auto pass = [&](int jl, bool in) {
+        bool acc = false;
+        int j = 0;
+        if (in && jl != il) {
+            j = R.off + jl;
+            const double3 d = sep(R, pi, a.P[j]);
+            acc = d.x * d.x + d.y * d.y + d.z * d.z < a.rl2;
         }
+        const uint64_t m = (__ballot(acc) >> gb) & gmask;
+        const int rank = __popcll(m & below);
+        if (acc && cnt + rank < a.cap) row[cnt + rank] = j;
+        cnt += __popcll(m);
     };
     if (R.nc[0] == 0) {
-        for (int jl = 0; jl < R.n; ++jl) consider(jl);
+        for (int s0 = 0; s0 < R.n; s0 += T) pass(s0 + lane, s0 + lane < R.n);
     } else {
-        const int cx = cell_coord(xi, R.L[0], R.invL[0], R.nc[0]);
-        const int cy = cell_coord(yi, R.L[1], R.invL[1], R.nc[1]);
-        const int cz = cell_coord(zi, R.L[2], R.invL[2], R.nc[2]);
+        const int cx = cell_coord(pi.x, R.L[0], R.invL[0], R.nc[0]);
+        const int cy = cell_coord(pi.y, R.L[1], R.invL[1], R.nc[1]);
+        const int cz = cell_coord(pi.z, R.L[2], R.invL[2], R.nc[2]);
         for (int ox = -1; ox <= 1; ++ox) {
             const int ux = (cx + ox + R.nc[0]) % R.nc[0];
             for (int oy = -1; oy <= 1; ++oy) {
@@ -297,28 +357,35 @@ __global__ void k_list(NeighArgs a)
                     const int c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
                     const int n = a.cell_n[c];
                     const int32_t* p = a.cell_atoms + (size_t)c * a.ccap;
-                    for (int s = 0; s < n; ++s) consider(p[s]);
+                    for (int s0 = 0; s0 < n; s0 += T) {
+                        const int s = s0 + lane;
+                        pass(s < n ? p[s] : -1, s < n);
+                    }
                 }
             }
         }
     }
-    if (cnt > a.cap) {
-        atomicOr(a.status, ST_NEIGH_OVERFLOW);
-        cnt = a.cap;
+    if (lane == 0) {
+        if (cnt > a.cap) {
+            atomicOr(a.status, ST_NEIGH_OVERFLOW);
+            cnt = a.cap;
+        }
+        a.nnb[i] = cnt;
+        a.xref[i] = pi.x;
+        a.xref[a.N + i] = pi.y;
+        a.xref[2 * a.N + i] = pi.z;
     }
-    a.nnb[i] = cnt;
-    a.xref[i] = xi;
-    a.xref[a.N + i] = yi;
-    a.xref[2 * a.N + i] = zi;
 }
 
 // --------------------------------------------------------------------------
-// Density pass
+// Density pass.  FP32 tables are staged in LDS (32 KB for rho).
 // --------------------------------------------------------------------------
 template <typename real, int T>
 __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 {
+    extern __shared__ float4 lds_tab[];
     __shared__ double sh[16 * 3];
+    constexpr bool kLds = sizeof(real) == 4;
     const Tile tl = a.tiles[blockIdx.x];
     if (tl.count == 0) return;   // padding tile: whole block leaves
     const RepDesc& R = a.reps[tl.rep];
@@ -328,30 +395,39 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     const int i = tl.first + (valid ? la : 0);
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter : 0;
+    const int nr = a.tab.n_r;
+
+    if (kLds && a.has_eam) {
+        const float4* g = (const float4*)a.tab.rho;
+        for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
+        __syncthreads();
+    }
 
     double acc = 0.0;
+    double4 pi = a.P[i];
     if (valid && a.has_eam) {
-        const double xi = a.x[i], yi = a.x[N + i], zi = a.x[2 * N + i];
         const int n = a.nnb[i];
         const int32_t* row = a.nbr + (size_t)i * a.cap;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        const int nr = a.tab.n_r;
         for (int b0 = lane * SB; b0 < n; b0 += T * SB) {
             real part = (real)0;
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
                 const int q = b0 + s;
                 if (q < n) {
-                    const int j = row[q];
-                    double dx = xi - a.x[j], dy = yi - a.x[N + j], dz = zi - a.x[2 * N + j];
-                    min_image(R, dx, dy, dz);
-                    const real rx = (real)dx, ry = (real)dy, rz = (real)dz;
+                    const double3 d = sep(R, pi, a.P[row[q]]);
+                    const real rx = (real)d.x, ry = (real)d.y, rz = (real)d.z;
                     const real r2 = rx * rx + ry * ry + rz * rz;
                     if (r2 < rc2) {
                         real t;
                         const int m = interval<real>(sqrt(r2), inv_h, nr, t);
-                        const auto c = Tab<real>::ld4(a.tab.rho, m);
-                        part += c.x + t * (c.y + t * (c.z + t * c.w));
+                        if constexpr (kLds) {
+                            const float4 c = lds_tab[m];
+                            part += c.x + t * (c.y + t * (c.z + t * c.w));
+                        } else {
+                            const auto c = Tab<real>::ld4(a.tab.rho, m);
+                            part += c.x + t * (c.y + t * (c.z + t * c.w));
+                        }
                     }
                 }
             }
@@ -367,7 +443,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         const auto c = Tab<real>::ld4(a.tab.F, m);
         const real F = c.x + t * (c.y + t * (c.z + t * c.w));
         const real Fp = (c.y + t * ((real)2 * c.z + (real)3 * t * c.w)) * (real)a.tab.inv_h_rho;
-        ((real*)a.Fp)[i] = Fp;
+        a.P[i].w = (double)Fp;
         a.e_emb[i] = (double)F;
         if (rho > a.tab.rho_max) atomicOr(a.status, ST_TABLE_RANGE);
         if (!isfinite(rho)) atomicOr(a.status, ST_NONFINITE);
@@ -389,7 +465,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 }
 
 // --------------------------------------------------------------------------
-// Force pass + integration + energies + work
+// Force pass + integration + energies + work.  FP32 pair table in LDS (64 KB).
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void total_force(int mode, const double (&fe)[3], const double (&d)[3], double k,
                                             double k2, double lam, double (&F)[3])
@@ -408,7 +484,9 @@ __device__ __forceinline__ void total_force(int mode, const double (&fe)[3], con
 template <typename real, int T>
 __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 {
+    extern __shared__ float4 lds_tab[];
     __shared__ double sh[16 * 2];
+    constexpr bool kLds = sizeof(real) == 4;
     const Tile tl = a.tiles[blockIdx.x];
     if (tl.count == 0) return;
     const RepDesc& R = a.reps[tl.rep];
@@ -418,37 +496,48 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     const int i = tl.first + (valid ? la : 0);
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter : 0;
+    const int nr = a.tab.n_r;
 
+    if (kLds && a.has_eam) {
+        const float4* g = (const float4*)a.tab.pair;
+        for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
+        __syncthreads();
+    }
+
+    const double4 pi = a.P[i];
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, ep = 0.0;
     if (valid && a.has_eam) {
-        const double xi = a.x[i], yi = a.x[N + i], zi = a.x[2 * N + i];
         const int n = a.nnb[i];
         const int32_t* row = a.nbr + (size_t)i * a.cap;
-        const real* Fp = (const real*)a.Fp;
-        const real Fpi = Fp[i];
+        const real Fpi = (real)pi.w;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        const int nr = a.tab.n_r;
         for (int b0 = lane * SB; b0 < n; b0 += T * SB) {
             real p0 = (real)0, p1 = (real)0, p2 = (real)0, pe = (real)0;
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
                 const int q = b0 + s;
                 if (q < n) {
-                    const int j = row[q];
-                    double dx = xi - a.x[j], dy = yi - a.x[N + j], dz = zi - a.x[2 * N + j];
-                    min_image(R, dx, dy, dz);
-                    const real rx = (real)dx, ry = (real)dy, rz = (real)dz;
+                    const double4 pj = a.P[row[q]];
+                    const double3 d = sep(R, pi, pj);
+                    const real rx = (real)d.x, ry = (real)d.y, rz = (real)d.z;
                     const real r2 = rx * rx + ry * ry + rz * rz;
                     if (r2 < rc2) {
                         const real r = sqrt(r2);
                         real t;
                         const int m = interval<real>(r, inv_h, nr, t);
-                        decltype(Tab<real>::ld4(a.tab.rho, 0)) u, w;
-                        Tab<real>::ld8(a.tab.pair, m, u, w);
-                        const real phi = u.x + t * (u.y + t * (u.z + t * u.w));
-                        const real dphi = (u.y + t * ((real)2 * u.z + (real)3 * t * u.w)) * inv_h;
-                        const real drho = w.x + t * (w.y + t * w.z);
-                        const real g = dphi + (Fpi + Fp[j]) * drho;   // dU/dr_ij
+                        real ua, ub, uc, ud, wb, wc, wd;
+                        if constexpr (kLds) {
+                            const float4 u = lds_tab[2 * m], w = lds_tab[2 * m + 1];
+                            ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
+                        } else {
+                            decltype(Tab<real>::ld4(a.tab.rho, 0)) u, w;
+                            Tab<real>::ld8(a.tab.pair, m, u, w);
+                            ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
+                        }
+                        const real phi = ua + t * (ub + t * (uc + t * ud));
+                        const real dphi = (ub + t * ((real)2 * uc + (real)3 * t * ud)) * inv_h;
+                        const real drho = wb + t * (wc + t * wd);
+                        const real g = dphi + (Fpi + (real)pj.w) * drho;   // dU/dr_ij
                         const real s_ = -g / r;
                         p0 += s_ * rx;
                         p1 += s_ * ry;
@@ -474,11 +563,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     double e[2] = {0.0, 0.0};   // U_EAM contribution, |x - x0|^2
     if (valid && lane == 0) {
         const double fe[3] = {Acc<real>::fin(f0), Acc<real>::fin(f1), Acc<real>::fin(f2)};
-        double x[3] = {a.x[i], a.x[N + i], a.x[2 * N + i]};
+        double x[3] = {pi.x, pi.y, pi.z};
         const double d[3] = {x[0] - a.x0[i], x[1] - a.x0[N + i], x[2] - a.x0[2 * N + i]};
         e[0] = a.has_eam ? a.e_emb[i] + 0.5 * Acc<real>::fin(ep) : 0.0;
         e[1] = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (!isfinite(fe[0] + fe[1] + fe[2] + e[0])) atomicOr(a.status, ST_NONFINITE);
+        if (!isfinite(fe[0] + fe[1] + fe[2] + e[0] + e[1])) atomicOr(a.status, ST_NONFINITE);
         if (a.f_out) {
             a.f_out[i] = fe[0];
             a.f_out[N + i] = fe[1];
@@ -508,9 +597,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 const double r0 = x[0] - a.xref[i], r1 = x[1] - a.xref[N + i], r2 = x[2] - a.xref[2 * N + i];
                 if (r0 * r0 + r1 * r1 + r2 * r2 > a.half_skin2) a.rebuild[tl.rep] = 1;
             }
-            a.x_next[i] = x[0];
-            a.x_next[N + i] = x[1];
-            a.x_next[2 * N + i] = x[2];
+            a.Pn[i] = make_double4(x[0], x[1], x[2], 0.0);
             a.v[i] = v[0];
             a.v[N + i] = v[1];
             a.v[2 * N + i] = v[2];
@@ -589,6 +676,20 @@ __global__ void k_sub_mean_v(StepArgs a)
 // --------------------------------------------------------------------------
 static int grid1(int n, int b) { return (n + b - 1) / b; }
 
+int launch_pack(double4* P, const double* x, int N, hipStream_t s)
+{
+    if (N <= 0) return 0;
+    hipLaunchKernelGGL(k_pack, dim3(grid1(N, 256)), dim3(256), 0, s, P, x, N);
+    return (int)hipGetLastError();
+}
+
+int launch_unpack(double* x, const double4* P, int N, hipStream_t s)
+{
+    if (N <= 0) return 0;
+    hipLaunchKernelGGL(k_unpack, dim3(grid1(N, 256)), dim3(256), 0, s, x, P, N);
+    return (int)hipGetLastError();
+}
+
 int launch_check_displacement(const NeighArgs& a, hipStream_t s)
 {
     if (a.N <= 0) return 0;
@@ -596,25 +697,45 @@ int launch_check_displacement(const NeighArgs& a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
-int launch_neigh_rebuild(const NeighArgs& a, hipStream_t s)
+int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s)
 {
     if (a.N <= 0) return 0;
     hipLaunchKernelGGL(k_bin, dim3(grid1(a.N, 256)), dim3(256), 0, s, a);
-    if (a.n_cells > 0) hipLaunchKernelGGL(k_cellsort, dim3(grid1(a.n_cells, 128)), dim3(128), 0, s, a);
-    hipLaunchKernelGGL(k_list, dim3(grid1(a.N, 128)), dim3(128), 0, s, a);
+    if (a.n_cells > 0) {
+        int p2 = 1;
+        while (p2 < a.ccap) p2 <<= 1;
+        hipLaunchKernelGGL(k_cellsort, dim3(a.n_cells < 4096 ? a.n_cells : 4096), dim3(64), p2 * sizeof(int32_t), s,
+                           a);
+    }
+    dim3 g(a.n_grid), b(block);
+    switch (lanes) {
+    case 1: hipLaunchKernelGGL((k_list<1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_list<2>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_list<4>), g, b, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_list<8>), g, b, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_list<16>), g, b, 0, s, a); break;
+    default: return (int)hipErrorInvalidValue;
+    }
     return (int)hipGetLastError();
+}
+
+template <typename real>
+static size_t lds_bytes(const StepArgs& a, int tables)
+{
+    return (sizeof(real) == 4 && a.has_eam) ? (size_t)tables * (a.tab.n_r - 1) * sizeof(float4) : 0;
 }
 
 template <typename real>
 static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t s)
 {
     dim3 g(a.n_grid), b(block);
+    const size_t sh = lds_bytes<real>(a, 1);
     switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_density<real, 1>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_density<real, 2>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_density<real, 4>), g, b, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_density<real, 8>), g, b, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_density<real, 16>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_density<real, 1>), g, b, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((k_density<real, 2>), g, b, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((k_density<real, 4>), g, b, sh, s, a); break;
+    case 8: hipLaunchKernelGGL((k_density<real, 8>), g, b, sh, s, a); break;
+    case 16: hipLaunchKernelGGL((k_density<real, 16>), g, b, sh, s, a); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
@@ -624,12 +745,13 @@ template <typename real>
 static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s)
 {
     dim3 g(a.n_grid), b(block);
+    const size_t sh = lds_bytes<real>(a, 2);
     switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_force<real, 1>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_force<real, 2>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_force<real, 4>), g, b, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_force<real, 8>), g, b, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_force<real, 16>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_force<real, 1>), g, b, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((k_force<real, 2>), g, b, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((k_force<real, 4>), g, b, sh, s, a); break;
+    case 8: hipLaunchKernelGGL((k_force<real, 8>), g, b, sh, s, a); break;
+    case 16: hipLaunchKernelGGL((k_force<real, 16>), g, b, sh, s, a); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
@@ -648,7 +770,7 @@ int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStre
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s)
 {
     (void)n_rep;
-    // tiles hold at most block/lanes atoms; one thread per atom, >= one wave
+    // tiles hold at most block/lanes <= 1024 atoms; one thread per atom
     hipLaunchKernelGGL(k_init_v, dim3(a.n_grid), dim3(kMaxBlock), 0, s, a, fix_com);
     if (fix_com) hipLaunchKernelGGL(k_sub_mean_v, dim3(a.n_grid), dim3(kMaxBlock), 0, s, a);
     return (int)hipGetLastError();

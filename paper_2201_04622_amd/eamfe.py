@@ -64,6 +64,10 @@ def lib():
         "eamfe_get_launch": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "eamfe_set_xcd_affinity": (i32, [vp, i32]),
         "eamfe_check": (i32, [vp]),
+        "eamfe_set_kernel_timing": (i32, [vp, i32]),
+        "eamfe_autotune": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, i32, C.POINTER(i32), C.POINTER(i32), _dp]),
+        "eamfe_kernel_timing": (i32, [vp, _dp, C.POINTER(i64)]),
+        "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
         "neigh_build": (i32, [vp, vp, dbl, i32]),
@@ -73,6 +77,8 @@ def lib():
         "run_switching": (i32, [vp, C.POINTER(Protocol), i64, i64, vp, vp, vp, vp, vp, i32]),
         "switch_step": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, vp, vp]),
         "eamfe_get_work": (i32, [vp, _dp]),
+        "eamfe_set_chunk": (i32, [vp, i64]),
+        "eamfe_replays": (i32, [vp, C.POINTER(i64)]),
         "eamfe_adjoint_theta": (i32, [vp, vp, dbl, vp]),
         "eamfe_einstein_free_energy": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
@@ -208,6 +214,27 @@ class Context:
     def check(self):
         self._c(self._lib.eamfe_check(self._h))
 
+    def autotune(self, p: Protocol, step, x, v, trial_steps=20):
+        a, b, ms = C.c_int(), C.c_int(), C.c_double()
+        self._c(self._lib.eamfe_autotune(self._h, C.byref(p), int(step), _ptr(x), _ptr(v), int(trial_steps),
+                                         C.byref(a), C.byref(b), C.byref(ms)))
+        return a.value, b.value, ms.value
+
+    def set_kernel_timing(self, on=True):
+        self._c(self._lib.eamfe_set_kernel_timing(self._h, int(bool(on))))
+
+    def kernel_timing(self):
+        """{'density'|'force'|'lists': (total ms, launches)} since timing was enabled."""
+        ms = np.zeros(3)
+        n = (C.c_int64 * 3)()
+        self._c(self._lib.eamfe_kernel_timing(self._h, ms.ctypes.data_as(_dp), n))
+        return {k: (float(ms[q]), int(n[q])) for q, k in enumerate(("density", "force", "lists"))}
+
+    def list_stats(self):
+        m, mx, cap = C.c_double(), C.c_int(), C.c_int()
+        self._c(self._lib.eamfe_list_stats(self._h, C.byref(m), C.byref(mx), C.byref(cap)))
+        return m.value, mx.value, cap.value
+
     # -- ABI -----------------------------------------------------------------
     def eam_setup(self, knots):
         """knots: paper_2201_04622_amd.inputs.PotentialKnots."""
@@ -250,6 +277,14 @@ class Context:
 
     def switch_step(self, p: Protocol, step, x, v, W, dHdl=None):
         self._c(self._lib.switch_step(self._h, C.byref(p), int(step), _ptr(x), _ptr(v), _ptr(W), _ptr(dHdl)))
+
+    def set_chunk(self, steps):
+        self._c(self._lib.eamfe_set_chunk(self._h, int(steps)))
+
+    def replays(self):
+        n = C.c_int64()
+        self._c(self._lib.eamfe_replays(self._h, C.byref(n)))
+        return n.value
 
     def get_work(self):
         W = np.zeros(self.n_rep)

@@ -249,3 +249,35 @@ def test_harmonic_switching_on_gpu_reaches_closed_form(oracle_lib):
                                    True)
         assert np.abs(Wg[r] - Wo).max() < 1e-9
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_overflow_replay_is_the_same_trajectory(prec):
+    """Rows far too short for a dense crystal: run_switching detects the
+    overflow, enlarges the lists, replays the chunk, and ends bit-identical
+    to a run that had room from the start."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = [I.Replica("bcc", 6, I.A_BCC_STABLE, 800.0, 5.0, 3), I.Replica("fcc", 5, I.A_FCC_STABLE, 800.0, 5.0, 4)]
+    p = E.protocol("fl", 20, 60, 10, 10)
+    out = []
+    for cap in (32, 0):
+        ctx, x0, arrs = make_ctx(reps, prec)
+        ctx.set_chunk(40)
+        x = x0.clone()
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        if cap:
+            with pytest.raises(E.EamfeError):
+                ctx.neigh_build(x, 0.3, cap)
+        else:
+            ctx.neigh_build(x, 0.3, 0)
+        W = torch.zeros(len(reps), 160, dtype=torch.float64, device="cuda")
+        ctx.run_switching(p, x, v, 0, 160, None, None, W)
+        out.append((x.cpu().numpy(), v.cpu().numpy(), W.cpu().numpy(), ctx.replays(), ctx.list_stats()))
+        ctx.close()
+    assert out[0][3] > 0 and out[1][3] == 0
+    assert out[0][4][2] >= out[0][4][1]
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
