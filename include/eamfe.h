@@ -122,6 +122,12 @@ int eamfe_set_stream(eamfe_ctx* ctx, void* hip_stream);
 int eamfe_set_launch(eamfe_ctx* ctx, int lanes_per_atom, int block_threads);
 int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threads);
 
+/* Blocks launched for the density and force passes (rounded up to a
+ * multiple of 8); each block stages the spline table once and strides over
+ * the tiles.  0 = one block per tile (default). */
+int eamfe_set_grid(eamfe_ctx* ctx, int blocks);
+int eamfe_get_grid(const eamfe_ctx* ctx, int* blocks);
+
 /* 1: place every replica's tiles on one XCD (workgroup id mod 8), balancing
  * atoms across the eight XCDs; 0: replica-major order.  Default 1. */
 int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
@@ -144,6 +150,11 @@ int eamfe_kernel_timing(eamfe_ctx* ctx, double* ms_total, int64_t* launches);
  * maximum row length over all atoms, and the row capacity. */
 int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capacity);
 
+/* Copy the current Verlet rows (for inspection): nnb_dev[N_tot] row lengths,
+ * nbr_dev[N_tot][cap] global atom ids (may be NULL; cap >= the row capacity
+ * reported by eamfe_list_stats).  Device int32 arrays.  Synchronises. */
+int eamfe_copy_lists(eamfe_ctx* ctx, int32_t* nnb_dev, int32_t* nbr_dev, int cap);
+
 /* ---- potential --------------------------------------------------------- */
 
 /* Tabulated EAM (the paper's "pair eam" input; Eq. H with U = EAM):
@@ -158,14 +169,16 @@ int eam_setup(eamfe_ctx* ctx, int n_r, double r_cut, const double* phi_knots,
 
 /* ---- system ------------------------------------------------------------ */
 
-/* Describe n_rep replicas (host array) and their lattice sites x0 (device,
- * SoA [3][N_tot], copied).  N_tot = sum n_atoms.  Replaces any previous system. */
+/* Describe n_rep replicas (host array, 1 <= n_rep <= 8192) and their lattice
+ * sites x0 (device, SoA [3][N_tot], copied).  N_tot = sum n_atoms.  Replaces
+ * any previous system. */
 int eamfe_system_setup(eamfe_ctx* ctx, int n_rep, const eamfe_replica* reps, const double* x0_dev);
 
 /* Build the Verlet lists at positions x (device SoA) with cutoff r_cut+skin:
  * cell binning with cells of edge >= r_cut+skin where a box holds at least
  * three per edge, all-pairs otherwise.  max_neighbors bounds each atom's row
- * (0 = estimate from the densest replica).  EAMFE_EBOX if an edge <= 2(r_cut+skin). */
+ * (rounded up to a multiple of 32; 0 = estimate from the densest replica).
+ * EAMFE_EBOX if an edge <= 2(r_cut+skin). */
 int neigh_build(eamfe_ctx* ctx, const double* x_dev, double skin, int max_neighbors);
 
 /* ---- evaluation -------------------------------------------------------- */

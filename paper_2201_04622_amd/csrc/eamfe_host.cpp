@@ -25,6 +25,8 @@ struct eamfe_ctx {
     int precision = EAMFE_FP64;
     int lanes = 4;
     int block = 256;
+    int grid = 0;      // pair-kernel blocks (0: one per tile), a multiple of 8
+    int n_cu = 256;
     int xcd = 1;
     std::string err;
 
@@ -43,7 +45,7 @@ struct eamfe_ctx {
     std::vector<RepDesc> reps;
     std::vector<Tile> tiles;
     int n_tiles = 0;   // real tiles
-    DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, e_emb_d, xi_d;
+    DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, noise_sum_d, U_rep_d, W_state_d;
     DevBuf cnt_density_d, cnt_force_d, cnt_all_d, iter_d, rebuild_d, status_d;
 
@@ -69,10 +71,15 @@ struct eamfe_ctx {
     int64_t chunk = 1000;
     int min_ccap = 0;
     int64_t replays = 0;
-    DevBuf snap_P, snap_v, snap_w;
+    DevBuf snap_P, snap_Q, snap_v, snap_w;
+
+    // folded single-precision positions for the list builder
+    DevBuf Pf_d;
 
     // lambda table
     DevBuf lam_d;
+
+    long n_atoms_total() const { return N; }
     std::vector<double> lam_h;
     eamfe_protocol lam_key{};
     bool lam_valid = false;
@@ -259,6 +266,12 @@ int upload_reps(eamfe_ctx* c)
     return EAMFE_OK;
 }
 
+double4* PA(eamfe_ctx* c) { return (double4*)c->Pa_d.p; }
+double4* PB(eamfe_ctx* c) { return (double4*)c->Pb_d.p; }
+uint4* QA(eamfe_ctx* c) { return (uint4*)c->Qa_d.p; }
+uint4* QB(eamfe_ctx* c) { return (uint4*)c->Qb_d.p; }
+uint4* Q_of(eamfe_ctx* c, const double4* P) { return P == PA(c) ? QA(c) : QB(c); }
+
 NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
 {
     NeighArgs a{};
@@ -267,7 +280,9 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
     a.rep_of = (const int32_t*)c->rep_of_d.p;
     a.cell_rep = (const int32_t*)c->cell_rep_d.p;
     a.P = P;
+    a.Q = Q_of(c, P);
     a.n_grid = (int)c->tiles.size();
+    a.n_rep = c->n_rep;
     a.xref = (double*)c->xref_d.p;
     a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
     a.cell_n = (int32_t*)c->cell_n_d.p;
@@ -281,6 +296,14 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
     a.ccap = c->ccap;
     a.cap = c->cap;
     a.rl2 = (c->r_cut + c->skin) * (c->r_cut + c->skin);
+    {
+        // candidate test in single precision on folded coordinates: widen the
+        // radius by far more than its rounding so no pair within r_cut + skin is lost
+        double Lmax = 0.0;
+        for (const auto& R : c->reps) Lmax = std::max({Lmax, R.L[0], R.L[1], R.L[2]});
+        const double margin = std::max(1e-3, 64.0 * Lmax * 1.2e-7);
+        a.rl2_f = (float)((c->r_cut + c->skin + margin) * (c->r_cut + c->skin + margin));
+    }
     a.half_skin2 = 0.25 * c->skin * c->skin;
     return a;
 }
@@ -312,6 +335,7 @@ StepArgs step_args(eamfe_ctx* c)
     a.N = c->N;
     a.n_tiles = c->n_tiles;
     a.n_grid = (int)c->tiles.size();
+    a.grid_blocks = c->grid;
     a.half_skin2 = 0.25 * c->skin * c->skin;
     return a;
 }
@@ -354,7 +378,8 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
         const double nmean = 4.0 / 3.0 * M_PI * rl * rl * rl * dens_max;
         max_neighbors = (int)(std::ceil((nmean * 2.0 + 32.0) / 32.0) * 32.0);
     }
-    c->cap = max_neighbors;
+    // rows are read four slots at a time from 16-byte aligned addresses
+    c->cap = (max_neighbors + 31) / 32 * 32;
     c->n_cells = n_cells;
     c->skin = skin;
     OK(ensure(c, c->nbr_d, (size_t)c->N * c->cap * sizeof(int32_t)));
@@ -497,8 +522,14 @@ int ensure_lists(eamfe_ctx* c, double skin, const double4* P)
     return EAMFE_OK;
 }
 
-double4* PA(eamfe_ctx* c) { return (double4*)c->Pa_d.p; }
-double4* PB(eamfe_ctx* c) { return (double4*)c->Pb_d.p; }
+
+// Pack caller SoA positions into the A buffers (both numeric forms).
+int pack(eamfe_ctx* c, const double* x)
+{
+    LCHK(c, launch_pack(PA(c), QA(c), x, (const int32_t*)c->rep_of_d.p, (const RepDesc*)c->reps_d.p, c->N,
+                        c->stream));
+    return EAMFE_OK;
+}
 
 // Record a timing event (kind: 0 density, 1 force, 2 lists; end = 0 start, 1 stop).
 int mark(eamfe_ctx* c, int kind, int end)
@@ -535,6 +566,8 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
         }
         a.P = cur;
         a.Pn = nxt;
+        a.Q = Q_of(c, cur);
+        a.Qn = Q_of(c, nxt);
         OK(mark(c, 0, 0));
         LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
         OK(mark(c, 0, 1));
@@ -580,6 +613,11 @@ int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->precision = precision;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            c->n_cu = cus;
+    }
     int r = EAMFE_OK;
     if ((r = ensure(c, c->cnt_all_d, sizeof(uint32_t))) || (r = ensure(c, c->iter_d, sizeof(int64_t))) ||
         (r = ensure(c, c->status_d, sizeof(int32_t)))) {
@@ -602,16 +640,18 @@ int eamfe_destroy(eamfe_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
-                      &c->xref_d, &c->Pa_d, &c->Pb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
+                      &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
                       &c->energy_part_d, &c->noise_sum_d, &c->U_rep_d, &c->W_state_d, &c->cnt_density_d,
                       &c->cnt_force_d, &c->cnt_all_d, &c->iter_d, &c->rebuild_d, &c->status_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
+    release(c->Pf_d);
     release(c->tune_x);
     release(c->tune_v);
     release(c->tune_w);
     release(c->snap_P);
+    release(c->snap_Q);
     release(c->snap_v);
     release(c->snap_w);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -642,6 +682,20 @@ int eamfe_set_launch(eamfe_ctx* c, int lanes, int block)
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return build_tiles(c);
     }
+    return EAMFE_OK;
+}
+
+int eamfe_set_grid(eamfe_ctx* c, int blocks)
+{
+    if (!c || blocks < 0) return EAMFE_EINVAL;
+    c->grid = (blocks + 7) / 8 * 8;
+    return EAMFE_OK;
+}
+
+int eamfe_get_grid(const eamfe_ctx* c, int* blocks)
+{
+    if (!c || !blocks) return EAMFE_EINVAL;
+    *blocks = c->grid;
     return EAMFE_OK;
 }
 
@@ -700,6 +754,8 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
 {
     if (!c) return EAMFE_EINVAL;
     if (n_rep < 1 || !in || !x0_dev) return fail(c, EAMFE_EINVAL, "system_setup: bad arguments");
+    if (n_rep > kMaxRepsList)
+        return fail(c, EAMFE_EINVAL, "system_setup: at most " + std::to_string(kMaxRepsList) + " replicas");
     (void)hipSetDevice(c->device);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     long N = 0;
@@ -740,6 +796,9 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->x0_d, v3));
     OK(ensure(c, c->xref_d, v3));
     OK(ensure(c, c->Pa_d, (size_t)N * sizeof(double4)));
+    OK(ensure(c, c->Qa_d, (size_t)N * sizeof(uint4)));
+    OK(ensure(c, c->Qb_d, (size_t)N * sizeof(uint4)));
+    OK(ensure(c, c->Pf_d, (size_t)N * sizeof(float4)));
     OK(ensure(c, c->Pb_d, (size_t)N * sizeof(double4)));
     OK(ensure(c, c->xi_d, v3));
     OK(ensure(c, c->e_emb_d, (size_t)N * sizeof(double)));
@@ -755,6 +814,8 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
     HIPCHK(c, hipMemset(c->Pa_d.p, 0, (size_t)N * sizeof(double4)));
     HIPCHK(c, hipMemset(c->Pb_d.p, 0, (size_t)N * sizeof(double4)));
+    HIPCHK(c, hipMemset(c->Qa_d.p, 0, (size_t)N * sizeof(uint4)));
+    HIPCHK(c, hipMemset(c->Qb_d.p, 0, (size_t)N * sizeof(uint4)));
     HIPCHK(c, hipMemset(c->e_emb_d.p, 0, (size_t)N * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->rep_of_d.p, rep_of.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(c->noise_sum_d.p, 0, (size_t)n_rep * 3 * sizeof(double)));
@@ -776,7 +837,7 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
     OK(plan_lists(c, skin, max_neighbors));
     c->have_list = true;
     OK(set_rebuild_all(c));
-    LCHK(c, launch_pack(PA(c), x, c->N, c->stream));
+    OK(pack(c, x));
     NeighArgs na = neigh_args(c, PA(c));
     LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
     // the flags are cleared by the next density pass; clear them here too
@@ -791,7 +852,7 @@ int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_at
     if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
     if (!x) return fail(c, EAMFE_EINVAL, "eam_forces: null positions");
     (void)hipSetDevice(c->device);
-    LCHK(c, launch_pack(PA(c), x, c->N, c->stream));
+    OK(pack(c, x));
     OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
     for (int attempt = 0;; ++attempt) {
         NeighArgs na = neigh_args(c, PA(c));
@@ -799,6 +860,8 @@ int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_at
         StepArgs a = step_args(c);
         a.P = PA(c);
         a.Pn = nullptr;
+        a.Q = QA(c);
+        a.Qn = nullptr;
         a.v = nullptr;
         a.has_eam = 1;
         a.step_kernel = 0;
@@ -869,13 +932,15 @@ namespace {
 int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int64_t s1, double* x, double* v,
               double* dHdl_out, double* W_out, int64_t stride, int64_t trace_off, double c1, bool has_eam)
 {
-    LCHK(c, launch_pack(PA(c), x, c->N, c->stream));
+    OK(pack(c, x));
     double4* cur = PA(c);
     if (has_eam) OK(ensure_lists(c, p->skin, cur));
     const size_t v3 = 3 * (size_t)c->N * sizeof(double);
     const size_t p4 = (size_t)c->N * sizeof(double4);
     const size_t wb = (size_t)c->n_rep * sizeof(double);
+    const size_t q4 = (size_t)c->N * sizeof(uint4);
     if (has_eam) {
+        OK(ensure(c, c->snap_Q, q4));
         OK(ensure(c, c->snap_P, p4));
         OK(ensure(c, c->snap_v, v3));
         OK(ensure(c, c->snap_w, wb));
@@ -884,6 +949,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
         const int64_t e = std::min(s1, b + c->chunk);
         if (has_eam) {
             HIPCHK(c, hipMemcpyAsync(c->snap_P.p, cur, p4, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->snap_Q.p, Q_of(c, cur), q4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->snap_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->snap_w.p, c->W_state_d.p, wb, hipMemcpyDeviceToDevice, c->stream));
         }
@@ -914,6 +980,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             OK(set_rebuild_all(c));
             cur = start;
             HIPCHK(c, hipMemcpyAsync(cur, c->snap_P.p, p4, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(Q_of(c, cur), c->snap_Q.p, q4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(v, c->snap_v.p, v3, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->W_state_d.p, c->snap_w.p, wb, hipMemcpyDeviceToDevice, c->stream));
             ++c->replays;
@@ -1046,8 +1113,8 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
                              hipMemcpyDeviceToDevice, c->stream));
     const int timing = c->timing;
     c->timing = 0;
-    const int lanes0 = c->lanes, block0 = c->block;
-    int best_l = lanes0, best_b = block0;
+    const int lanes0 = c->lanes, block0 = c->block, grid0 = c->grid;
+    int best_l = lanes0, best_b = block0, best_g = grid0;
     double best = 1e300;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1055,11 +1122,15 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
     int rc = EAMFE_OK;
     const int lanes_c[] = {1, 2, 4, 8, 16};
     const int block_c[] = {64, 128, 256, 512, 1024};
+    const int grid_c[] = {0, c->n_cu, 2 * c->n_cu, 4 * c->n_cu};
     for (int L : lanes_c) {
         for (int B : block_c) {
+          for (int G : grid_c) {
             if (B / L < 4) continue;   // at least four atoms per block
             c->lanes = L;
             c->block = B;
+            c->grid = (G + 7) / 8 * 8;
+            if (G && (int)((c->n_atoms_total() + B / L - 1) / (B / L)) <= c->grid) continue;   // no fewer blocks than tiles
             if ((rc = build_tiles(c))) goto done;
             if (hipMemcpyAsync(c->tune_x.p, x, v3, hipMemcpyDeviceToDevice, c->stream) ||
                 hipMemcpyAsync(c->tune_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream)) {
@@ -1083,8 +1154,10 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
                     best = per;
                     best_l = L;
                     best_b = B;
+                    best_g = c->grid;
                 }
             }
+          }
         }
     }
 done:
@@ -1093,6 +1166,7 @@ done:
     c->timing = timing;
     c->lanes = rc ? lanes0 : best_l;
     c->block = rc ? block0 : best_b;
+    c->grid = rc ? grid0 : best_g;
     {
         const int r2 = build_tiles(c);
         if (!rc) rc = r2;
@@ -1105,6 +1179,21 @@ done:
     if (block_out) *block_out = best_b;
     if (ms_per_step) *ms_per_step = best;
     return read_status(c);
+}
+
+int eamfe_copy_lists(eamfe_ctx* c, int32_t* nnb_dev, int32_t* nbr_dev, int cap)
+{
+    if (!c || !nnb_dev) return EAMFE_EINVAL;
+    if (!c->have_list) return fail(c, EAMFE_ESTATE, "no neighbour lists");
+    if (nbr_dev && cap < c->cap) return fail(c, EAMFE_EINVAL, "copy_lists: capacity smaller than the rows'");
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipMemcpyAsync(nnb_dev, c->nnb_d.p, (size_t)c->N * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                             c->stream));
+    if (nbr_dev)
+        HIPCHK(c, hipMemcpy2DAsync(nbr_dev, (size_t)cap * sizeof(int32_t), c->nbr_d.p, (size_t)c->cap * sizeof(int32_t),
+                                   (size_t)c->cap * sizeof(int32_t), c->N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EAMFE_OK;
 }
 
 __global__ void k_list_stats(const int32_t* nnb, int n, unsigned long long* out)

@@ -23,6 +23,9 @@ enum : int {
 
 enum : int { MODE_FL = 0, MODE_RS = 1, MODE_HH = 2, MODE_EIN_RS = 3 };
 
+// Replicas per context (bounded by the list builder's LDS prefix table).
+constexpr int kMaxRepsList = 8192;
+
 // Fixed-point quantum of the FP32 accumulators: sums are carried as exact
 // integers (multiples of 2^-32) inside float64, so addition is associative.
 constexpr double kFixScale = 4294967296.0;          // 2^32
@@ -69,6 +72,7 @@ struct NeighArgs {
     const int32_t* rep_of;      // [N] replica of each atom
     const int32_t* cell_rep;    // [n_cells] replica of each cell
     const double4* P;           // [N] packed positions (x, y, z, .)
+    const uint4* Q;             // [N] box coordinates frac(x/L) 2^32
     double* xref;               // SoA [3][N]
     int32_t* cell_cnt;          // [n_cells]
     int32_t* cell_n;            // [n_cells] sorted occupancy
@@ -79,7 +83,9 @@ struct NeighArgs {
     int32_t* status;
     int N, n_cells, ccap, cap;
     int n_grid;                 // tiles launched (including padding)
+    int n_rep;
     double rl2;                 // (r_cut + skin)^2
+    float rl2_f;                // (r_cut + skin + margin)^2 for the single-precision candidate test
     double half_skin2;          // (skin/2)^2
 };
 
@@ -87,8 +93,10 @@ struct NeighArgs {
 struct StepArgs {
     const Tile* tiles;
     const RepDesc* reps;
-    double4* P;             // [N] positions at the start of the iteration, .w = F'(rho_i)
+    double4* P;             // [N] positions at the start of the iteration, .w = F'(rho_i) (FP64 form)
     double4* Pn;            // [N] positions after the step
+    uint4* Q;               // [N] FP32 form: box coordinates frac(x/L) 2^32 per axis, .w = F'(rho_i) bits
+    uint4* Qn;              // [N] box coordinates after the step
     double* v;              // SoA, in place
     const double* x0;       // SoA
     const double* xref;     // SoA, list reference positions
@@ -123,7 +131,8 @@ struct StepArgs {
     int fix_com;
     int has_eam;
     int n_tiles;            // real (non-padding) tiles
-    int n_grid;             // launched blocks = tiles including padding
+    int n_grid;             // tiles including padding
+    int grid_blocks;        // blocks launched for the pair kernels (<= n_grid; multiple of 8)
     int step_kernel;        // 1: integrate; 0: evaluate only (eam_forces)
     double dt;
     double c1;
@@ -145,7 +154,8 @@ struct AdjointArgs {
 };
 
 // Launchers (eamfe_kernels.hip).  Each returns a hipError_t as int.
-int launch_pack(double4* P, const double* x, int N, hipStream_t s);
+int launch_pack(double4* P, uint4* Q, const double* x, const int32_t* rep_of, const RepDesc* reps, int N,
+                hipStream_t s);
 int launch_unpack(double* x, const double4* P, int N, hipStream_t s);
 int launch_check_displacement(const NeighArgs& a, hipStream_t s);
 int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s);

@@ -135,6 +135,40 @@ __device__ __forceinline__ void min_image(const RepDesc& R, double& dx, double& 
     dz -= R.L[2] * rint(dz * R.invL[2]);
 }
 
+
+// 1/r and r from r^2: hardware reciprocal square root in FP32 (about 1 ulp),
+// correctly rounded sqrt and division in FP64.
+template <typename real>
+struct Root;
+template <>
+struct Root<float> {
+    static __device__ __forceinline__ void of(float r2, float& r, float& ir)
+    {
+        ir = __builtin_amdgcn_rsqf(r2);
+        r = r2 * ir;
+    }
+};
+template <>
+struct Root<double> {
+    static __device__ __forceinline__ void of(double r2, double& r, double& ir)
+    {
+        r = sqrt(r2);
+        ir = 1.0 / r;
+    }
+};
+
+// Neighbour ids of slots [b0, b0+SB) of a row (SB = 4, 16-byte aligned since
+// rows start at multiples of the capacity, a multiple of 32); slots at or
+// beyond n read as the atom itself, whose contribution is masked out.
+__device__ __forceinline__ int4 row_ids(const int32_t* row, int b0, int n, int self)
+{
+    int4 j = *(const int4*)(row + b0);
+    if (b0 + 1 >= n) j.y = self;
+    if (b0 + 2 >= n) j.z = self;
+    if (b0 + 3 >= n) j.w = self;
+    return j;
+}
+
 // --------------------------------------------------------------------------
 // Deterministic block reductions
 // --------------------------------------------------------------------------
@@ -203,10 +237,31 @@ __device__ bool replica_reduce(const double (&vin)[K], double* part, uint32_t* c
 // Packed positions: the pair kernels gather one 32-byte record per neighbour
 // (x, y, z and, after the density pass, F'(rho)) instead of four arrays.
 // --------------------------------------------------------------------------
-__global__ void k_pack(double4* P, const double* x, int N)
+// Box coordinate of x along an axis of length L: frac(x/L) as a 32-bit
+// fixed-point number.  The signed 32-bit difference of two box coordinates
+// is the minimum-image separation in units of L/2^32 (integer wrap-around is
+// the periodicity), exact up to the 2^-32 L quantum.
+__device__ __forceinline__ uint32_t box_code(double x, double invL)
+{
+    double f = x * invL;
+    f -= floor(f);
+    return (uint32_t)(unsigned long long)(f * 4294967296.0);   // f == 1.0 wraps to 0
+}
+
+__device__ __forceinline__ uint4 box_codes(const RepDesc& R, double x, double y, double z, uint32_t w)
+{
+    return make_uint4(box_code(x, R.invL[0]), box_code(y, R.invL[1]), box_code(z, R.invL[2]), w);
+}
+
+// Cell of a box coordinate on an nc-cell axis (exact integer arithmetic).
+__device__ __forceinline__ int box_cell(uint32_t q, int nc) { return (int)(((uint64_t)q * (uint64_t)nc) >> 32); }
+
+__global__ void k_pack(double4* P, uint4* Q, const double* x, const int32_t* rep_of, const RepDesc* reps, int N)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) P[i] = make_double4(x[i], x[N + i], x[2 * N + i], 0.0);
+    if (i >= N) return;
+    P[i] = make_double4(x[i], x[N + i], x[2 * N + i], 0.0);
+    Q[i] = box_codes(reps[rep_of[i]], x[i], x[N + i], x[2 * N + i], 0u);
 }
 
 __global__ void k_unpack(double* x, const double4* P, int N)
@@ -259,10 +314,8 @@ __global__ void k_bin(NeighArgs a)
     if (!a.rebuild[r]) return;
     const RepDesc& R = a.reps[r];
     if (R.nc[0] == 0) return;
-    const double4 p = a.P[i];
-    const int cx = cell_coord(p.x, R.L[0], R.invL[0], R.nc[0]);
-    const int cy = cell_coord(p.y, R.L[1], R.invL[1], R.nc[1]);
-    const int cz = cell_coord(p.z, R.L[2], R.invL[2], R.nc[2]);
+    const uint4 q = a.Q[i];
+    const int cx = box_cell(q.x, R.nc[0]), cy = box_cell(q.y, R.nc[1]), cz = box_cell(q.z, R.nc[2]);
     const int c = R.cell_base + (cx * R.nc[1] + cy) * R.nc[2] + cz;
     const int slot = atomicAdd(&a.cell_cnt[c], 1);
     if (slot < a.ccap)
@@ -309,71 +362,134 @@ __global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
     }
 }
 
-// Rows, T lanes per atom: each pass tests T consecutive candidates and the
-// accepted ones are appended in candidate order (ballot + prefix count).
-template <int T>
-__global__ __launch_bounds__(kMaxBlock) void k_list(NeighArgs a)
+// Rows: one wavefront per atom of a flagged replica (waves of the whole grid
+// stride over the flagged atoms; each block first forms the prefix of
+// flagged replica sizes in LDS).  The 27 stencil cells' members form one
+// candidate stream in a fixed order (cells by offset, atoms by id); each pass
+// tests 64 candidates with exact minimum-image box coordinates and appends
+// the accepted ones in stream order (ballot + prefix count).
+constexpr int kListBlock = 256;
+constexpr int kListGrid = 1024;
+
+__global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 {
-    const Tile tl = a.tiles[blockIdx.x];
-    if (tl.count == 0 || !a.rebuild[tl.rep]) return;
-    const int lane = threadIdx.x % T;
-    const int la = threadIdx.x / T;
-    if (la >= tl.count) return;   // the whole T-lane group leaves together
-    const RepDesc& R = a.reps[tl.rep];
-    const int i = tl.first + la;
-    const int il = i - R.off;
-    const double4 pi = a.P[i];
-    int32_t* row = a.nbr + (size_t)i * a.cap;
-    const int lw = threadIdx.x & 63;
-    const int gb = lw & ~(T - 1);
-    const uint64_t gmask = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
-    const uint64_t below = (1ull << (lw - gb)) - 1ull;
-    int cnt = 0;
-    auto pass = [&](int jl, bool in) {
-        bool acc = false;
-        int j = 0;
-        if (in && jl != il) {
-            j = R.off + jl;
-            const double3 d = sep(R, pi, a.P[j]);
-            acc = d.x * d.x + d.y * d.y + d.z * d.z < a.rl2;
+    __shared__ int pre[kMaxRepsList + 1];
+    __shared__ int wsum[kListBlock / 64];
+    __shared__ int cend[kListBlock / 64][28];   // per wave: inclusive prefix of stencil cell sizes
+    __shared__ int cid[kListBlock / 64][28];    // per wave: global stencil cell ids
+    const int lw = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int carry = 0;
+    for (int base = 0; base < n_rep; base += kListBlock) {
+        const int r = base + threadIdx.x;
+        const int v = (r < n_rep && a.rebuild[r]) ? a.reps[r].n : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lw >= o) x += y;
         }
-        const uint64_t m = (__ballot(acc) >> gb) & gmask;
-        const int rank = __popcll(m & below);
-        if (acc && cnt + rank < a.cap) row[cnt + rank] = j;
-        cnt += __popcll(m);
-    };
-    if (R.nc[0] == 0) {
-        for (int s0 = 0; s0 < R.n; s0 += T) pass(s0 + lane, s0 + lane < R.n);
-    } else {
-        const int cx = cell_coord(pi.x, R.L[0], R.invL[0], R.nc[0]);
-        const int cy = cell_coord(pi.y, R.L[1], R.invL[1], R.nc[1]);
-        const int cz = cell_coord(pi.z, R.L[2], R.invL[2], R.nc[2]);
-        for (int ox = -1; ox <= 1; ++ox) {
-            const int ux = (cx + ox + R.nc[0]) % R.nc[0];
-            for (int oy = -1; oy <= 1; ++oy) {
-                const int uy = (cy + oy + R.nc[1]) % R.nc[1];
-                for (int oz = -1; oz <= 1; ++oz) {
-                    const int uz = (cz + oz + R.nc[2]) % R.nc[2];
-                    const int c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
-                    const int n = a.cell_n[c];
-                    const int32_t* p = a.cell_atoms + (size_t)c * a.ccap;
-                    for (int s0 = 0; s0 < n; s0 += T) {
-                        const int s = s0 + lane;
-                        pass(s < n ? p[s] : -1, s < n);
-                    }
-                }
-            }
+        if (lw == 63) wsum[w] = x;
+        __syncthreads();
+        int off = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kListBlock / 64; ++q) {
+            off += q < w ? wsum[q] : 0;
+            tot += wsum[q];
         }
+        if (r < n_rep) pre[r] = carry + off + x - v;
+        carry += tot;
+        __syncthreads();
     }
-    if (lane == 0) {
-        if (cnt > a.cap) {
-            atomicOr(a.status, ST_NEIGH_OVERFLOW);
-            cnt = a.cap;
+    if (threadIdx.x == 0) pre[n_rep] = carry;
+    __syncthreads();
+    const int total = pre[n_rep];
+    if (total == 0) return;
+
+    const uint64_t below = (1ull << lw) - 1ull;
+    const int waves = gridDim.x * (kListBlock / 64);
+    for (int f = blockIdx.x * (kListBlock / 64) + w; f < total; f += waves) {
+        int lo = 0, hi = n_rep;   // replica holding flagged atom f: pre[lo] <= f < pre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= f) lo = mid;
+            else hi = mid;
         }
-        a.nnb[i] = cnt;
-        a.xref[i] = pi.x;
-        a.xref[a.N + i] = pi.y;
-        a.xref[2 * a.N + i] = pi.z;
+        const RepDesc& R = a.reps[lo];
+        const int il = f - pre[lo];
+        const int i = R.off + il;
+        const uint4 qi = a.Q[i];
+        const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
+                    sz = (float)(R.L[2] * 2.3283064365386963e-10);
+        int32_t* row = a.nbr + (size_t)i * a.cap;
+        int cnt = 0;
+        auto test = [&](int jl) {
+            const uint4 qj = a.Q[R.off + jl];
+            const float dx = (float)(int)(qi.x - qj.x) * sx, dy = (float)(int)(qi.y - qj.y) * sy,
+                        dz = (float)(int)(qi.z - qj.z) * sz;
+            return jl != il && dx * dx + dy * dy + dz * dz < a.rl2_f;
+        };
+        auto append = [&](bool acc, int j) {
+            const uint64_t m = __ballot(acc);
+            const int rank = __popcll(m & below);
+            if (acc && cnt + rank < a.cap) row[cnt + rank] = j;
+            cnt += __popcll(m);
+        };
+        if (R.nc[0] == 0) {
+            for (int s0 = 0; s0 < R.n; s0 += 64) {
+                const int jl = s0 + lw;
+                append(jl < R.n && test(jl), R.off + jl);
+            }
+        } else {
+            const int cx = box_cell(qi.x, R.nc[0]), cy = box_cell(qi.y, R.nc[1]), cz = box_cell(qi.z, R.nc[2]);
+            int n_c = 0, c = 0;
+            if (lw < 27) {
+                const int ux = (cx + lw / 9 - 1 + R.nc[0]) % R.nc[0];
+                const int uy = (cy + (lw / 3) % 3 - 1 + R.nc[1]) % R.nc[1];
+                const int uz = (cz + lw % 3 - 1 + R.nc[2]) % R.nc[2];
+                c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
+                n_c = a.cell_n[c];
+            }
+            int incl = n_c;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lw >= o) incl += y;
+            }
+            if (lw < 27) {
+                cend[w][lw] = incl;
+                cid[w][lw] = c;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int tot_c = __shfl(incl, 26, 64);
+            for (int k0 = 0; k0 < tot_c; k0 += 64) {
+                const int k = k0 + lw;
+                bool acc = false;
+                int j = 0;
+                if (k < tot_c) {
+                    int q = 0;   // first stencil cell whose inclusive end exceeds k
+#pragma unroll
+                    for (int step = 16; step > 0; step >>= 1)
+                        if (q + step <= 26 && cend[w][q + step - 1] <= k) q += step;
+                    const int slot = k - (q ? cend[w][q - 1] : 0);
+                    const int jl = a.cell_atoms[(size_t)cid[w][q] * a.ccap + slot];
+                    j = R.off + jl;
+                    acc = test(jl);
+                }
+                append(acc, j);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lw == 0) {
+            if (cnt > a.cap) {
+                atomicOr(a.status, ST_NEIGH_OVERFLOW);
+                cnt = a.cap;
+            }
+            a.nnb[i] = cnt;
+            const double4 pi = a.P[i];
+            a.xref[i] = pi.x;
+            a.xref[a.N + i] = pi.y;
+            a.xref[2 * a.N + i] = pi.z;
+        }
     }
 }
 
@@ -386,50 +502,79 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     extern __shared__ float4 lds_tab[];
     __shared__ double sh[16 * 3];
     constexpr bool kLds = sizeof(real) == 4;
-    const Tile tl = a.tiles[blockIdx.x];
-    if (tl.count == 0) return;   // padding tile: whole block leaves
+    constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
+    const int N = a.N;
+    const int64_t it = a.step_kernel ? *a.iter : 0;
+    const int nr = a.tab.n_r;
+    if (kLds && a.has_eam) {   // table staged once per block; blocks then stride over tiles
+        const float4* g = (const float4*)a.tab.rho;
+        for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
+        __syncthreads();
+    }
+    for (int tix = blockIdx.x; tix < a.n_grid; tix += gridDim.x) {
+    const Tile tl = a.tiles[tix];
+    if (tl.count == 0) continue;   // padding tile (uniform in the block)
     const RepDesc& R = a.reps[tl.rep];
     const int lane = threadIdx.x % T;
     const int la = threadIdx.x / T;
     const bool valid = la < tl.count;
     const int i = tl.first + (valid ? la : 0);
-    const int N = a.N;
-    const int64_t it = a.step_kernel ? *a.iter : 0;
-    const int nr = a.tab.n_r;
-
-    if (kLds && a.has_eam) {
-        const float4* g = (const float4*)a.tab.rho;
-        for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
-        __syncthreads();
-    }
 
     double acc = 0.0;
-    double4 pi = a.P[i];
+    const double4 pi = a.P[i];
+    const uint4 qi = kQ ? a.Q[i] : make_uint4(0u, 0u, 0u, 0u);
+    const float qsx = (float)(R.L[0] * 2.3283064365386963e-10), qsy = (float)(R.L[1] * 2.3283064365386963e-10),
+                qsz = (float)(R.L[2] * 2.3283064365386963e-10);
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
         const int32_t* row = a.nbr + (size_t)i * a.cap;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        for (int b0 = lane * SB; b0 < n; b0 += T * SB) {
+        const int step = T * SB;
+        int4 jn = lane * SB < n ? row_ids(row, lane * SB, n, i) : make_int4(i, i, i, i);
+        for (int b0 = lane * SB; b0 < n; b0 += step) {
+            const int js[SB] = {jn.x, jn.y, jn.z, jn.w};
+            double4 pj[kQ ? 1 : SB];
+            uint4 qj[kQ ? SB : 1];
+#pragma unroll
+            for (int s = 0; s < SB; ++s) {   // all gathers in flight together
+                if constexpr (kQ) qj[s] = a.Q[js[s]];
+                else pj[s] = a.P[js[s]];
+            }
+            if (b0 + step < n) jn = row_ids(row, b0 + step, n, i);   // next block's ids, one iteration ahead
+            real r[SB], t[SB];
+            int m[SB];
+            bool in[SB];
+#pragma unroll
+            for (int s = 0; s < SB; ++s) {
+                real rx, ry, rz;
+                if constexpr (kQ) {
+                    rx = (real)(int)(qi.x - qj[s].x) * qsx;
+                    ry = (real)(int)(qi.y - qj[s].y) * qsy;
+                    rz = (real)(int)(qi.z - qj[s].z) * qsz;
+                } else {
+                    const double3 d = sep(R, pi, pj[s]);
+                    rx = (real)d.x;
+                    ry = (real)d.y;
+                    rz = (real)d.z;
+                }
+                const real r2 = rx * rx + ry * ry + rz * rz;
+                in[s] = (b0 + s < n) && r2 < rc2;
+                real ir;
+                Root<real>::of(r2, r[s], ir);
+                m[s] = interval<real>(in[s] ? r[s] : (real)0, inv_h, nr, t[s]);
+            }
             real part = (real)0;
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
-                const int q = b0 + s;
-                if (q < n) {
-                    const double3 d = sep(R, pi, a.P[row[q]]);
-                    const real rx = (real)d.x, ry = (real)d.y, rz = (real)d.z;
-                    const real r2 = rx * rx + ry * ry + rz * rz;
-                    if (r2 < rc2) {
-                        real t;
-                        const int m = interval<real>(sqrt(r2), inv_h, nr, t);
-                        if constexpr (kLds) {
-                            const float4 c = lds_tab[m];
-                            part += c.x + t * (c.y + t * (c.z + t * c.w));
-                        } else {
-                            const auto c = Tab<real>::ld4(a.tab.rho, m);
-                            part += c.x + t * (c.y + t * (c.z + t * c.w));
-                        }
-                    }
+                real v;
+                if constexpr (kLds) {
+                    const float4 c = lds_tab[m[s]];
+                    v = c.x + t[s] * (c.y + t[s] * (c.z + t[s] * c.w));
+                } else {
+                    const auto c = Tab<real>::ld4(a.tab.rho, m[s]);
+                    v = c.x + t[s] * (c.y + t[s] * (c.z + t[s] * c.w));
                 }
+                part += in[s] ? v : (real)0;
             }
             acc += Acc<real>::q(part);
         }
@@ -443,7 +588,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         const auto c = Tab<real>::ld4(a.tab.F, m);
         const real F = c.x + t * (c.y + t * (c.z + t * c.w));
         const real Fp = (c.y + t * ((real)2 * c.z + (real)3 * t * c.w)) * (real)a.tab.inv_h_rho;
-        a.P[i].w = (double)Fp;
+        if constexpr (kQ) a.Q[i].w = __float_as_uint((float)Fp);
+        else a.P[i].w = (double)Fp;
         a.e_emb[i] = (double)F;
         if (rho > a.tab.rho_max) atomicOr(a.status, ST_TABLE_RANGE);
         if (!isfinite(rho)) atomicOr(a.status, ST_NONFINITE);
@@ -462,6 +608,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         if (a.fix_com)
             replica_reduce<3>(z, a.noise_part, a.cnt_density + tl.rep, R, tl.idx, a.noise_sum + 3 * tl.rep, sh);
     }
+    }   // tiles
 }
 
 // --------------------------------------------------------------------------
@@ -487,64 +634,91 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     extern __shared__ float4 lds_tab[];
     __shared__ double sh[16 * 2];
     constexpr bool kLds = sizeof(real) == 4;
-    const Tile tl = a.tiles[blockIdx.x];
-    if (tl.count == 0) return;
+    constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
+    const int N = a.N;
+    const int64_t it = a.step_kernel ? *a.iter : 0;
+    const int nr = a.tab.n_r;
+    if (kLds && a.has_eam) {   // table staged once per block; blocks then stride over tiles
+        const float4* g = (const float4*)a.tab.pair;
+        for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
+        __syncthreads();
+    }
+    for (int tix = blockIdx.x; tix < a.n_grid; tix += gridDim.x) {
+    const Tile tl = a.tiles[tix];
+    if (tl.count == 0) continue;   // padding tile (uniform in the block)
     const RepDesc& R = a.reps[tl.rep];
     const int lane = threadIdx.x % T;
     const int la = threadIdx.x / T;
     const bool valid = la < tl.count;
     const int i = tl.first + (valid ? la : 0);
-    const int N = a.N;
-    const int64_t it = a.step_kernel ? *a.iter : 0;
-    const int nr = a.tab.n_r;
-
-    if (kLds && a.has_eam) {
-        const float4* g = (const float4*)a.tab.pair;
-        for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
-        __syncthreads();
-    }
 
     const double4 pi = a.P[i];
+    const uint4 qi = kQ ? a.Q[i] : make_uint4(0u, 0u, 0u, 0u);
+    const float qsx = (float)(R.L[0] * 2.3283064365386963e-10), qsy = (float)(R.L[1] * 2.3283064365386963e-10),
+                qsz = (float)(R.L[2] * 2.3283064365386963e-10);
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, ep = 0.0;
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
         const int32_t* row = a.nbr + (size_t)i * a.cap;
-        const real Fpi = (real)pi.w;
+        const real Fpi = kQ ? (real)__uint_as_float(qi.w) : (real)pi.w;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        for (int b0 = lane * SB; b0 < n; b0 += T * SB) {
+        const int step = T * SB;
+        int4 jn = lane * SB < n ? row_ids(row, lane * SB, n, i) : make_int4(i, i, i, i);
+        for (int b0 = lane * SB; b0 < n; b0 += step) {
+            const int js[SB] = {jn.x, jn.y, jn.z, jn.w};
+            double4 pj[kQ ? 1 : SB];
+            uint4 qj[kQ ? SB : 1];
+#pragma unroll
+            for (int s = 0; s < SB; ++s) {   // all gathers in flight together
+                if constexpr (kQ) qj[s] = a.Q[js[s]];
+                else pj[s] = a.P[js[s]];
+            }
+            if (b0 + step < n) jn = row_ids(row, b0 + step, n, i);   // next block's ids, one iteration ahead
+            real rx[SB], ry[SB], rz[SB], ir[SB], t[SB], fpj[SB];
+            int m[SB];
+            bool in[SB];
+#pragma unroll
+            for (int s = 0; s < SB; ++s) {
+                if constexpr (kQ) {
+                    rx[s] = (real)(int)(qi.x - qj[s].x) * qsx;
+                    ry[s] = (real)(int)(qi.y - qj[s].y) * qsy;
+                    rz[s] = (real)(int)(qi.z - qj[s].z) * qsz;
+                    fpj[s] = (real)__uint_as_float(qj[s].w);
+                } else {
+                    const double3 d = sep(R, pi, pj[s]);
+                    rx[s] = (real)d.x;
+                    ry[s] = (real)d.y;
+                    rz[s] = (real)d.z;
+                    fpj[s] = (real)pj[s].w;
+                }
+                const real r2 = rx[s] * rx[s] + ry[s] * ry[s] + rz[s] * rz[s];
+                in[s] = (b0 + s < n) && r2 < rc2;
+                real r;
+                Root<real>::of(in[s] ? r2 : (real)1, r, ir[s]);
+                m[s] = interval<real>(in[s] ? r : (real)0, inv_h, nr, t[s]);
+            }
             real p0 = (real)0, p1 = (real)0, p2 = (real)0, pe = (real)0;
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
-                const int q = b0 + s;
-                if (q < n) {
-                    const double4 pj = a.P[row[q]];
-                    const double3 d = sep(R, pi, pj);
-                    const real rx = (real)d.x, ry = (real)d.y, rz = (real)d.z;
-                    const real r2 = rx * rx + ry * ry + rz * rz;
-                    if (r2 < rc2) {
-                        const real r = sqrt(r2);
-                        real t;
-                        const int m = interval<real>(r, inv_h, nr, t);
-                        real ua, ub, uc, ud, wb, wc, wd;
-                        if constexpr (kLds) {
-                            const float4 u = lds_tab[2 * m], w = lds_tab[2 * m + 1];
-                            ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
-                        } else {
-                            decltype(Tab<real>::ld4(a.tab.rho, 0)) u, w;
-                            Tab<real>::ld8(a.tab.pair, m, u, w);
-                            ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
-                        }
-                        const real phi = ua + t * (ub + t * (uc + t * ud));
-                        const real dphi = (ub + t * ((real)2 * uc + (real)3 * t * ud)) * inv_h;
-                        const real drho = wb + t * (wc + t * wd);
-                        const real g = dphi + (Fpi + (real)pj.w) * drho;   // dU/dr_ij
-                        const real s_ = -g / r;
-                        p0 += s_ * rx;
-                        p1 += s_ * ry;
-                        p2 += s_ * rz;
-                        pe += phi;
-                    }
+                real ua, ub, uc, ud, wb, wc, wd;
+                if constexpr (kLds) {
+                    const float4 u = lds_tab[2 * m[s]], w = lds_tab[2 * m[s] + 1];
+                    ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
+                } else {
+                    decltype(Tab<real>::ld4(a.tab.rho, 0)) u, w;
+                    Tab<real>::ld8(a.tab.pair, m[s], u, w);
+                    ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
                 }
+                const real ts = t[s];
+                const real phi = ua + ts * (ub + ts * (uc + ts * ud));
+                const real dphi = (ub + ts * ((real)2 * uc + (real)3 * ts * ud)) * inv_h;
+                const real drho = wb + ts * (wc + ts * wd);
+                const real g = dphi + (Fpi + fpj[s]) * drho;   // dU/dr_ij
+                const real sc = in[s] ? -g * ir[s] : (real)0;
+                p0 += sc * rx[s];
+                p1 += sc * ry[s];
+                p2 += sc * rz[s];
+                pe += in[s] ? phi : (real)0;
             }
             f0 += Acc<real>::q(p0);
             f1 += Acc<real>::q(p1);
@@ -598,6 +772,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 if (r0 * r0 + r1 * r1 + r2 * r2 > a.half_skin2) a.rebuild[tl.rep] = 1;
             }
             a.Pn[i] = make_double4(x[0], x[1], x[2], 0.0);
+            a.Qn[i] = box_codes(R, x[0], x[1], x[2], 0u);   // list builder uses box coordinates in both forms
             a.v[i] = v[0];
             a.v[N + i] = v[1];
             a.v[2 * N + i] = v[2];
@@ -635,6 +810,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
             *a.cnt_all = 0u;
         }
     }
+    }   // tiles
 }
 
 // --------------------------------------------------------------------------
@@ -676,10 +852,11 @@ __global__ void k_sub_mean_v(StepArgs a)
 // --------------------------------------------------------------------------
 static int grid1(int n, int b) { return (n + b - 1) / b; }
 
-int launch_pack(double4* P, const double* x, int N, hipStream_t s)
+int launch_pack(double4* P, uint4* Q, const double* x, const int32_t* rep_of, const RepDesc* reps, int N,
+                hipStream_t s)
 {
     if (N <= 0) return 0;
-    hipLaunchKernelGGL(k_pack, dim3(grid1(N, 256)), dim3(256), 0, s, P, x, N);
+    hipLaunchKernelGGL(k_pack, dim3(grid1(N, 256)), dim3(256), 0, s, P, Q, x, rep_of, reps, N);
     return (int)hipGetLastError();
 }
 
@@ -707,15 +884,9 @@ int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s
         hipLaunchKernelGGL(k_cellsort, dim3(a.n_cells < 4096 ? a.n_cells : 4096), dim3(64), p2 * sizeof(int32_t), s,
                            a);
     }
-    dim3 g(a.n_grid), b(block);
-    switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_list<1>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_list<2>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_list<4>), g, b, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_list<8>), g, b, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_list<16>), g, b, 0, s, a); break;
-    default: return (int)hipErrorInvalidValue;
-    }
+    (void)lanes;
+    (void)block;
+    hipLaunchKernelGGL(k_list, dim3(kListGrid), dim3(kListBlock), 0, s, a, a.n_rep);
     return (int)hipGetLastError();
 }
 
@@ -725,10 +896,15 @@ static size_t lds_bytes(const StepArgs& a, int tables)
     return (sizeof(real) == 4 && a.has_eam) ? (size_t)tables * (a.tab.n_r - 1) * sizeof(float4) : 0;
 }
 
+static int pair_grid(const StepArgs& a)
+{
+    return (a.grid_blocks > 0 && a.grid_blocks < a.n_grid) ? a.grid_blocks : a.n_grid;
+}
+
 template <typename real>
 static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t s)
 {
-    dim3 g(a.n_grid), b(block);
+    dim3 g(pair_grid(a)), b(block);
     const size_t sh = lds_bytes<real>(a, 1);
     switch (lanes) {
     case 1: hipLaunchKernelGGL((k_density<real, 1>), g, b, sh, s, a); break;
@@ -744,7 +920,7 @@ static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t
 template <typename real>
 static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s)
 {
-    dim3 g(a.n_grid), b(block);
+    dim3 g(pair_grid(a)), b(block);
     const size_t sh = lds_bytes<real>(a, 2);
     switch (lanes) {
     case 1: hipLaunchKernelGGL((k_force<real, 1>), g, b, sh, s, a); break;

@@ -62,12 +62,15 @@ def lib():
         "eamfe_set_stream": (i32, [vp, vp]),
         "eamfe_set_launch": (i32, [vp, i32, i32]),
         "eamfe_get_launch": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "eamfe_set_grid": (i32, [vp, i32]),
+        "eamfe_get_grid": (i32, [vp, C.POINTER(i32)]),
         "eamfe_set_xcd_affinity": (i32, [vp, i32]),
         "eamfe_check": (i32, [vp]),
         "eamfe_set_kernel_timing": (i32, [vp, i32]),
         "eamfe_autotune": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, i32, C.POINTER(i32), C.POINTER(i32), _dp]),
         "eamfe_kernel_timing": (i32, [vp, _dp, C.POINTER(i64)]),
         "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
+        "eamfe_copy_lists": (i32, [vp, vp, vp, i32]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
         "neigh_build": (i32, [vp, vp, dbl, i32]),
@@ -208,6 +211,14 @@ class Context:
         self._c(self._lib.eamfe_get_launch(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def set_grid(self, blocks):
+        self._c(self._lib.eamfe_set_grid(self._h, int(blocks)))
+
+    def get_grid(self):
+        g = C.c_int()
+        self._c(self._lib.eamfe_get_grid(self._h, C.byref(g)))
+        return g.value
+
     def set_xcd_affinity(self, on: bool):
         self._c(self._lib.eamfe_set_xcd_affinity(self._h, int(bool(on))))
 
@@ -229,6 +240,15 @@ class Context:
         n = (C.c_int64 * 3)()
         self._c(self._lib.eamfe_kernel_timing(self._h, ms.ctypes.data_as(_dp), n))
         return {k: (float(ms[q]), int(n[q])) for q, k in enumerate(("density", "force", "lists"))}
+
+    def copy_lists(self):
+        """(row lengths [N], rows [N, cap]) as device int32 tensors."""
+        import torch
+        _, _, cap = self.list_stats()
+        nnb = torch.zeros(self.N, dtype=torch.int32, device="cuda")
+        nbr = torch.zeros(self.N, cap, dtype=torch.int32, device="cuda")
+        self._c(self._lib.eamfe_copy_lists(self._h, C.c_void_p(nnb.data_ptr()), C.c_void_p(nbr.data_ptr()), cap))
+        return nnb, nbr
 
     def list_stats(self):
         m, mx, cap = C.c_double(), C.c_int(), C.c_int()

@@ -281,3 +281,36 @@ def test_overflow_replay_is_the_same_trajectory(prec):
     assert out[0][4][2] >= out[0][4][1]
     for a, b in zip(out[0][:3], out[1][:3]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("shift", [0.0, 13.7])
+def test_neighbour_rows_match_brute_force(shift):
+    """Every row holds exactly the atoms within r_cut + skin (FP64 brute force),
+    up to the candidate test's widening margin, with no duplicates and no self."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()
+    ctx, x0, arrs = make_ctx(reps, FP32, 8, 256)
+    x = I.displaced(arrs["x0"], 0.3, seed=5) + shift
+    xd = E.to_soa(x)
+    skin = 0.3
+    ctx.neigh_build(xd, skin, 0)
+    nnb, nbr = ctx.copy_lists()
+    nnb, nbr = nnb.cpu().numpy(), nbr.cpu().numpy()
+    rl = I.R_CUT + skin
+    for r, rep in enumerate(reps):
+        o0, o1 = ctx.offsets[r], ctx.offsets[r + 1]
+        xr = x[o0:o1]
+        d = xr[:, None, :] - xr[None, :, :]
+        d -= rep.box * np.rint(d / rep.box)
+        dist = np.sqrt((d ** 2).sum(-1))
+        np.fill_diagonal(dist, np.inf)
+        for il in range(0, o1 - o0, 7):
+            row = nbr[o0 + il, : nnb[o0 + il]] - o0
+            assert len(set(row.tolist())) == len(row)
+            assert il not in set(row.tolist())
+            need = set(np.nonzero(dist[il] < rl - 1e-9)[0].tolist())
+            assert need <= set(row.tolist()), (r, il)
+            assert np.all(dist[il, row] < rl + 2e-3)
+    ctx.close()
