@@ -240,16 +240,32 @@ int eamfe_get_work(eamfe_ctx* ctx, double* W_host);
 
 /* ---- differentiation --------------------------------------------------- */
 
-/* dU_EAM/dtheta at x for every replica, theta = the knot values of
- * (phi, rho, F) given to eam_setup (n_r == n_rho required):
- *   dtheta_dev[r][0][k] += scale * dU_r/dphi_k,
- *   dtheta_dev[r][1][k] += scale * dU_r/drho_k,
- *   dtheta_dev[r][2][k] += scale * dU_r/dF_k,
- * device float64 [n_rep][3][n_r], accumulated (the caller zeroes it).  By
- * Eq. dFdL with theta in the role of lambda, averaging this over the H0
- * ensemble gives dF/dtheta.  Per-bin sums are accumulated in fixed point so
- * the result is deterministic.  Synchronises. */
-int eamfe_adjoint_theta(eamfe_ctx* ctx, const double* x_dev, double scale, double* dtheta_dev);
+/* dU_EAM/dtheta at x, theta = the knot values (phi_k, rho_k, F_k) given to
+ * eam_setup (n_r == n_rho required).  U is linear in the phi and F knots and,
+ * through rho_i, depends on the rho knots; the kernels bin (1, t, t^2, t^3)
+ * of every spline evaluation per interval in 2^-32 fixed point
+ * (deterministic), then apply the transpose of the natural-spline map.
+ * Pair geometry and spline coordinates are float64 in both numeric forms
+ * (in EAMFE_FP32 from the box coordinates); F'(rho_i) and rho_i come from
+ * the form's density pass.
+ * By Eq. dFdL with theta in the role of lambda, the average of this over the
+ * H0 ensemble is dF0/dtheta.
+ *   reduce == 0: dtheta_dev[r][f][k] += w[r] dU_r/dtheta_{f,k}   (device, [n_rep][3][n_r])
+ *   reduce != 0: dtheta_dev[f][k]    += sum_r w[r] dU_r/dtheta_{f,k}  (device, [3][n_r])
+ * f = 0 phi, 1 rho, 2 F.  w_host: host [n_rep] weights or NULL (all 1).
+ * The caller zeroes dtheta_dev.  Synchronises. */
+int eamfe_adjoint_theta(eamfe_ctx* ctx, const double* x_dev, const double* w_host, int reduce,
+                        double* dtheta_dev);
+
+/* Sample dU/dtheta inside run_switching at every `every`-th step whose
+ * lambda equals the protocol's start value (the H0 ensemble: lambda = 0 for
+ * FL/HH, 1 for RS), accumulating as eamfe_adjoint_theta would into
+ * dtheta_dev (device, kept by the caller until sampling is switched off with
+ * every = 0).  Resets the sample count. */
+int eamfe_set_adjoint_sampling(eamfe_ctx* ctx, int every, const double* w_host, int reduce, double* dtheta_dev);
+
+/* Samples accumulated since the last eamfe_set_adjoint_sampling. */
+int eamfe_adjoint_samples(const eamfe_ctx* ctx, int64_t* n);
 
 /* ---- estimators (host, float64) ---------------------------------------- */
 

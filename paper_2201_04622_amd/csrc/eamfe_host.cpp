@@ -73,8 +73,14 @@ struct eamfe_ctx {
     int64_t replays = 0;
     DevBuf snap_P, snap_Q, snap_v, snap_w;
 
-    // folded single-precision positions for the list builder
-    DevBuf Pf_d;
+    // adjoint: densities, fixed-point bins, finish scratch, weights
+    DevBuf rho_d, bins_d, adj_scratch_d, adj_w_d;
+    // sampling of dU/dtheta inside run_switching (0 = off)
+    int adj_every = 0;
+    int adj_reduce = 0;
+    double* adj_out = nullptr;
+    std::vector<double> adj_w;
+    int64_t adj_samples = 0;
 
     // lambda table
     DevBuf lam_d;
@@ -531,6 +537,45 @@ int pack(eamfe_ctx* c, const double* x)
     return EAMFE_OK;
 }
 
+// dU/dtheta at the packed positions P (density pass already run with
+// rho_out, so F' and rho are current): bins -> knot gradients into out.
+int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce, double* out)
+{
+    if (c->n_r != c->n_rho) return fail(c, EAMFE_EINVAL, "adjoint: phi/rho and F tables must have equal knot counts");
+    const int nb = std::max(c->n_r, c->n_rho) - 1;
+    const size_t bins = (size_t)c->n_rep * 3 * nb * 4 * sizeof(unsigned long long);
+    OK(ensure(c, c->bins_d, bins));
+    OK(ensure(c, c->adj_scratch_d, (size_t)c->n_rep * 3 * 2 * (nb + 1) * sizeof(double)));
+    HIPCHK(c, hipMemsetAsync(c->bins_d.p, 0, bins, c->stream));
+    AdjointArgs a{};
+    a.reps = (const RepDesc*)c->reps_d.p;
+    a.P = P;
+    a.Q = Q_of(c, P);
+    a.nbr = (const int32_t*)c->nbr_d.p;
+    a.nnb = (const int32_t*)c->nnb_d.p;
+    a.cap = c->cap;
+    a.rho = (const double*)c->rho_d.p;
+    a.bins = (unsigned long long*)c->bins_d.p;
+    a.nb = nb;
+    a.tab = tables_of(c);
+    a.N = c->N;
+    a.n_rep = c->n_rep;
+    a.tile_atoms = c->block / c->lanes;
+    a.n_units = c->n_tiles;
+    const int grid = std::max(1, std::min(c->n_tiles, 2 * c->n_cu));
+    LCHK(c, launch_adjoint(a, c->precision, grid, c->stream));
+    const double* wd = nullptr;
+    if (w_host) {
+        OK(ensure(c, c->adj_w_d, (size_t)c->n_rep * sizeof(double)));
+        HIPCHK(c, hipMemcpyAsync(c->adj_w_d.p, w_host, (size_t)c->n_rep * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));   // the host array may go away
+        wd = (const double*)c->adj_w_d.p;
+    }
+    LCHK(c, launch_adjoint_finish(a, wd, reduce, out, (double*)c->adj_scratch_d.p, c->stream));
+    return EAMFE_OK;
+}
+
 // Record a timing event (kind: 0 density, 1 force, 2 lists; end = 0 start, 1 stop).
 int mark(eamfe_ctx* c, int kind, int end)
 {
@@ -568,9 +613,17 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
         a.Pn = nxt;
         a.Q = Q_of(c, cur);
         a.Qn = Q_of(c, nxt);
+        // dU/dtheta samples in the H0 ensemble (lambda at its start value)
+        const bool sample = has_eam && c->adj_every > 0 && it < it_last && it % c->adj_every == 0 &&
+                            c->lam_valid && c->lam_h[it] == c->lam_h[0];
+        a.rho_out = sample ? (double*)c->rho_d.p : nullptr;
         OK(mark(c, 0, 0));
         LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
         OK(mark(c, 0, 1));
+        if (sample) {
+            OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out));
+            ++c->adj_samples;
+        }
         OK(mark(c, 1, 0));
         LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
         OK(mark(c, 1, 1));
@@ -646,7 +699,10 @@ int eamfe_destroy(eamfe_ctx* c)
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
-    release(c->Pf_d);
+    release(c->rho_d);
+    release(c->bins_d);
+    release(c->adj_scratch_d);
+    release(c->adj_w_d);
     release(c->tune_x);
     release(c->tune_v);
     release(c->tune_w);
@@ -798,7 +854,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->Pa_d, (size_t)N * sizeof(double4)));
     OK(ensure(c, c->Qa_d, (size_t)N * sizeof(uint4)));
     OK(ensure(c, c->Qb_d, (size_t)N * sizeof(uint4)));
-    OK(ensure(c, c->Pf_d, (size_t)N * sizeof(float4)));
+    OK(ensure(c, c->rho_d, (size_t)N * sizeof(double)));
     OK(ensure(c, c->Pb_d, (size_t)N * sizeof(double4)));
     OK(ensure(c, c->xi_d, v3));
     OK(ensure(c, c->e_emb_d, (size_t)N * sizeof(double)));
@@ -1058,9 +1114,43 @@ int eamfe_get_work(eamfe_ctx* c, double* W)
     return EAMFE_OK;
 }
 
-int eamfe_adjoint_theta(eamfe_ctx* c, const double*, double, double*)
+int eamfe_adjoint_theta(eamfe_ctx* c, const double* x, const double* w_host, int reduce, double* dtheta)
 {
-    return fail(c, EAMFE_ESTATE, "adjoint not built yet");
+    if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!x || !dtheta) return fail(c, EAMFE_EINVAL, "adjoint_theta: null argument");
+    (void)hipSetDevice(c->device);
+    OK(pack(c, x));
+    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
+    NeighArgs na = neigh_args(c, PA(c));
+    LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+    StepArgs a = step_args(c);
+    a.P = PA(c);
+    a.Q = QA(c);
+    a.has_eam = 1;
+    a.step_kernel = 0;
+    a.rho_out = (double*)c->rho_d.p;
+    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+    OK(adjoint_at(c, PA(c), w_host, reduce, dtheta));
+    return read_status(c);
+}
+
+int eamfe_set_adjoint_sampling(eamfe_ctx* c, int every, const double* w_host, int reduce, double* dtheta)
+{
+    if (!c || every < 0 || (every > 0 && !dtheta)) return EAMFE_EINVAL;
+    c->adj_every = every;
+    c->adj_reduce = reduce ? 1 : 0;
+    c->adj_out = dtheta;
+    if (w_host && c->n_rep) c->adj_w.assign(w_host, w_host + c->n_rep);
+    else c->adj_w.clear();
+    c->adj_samples = 0;
+    return EAMFE_OK;
+}
+
+int eamfe_adjoint_samples(const eamfe_ctx* c, int64_t* n)
+{
+    if (!c || !n) return EAMFE_EINVAL;
+    *n = c->adj_samples;
+    return EAMFE_OK;
 }
 
 int eamfe_set_kernel_timing(eamfe_ctx* c, int on)

@@ -125,6 +125,7 @@ struct StepArgs {
     double* W_state;        // [n_rep]
     double* f_out;          // SoA [3][N] EAM forces or null
     double* e_atom_out;     // [N] per-atom EAM energy or null
+    double* rho_out;        // [N] densities rho_i or null
     Tables tab;
     int N;
     int mode;
@@ -139,18 +140,24 @@ struct StepArgs {
     double half_skin2;
 };
 
+// Knot gradient dU/dtheta.  Bins hold per-interval sums of (1, t, t^2, t^3)
+// times the weight of each evaluation, in 2^-32 fixed point (two's
+// complement in 64 bits), so accumulation order does not matter.
 struct AdjointArgs {
-    const Tile* tiles;
     const RepDesc* reps;
-    const double4* P;         // positions, .w = F'(rho_i)
+    const double4* P;           // positions (FP64 form), .w = F'(rho_i)
+    const uint4* Q;             // box coordinates (FP32 form), .w = F'(rho_i) bits
     const int32_t* nbr;
     const int32_t* nnb;
     int cap;
-    const double* rho;        // [N] densities (float64)
-    unsigned long long* bins; // [n_rep][3][n-1][4] fixed-point sums (2^-32 quanta, two's complement)
+    const double* rho;          // [N] densities from the density pass
+    unsigned long long* bins;   // [n_rep][3][nb][4], nb = max(n_r, n_rho) - 1; functions (phi, rho, F)
+    int nb;
     Tables tab;
     int N;
-    int n_tiles;
+    int n_rep;
+    int tile_atoms;             // atoms per work unit
+    int n_units;                // total work units (replica-major)
 };
 
 // Launchers (eamfe_kernels.hip).  Each returns a hipError_t as int.
@@ -162,9 +169,12 @@ int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s
 int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);
-int launch_adjoint(const AdjointArgs& a, const StepArgs& d, int precision, int lanes, int block, hipStream_t s);
-int launch_adjoint_finish(const unsigned long long* bins, int n_rep, int n, double scale, double* coef_grad,
+int launch_adjoint(const AdjointArgs& a, int precision, int grid, hipStream_t s);
+// Coefficient-bin sums -> knot gradients.  out[r][f][k] += w[r] dU_r/dtheta_{f,k}
+// (per replica), or out[f][k] += sum_r w[r] dU_r/dtheta_{f,k} when reduce;
+// scratch: device doubles, >= 3 * 3 * nmax per output row.
+int launch_adjoint_finish(const AdjointArgs& a, const double* w, int reduce, double* out, double* scratch,
                           hipStream_t s);
-int launch_rho_dump(const StepArgs& a, double* rho_out, int precision, int lanes, int block, hipStream_t s);
+int launch_rho(const StepArgs& a, double* rho_out, int precision, int lanes, int block, hipStream_t s);
 
 }  // namespace eamfe

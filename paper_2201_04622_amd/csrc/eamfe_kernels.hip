@@ -591,6 +591,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         if constexpr (kQ) a.Q[i].w = __float_as_uint((float)Fp);
         else a.P[i].w = (double)Fp;
         a.e_emb[i] = (double)F;
+        if (a.rho_out) a.rho_out[i] = rho;
         if (rho > a.tab.rho_max) atomicOr(a.status, ST_TABLE_RANGE);
         if (!isfinite(rho)) atomicOr(a.status, ST_NONFINITE);
     }
@@ -952,11 +953,195 @@ int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_
     return (int)hipGetLastError();
 }
 
-int launch_adjoint(const AdjointArgs&, const StepArgs&, int, int, int, hipStream_t) { return (int)hipErrorNotSupported; }
-int launch_adjoint_finish(const unsigned long long*, int, int, double, double*, hipStream_t)
+// --------------------------------------------------------------------------
+// Knot gradient dU/dtheta (theta = knot values of phi, rho, F).
+// U is linear in the interval coefficients of phi and F, and rho_i is linear
+// in those of rho, so with B(t) = (1, t, t^2, t^3) of every evaluation:
+//   dU/dc_phi[m] = 1/2 sum over ordered pairs in interval m of B
+//   dU/dc_rho[m] = sum_i F'(rho_i) sum_j over pairs in interval m of B
+//   dU/dc_F[m]   = sum over atoms with rho_i in interval m of B
+// Each block accumulates one function's bins in an LDS histogram (2^-32
+// fixed point, 64-bit) over a contiguous range of work units and adds it to
+// the replica's global bins when the replica changes.
+// --------------------------------------------------------------------------
+constexpr int kAdjBlock = 256;
+constexpr int kAdjLanes = 8;
+
+__device__ __forceinline__ unsigned long long fix64(double v)
 {
-    return (int)hipErrorNotSupported;
+    return (unsigned long long)__double2ll_rn(v * kFixScale);
 }
-int launch_rho_dump(const StepArgs&, double*, int, int, int, hipStream_t) { return (int)hipErrorNotSupported; }
+
+template <typename real, int WHICH>
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint(AdjointArgs a)
+{
+    extern __shared__ unsigned long long hist[];
+    constexpr bool kQ = sizeof(real) == 4;
+    const int nint = (WHICH == 2 ? a.tab.n_rho : a.tab.n_r) - 1;
+    for (int k = threadIdx.x; k < 4 * nint; k += blockDim.x) hist[k] = 0ull;
+    __syncthreads();
+    const int per = (a.n_units + gridDim.x - 1) / gridDim.x;
+    const int u0 = blockIdx.x * per, u1 = min(a.n_units, u0 + per);
+    int rep = -1;
+    auto flush = [&]() {
+        __syncthreads();
+        unsigned long long* g = a.bins + ((size_t)rep * 3 + WHICH) * (size_t)a.nb * 4;
+        for (int k = threadIdx.x; k < 4 * nint; k += blockDim.x) {
+            const unsigned long long v = hist[k];
+            if (v) {
+                atomicAdd(&g[k], v);
+                hist[k] = 0ull;
+            }
+        }
+        __syncthreads();
+    };
+    const int A = a.tile_atoms;
+    const int lane = threadIdx.x % kAdjLanes;
+    const int slot = threadIdx.x / kAdjLanes;
+    constexpr int per_pass = kAdjBlock / kAdjLanes;
+    for (int u = u0; u < u1; ++u) {
+        int r = rep < 0 ? 0 : rep;   // replica of unit u (units are replica-major)
+        while (u >= a.reps[r].tile_base + a.reps[r].n_tiles) ++r;
+        if (r != rep) {
+            if (rep >= 0) flush();
+            rep = r;
+        }
+        const RepDesc& R = a.reps[r];
+        const int first = R.off + (u - R.tile_base) * A;
+        const int count = min(A, R.n - (u - R.tile_base) * A);
+        for (int c0 = 0; c0 < count; c0 += per_pass) {
+            const int la = c0 + slot;
+            if (la >= count) continue;
+            const int i = first + la;
+            if constexpr (WHICH == 2) {
+                if (lane == 0) {
+                    double td;
+                    const int m = interval<double>(a.rho[i], a.tab.inv_h_rho, a.tab.n_rho, td);
+                    atomicAdd(&hist[4 * m + 0], fix64(1.0));
+                    atomicAdd(&hist[4 * m + 1], fix64(td));
+                    atomicAdd(&hist[4 * m + 2], fix64(td * td));
+                    atomicAdd(&hist[4 * m + 3], fix64(td * td * td));
+                }
+            } else {
+                const double4 pi = a.P[i];
+                const uint4 qi = kQ ? a.Q[i] : make_uint4(0u, 0u, 0u, 0u);
+                const double wgt = WHICH == 0 ? 0.5 : (kQ ? (double)__uint_as_float(qi.w) : pi.w);
+                const int n = a.nnb[i];
+                const int32_t* row = a.nbr + (size_t)i * a.cap;
+                for (int q = lane; q < n; q += kAdjLanes) {
+                    // geometry in float64 in both forms: the basis weights B(t) vary on the
+                    // scale of one interval, so t needs more than single precision
+                    const int j = row[q];
+                    double dx, dy, dz;
+                    if constexpr (kQ) {
+                        const uint4 qj = a.Q[j];
+                        dx = (double)(int)(qi.x - qj.x) * (R.L[0] * 2.3283064365386963e-10);
+                        dy = (double)(int)(qi.y - qj.y) * (R.L[1] * 2.3283064365386963e-10);
+                        dz = (double)(int)(qi.z - qj.z) * (R.L[2] * 2.3283064365386963e-10);
+                    } else {
+                        const double3 d = sep(R, pi, a.P[j]);
+                        dx = d.x;
+                        dy = d.y;
+                        dz = d.z;
+                    }
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < a.tab.rc2) {
+                        double td;
+                        const int m = interval<double>(sqrt(r2), a.tab.inv_h_r, a.tab.n_r, td);
+                        atomicAdd(&hist[4 * m + 0], fix64(wgt));
+                        atomicAdd(&hist[4 * m + 1], fix64(wgt * td));
+                        atomicAdd(&hist[4 * m + 2], fix64(wgt * td * td));
+                        atomicAdd(&hist[4 * m + 3], fix64(wgt * td * td * td));
+                    }
+                }
+            }
+        }
+    }
+    if (rep >= 0) flush();
+}
+
+// One thread per (output row, function): fixed-point bins -> coefficient
+// gradients g = (g_a, g_b, g_c, d_d) per interval -> knot gradient through the
+// transpose of the natural-spline map.  With y the knots and M the second
+// derivatives (M_0 = M_{n-1} = 0, K M = r, K = tridiag(1, 4, 1),
+// r_l = 6 (y_{l+1} - 2 y_l + y_{l-1}) / h^2):
+//   a_m = y_m, b_m = y_{m+1} - y_m - h^2 (2 M_m + M_{m+1})/6,
+//   c_m = h^2 M_m / 2, d_m = h^2 (M_{m+1} - M_m)/6,
+// so dU/dy = direct terms + (dr/dy)^T K^{-1} (dU/dM).
+__global__ void k_adjoint_finish(AdjointArgs a, const double* w, int reduce, double* out, double* scratch)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rows = reduce ? 1 : a.n_rep;
+    if (t >= rows * 3) return;
+    const int row = t / 3, f = t % 3;
+    const int n = f == 2 ? a.tab.n_rho : a.tab.n_r;
+    const double h = f == 2 ? 1.0 / a.tab.inv_h_rho : 1.0 / a.tab.inv_h_r;
+    const int nmax = a.nb + 1;
+    double* gM = scratch + (size_t)t * 2 * nmax;
+    double* dg = gM + nmax;
+    double* o = out + ((size_t)row * 3 + f) * nmax;
+    const int r0 = reduce ? 0 : row, r1 = reduce ? a.n_rep : row + 1;
+    auto g = [&](int m, int q) {   // coefficient gradient, fixed replica order
+        double s = 0.0;
+        for (int r = r0; r < r1; ++r) {
+            const long long v = (long long)a.bins[(((size_t)r * 3 + f) * a.nb + m) * 4 + q];
+            s += (w ? w[r] : 1.0) * ((double)v * kFixInv);
+        }
+        return s;
+    };
+    const double h2 = h * h;
+    // dU/dM for interior knots, and the direct y terms
+    for (int k = 0; k < n; ++k) {
+        double dy = 0.0, gm = 0.0;
+        if (k <= n - 2) dy += g(k, 0) - g(k, 1);
+        if (k >= 1) dy += g(k - 1, 1);
+        if (k >= 1 && k <= n - 2)
+            gm = h2 / 6.0 * (-2.0 * g(k, 1) - g(k - 1, 1) + 3.0 * g(k, 2) - g(k, 3) + g(k - 1, 3));
+        o[k] += dy;
+        gM[k] = gm;
+    }
+    // solve K z = gM on the interior (Thomas); z overwrites gM
+    dg[1] = 4.0;
+    for (int k = 2; k <= n - 2; ++k) {
+        const double q = 1.0 / dg[k - 1];
+        dg[k] = 4.0 - q;
+        gM[k] -= q * gM[k - 1];
+    }
+    gM[n - 2] /= dg[n - 2];
+    for (int k = n - 3; k >= 1; --k) gM[k] = (gM[k] - gM[k + 1]) / dg[k];
+    gM[0] = 0.0;
+    gM[n - 1] = 0.0;
+    const double s6 = 6.0 / h2;
+    for (int k = 0; k < n; ++k) {
+        double v = -2.0 * gM[k];
+        if (k >= 1) v += gM[k - 1];
+        if (k + 1 <= n - 1) v += gM[k + 1];
+        o[k] += s6 * v;
+    }
+}
+
+template <typename real>
+static int launch_adjoint_t(const AdjointArgs& a, int grid, hipStream_t s)
+{
+    const size_t sh_r = (size_t)(a.tab.n_r - 1) * 4 * sizeof(unsigned long long);
+    const size_t sh_f = (size_t)(a.tab.n_rho - 1) * 4 * sizeof(unsigned long long);
+    hipLaunchKernelGGL((k_adjoint<real, 0>), dim3(grid), dim3(kAdjBlock), sh_r, s, a);
+    hipLaunchKernelGGL((k_adjoint<real, 1>), dim3(grid), dim3(kAdjBlock), sh_r, s, a);
+    hipLaunchKernelGGL((k_adjoint<real, 2>), dim3(grid), dim3(kAdjBlock), sh_f, s, a);
+    return (int)hipGetLastError();
+}
+
+int launch_adjoint(const AdjointArgs& a, int precision, int grid, hipStream_t s)
+{
+    return precision ? launch_adjoint_t<float>(a, grid, s) : launch_adjoint_t<double>(a, grid, s);
+}
+
+int launch_adjoint_finish(const AdjointArgs& a, const double* w, int reduce, double* out, double* scratch,
+                          hipStream_t s)
+{
+    const int threads = (reduce ? 1 : a.n_rep) * 3;
+    hipLaunchKernelGGL(k_adjoint_finish, dim3((threads + 63) / 64), dim3(64), 0, s, a, w, reduce, out, scratch);
+    return (int)hipGetLastError();
+}
 
 }  // namespace eamfe

@@ -82,7 +82,9 @@ def lib():
         "eamfe_get_work": (i32, [vp, _dp]),
         "eamfe_set_chunk": (i32, [vp, i64]),
         "eamfe_replays": (i32, [vp, C.POINTER(i64)]),
-        "eamfe_adjoint_theta": (i32, [vp, vp, dbl, vp]),
+        "eamfe_adjoint_theta": (i32, [vp, vp, _dp, i32, vp]),
+        "eamfe_set_adjoint_sampling": (i32, [vp, i32, _dp, i32, vp]),
+        "eamfe_adjoint_samples": (i32, [vp, C.POINTER(i64)]),
         "eamfe_einstein_free_energy": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fl_free_energy": (i32, [i32, _dp, _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp, _dp]),
@@ -311,5 +313,19 @@ class Context:
         self._c(self._lib.eamfe_get_work(self._h, W.ctypes.data_as(_dp)))
         return W
 
-    def adjoint_theta(self, x, dtheta, scale=1.0):
-        self._c(self._lib.eamfe_adjoint_theta(self._h, _ptr(x), float(scale), _ptr(dtheta)))
+    def adjoint_theta(self, x, dtheta, weights=None, reduce=False):
+        """dtheta (device float64, [n_rep, 3, n] or [3, n] with reduce) += w_r dU_r/dtheta."""
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        self._c(self._lib.eamfe_adjoint_theta(self._h, _ptr(x), None if w is None else w.ctypes.data_as(_dp),
+                                              int(bool(reduce)), _ptr(dtheta)))
+
+    def set_adjoint_sampling(self, every, dtheta=None, weights=None, reduce=False):
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        self._adj_keep = (dtheta, w)
+        self._c(self._lib.eamfe_set_adjoint_sampling(self._h, int(every), None if w is None else w.ctypes.data_as(_dp),
+                                                     int(bool(reduce)), _ptr(dtheta)))
+
+    def adjoint_samples(self):
+        n = C.c_int64()
+        self._c(self._lib.eamfe_adjoint_samples(self._h, C.byref(n)))
+        return n.value
