@@ -128,6 +128,13 @@ int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threa
 int eamfe_set_grid(eamfe_ctx* ctx, int blocks);
 int eamfe_get_grid(const eamfe_ctx* ctx, int* blocks);
 
+/* Replay the steps of run_switching from a captured HIP graph of `iters`
+ * iterations (rounded up to even; 0 = eager launches, the default).  The
+ * first and last iteration of every chunk run eagerly; the graph runs on an
+ * internal default-priority stream ordered after and before the context's
+ * stream with events.  Kernel timing or adjoint sampling switch it off. */
+int eamfe_set_graph(eamfe_ctx* ctx, int iters);
+
 /* 1: place every replica's tiles on one XCD (workgroup id mod 8), balancing
  * atoms across the eight XCDs; 0: replica-major order.  Default 1. */
 int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
@@ -136,9 +143,12 @@ int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
  * (EAMFE_ENEIGH_OVERFLOW ...), clearing it. */
 int eamfe_check(eamfe_ctx* ctx);
 
-/* Time every following kernel launch with HIP events recorded on the
- * context's stream (1) or stop (0); switching resets the accumulators. */
-int eamfe_set_kernel_timing(eamfe_ctx* ctx, int on);
+/* Time the kernel launches of every `stride`-th iteration (global step index
+ * divisible by stride) with HIP events recorded around them on the context's
+ * stream; 0 stops.  An event pair costs about 10 us of stream time, so a
+ * stride of tens leaves the timed work essentially unperturbed.  Switching
+ * resets the accumulators. */
+int eamfe_set_kernel_timing(eamfe_ctx* ctx, int stride);
 
 /* Synchronise and return the summed event times (ms) and launch counts of
  * the density pass [0], the force pass [1] and the neighbour-list rebuild

@@ -55,8 +55,15 @@ struct eamfe_ctx {
     int cap = 0, ccap = 0, n_cells = 0;
     DevBuf nbr_d, nnb_d, cell_cnt_d, cell_n_d, cell_atoms_d, cell_rep_d;
 
+    // graph replay of the middle iterations (0 = eager launches)
+    int graph_iters = 0;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_user = nullptr, ev_graph = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+
     // optional per-launch timing with HIP events on the context's stream
-    int timing = 0;
+    int timing = 0;          // sample every timing-th iteration (0 = off)
+    bool timing_now = false; // current iteration is sampled
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<int> ev_kind;   // 0 density, 1 force, 2 neighbour rebuild (one entry per event pair)
@@ -579,7 +586,7 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
 // Record a timing event (kind: 0 density, 1 force, 2 lists; end = 0 start, 1 stop).
 int mark(eamfe_ctx* c, int kind, int end)
 {
-    if (!c->timing) return EAMFE_OK;
+    if (!c->timing || !c->timing_now) return EAMFE_OK;
     if (c->ev_used == c->ev_pool.size()) {
         hipEvent_t e;
         HIPCHK(c, hipEventCreate(&e));
@@ -593,6 +600,80 @@ int mark(eamfe_ctx* c, int kind, int end)
 // Iterations it_first .. it_last of a protocol starting from packed
 // positions *cur (one of the two internal buffers); on return *cur is the
 // buffer holding the final positions.
+// One MD iteration on stream st: list upkeep, density pass, force pass.
+int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool has_eam, hipStream_t st, bool sample,
+                  int64_t it)
+{
+    c->timing_now = c->timing > 0 && it % c->timing == 0;
+    if (has_eam) {
+        NeighArgs na = neigh_args(c, cur);
+        OK(mark(c, 2, 0));
+        LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, st));
+        OK(mark(c, 2, 1));
+    }
+    a.P = cur;
+    a.Pn = nxt;
+    a.Q = Q_of(c, cur);
+    a.Qn = Q_of(c, nxt);
+    a.rho_out = sample ? (double*)c->rho_d.p : nullptr;
+    OK(mark(c, 0, 0));
+    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, st));
+    OK(mark(c, 0, 1));
+    if (sample) {
+        OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out));
+        ++c->adj_samples;
+    }
+    OK(mark(c, 1, 0));
+    LCHK(c, launch_force(a, c->precision, c->lanes, c->block, st));
+    OK(mark(c, 1, 1));
+    return EAMFE_OK;
+}
+
+void drop_graphs(eamfe_ctx* c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+    }
+}
+
+// Capture `iters` (even) middle iterations starting from buffer `start` into a
+// graph on the internal stream; the kernels read the step from the device
+// counter, so one graph serves every middle stretch of a run.
+int capture_middle(eamfe_ctx* c, const StepArgs& a0, double4* start, bool has_eam, int iters, hipGraphExec_t* out)
+{
+    StepArgs a = a0;
+    const int timing = c->timing;
+    c->timing = 0;                   // no event records inside a graph
+    a.it_first = -1;                 // the closing kick of the previous step always applies
+    a.it_last = INT64_MAX;           // and a new step always starts
+    HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+    double4* cur = start;
+    double4* nxt = cur == PA(c) ? PB(c) : PA(c);
+    int rc = EAMFE_OK;
+    for (int k = 0; k < iters && rc == EAMFE_OK; ++k) {
+        rc = one_iteration(c, a, cur, nxt, has_eam, c->gstream, false, 1);
+        std::swap(cur, nxt);
+    }
+    c->timing = timing;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->gstream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, EAMFE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(c, EAMFE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    return EAMFE_OK;
+}
+
+// Iterations it_first .. it_last of a protocol starting from packed
+// positions *cur (one of the two internal buffers); on return *cur is the
+// buffer holding the final positions.  The first and last iterations carry
+// the open/close flags and run eagerly; with graphs enabled the middle ones
+// replay a captured graph of c->graph_iters iterations.
 int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it_first, int64_t it_last)
 {
     double4* cur = *cur_io;
@@ -602,32 +683,27 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
     a.step_kernel = 1;
     a.has_eam = has_eam ? 1 : 0;
     OK(set_iter(c, it_first));
-    for (int64_t it = it_first; it <= it_last; ++it) {
-        if (has_eam) {
-            NeighArgs na = neigh_args(c, cur);
-            OK(mark(c, 2, 0));
-            LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
-            OK(mark(c, 2, 1));
+    const bool graphs = c->graph_iters > 0 && !c->timing && c->adj_every == 0 && c->gstream;
+    int64_t it = it_first;
+    while (it <= it_last) {
+        const bool middle = it > it_first && it < it_last;
+        if (graphs && middle && it_last - it >= c->graph_iters) {
+            const int k = cur == PA(c) ? 0 : 1;
+            if (!c->gexec[k]) OK(capture_middle(c, a, cur, has_eam, c->graph_iters, &c->gexec[k]));
+            HIPCHK(c, hipEventRecord(c->ev_user, c->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev_user, 0));
+            const int64_t reps = (it_last - it) / c->graph_iters;
+            for (int64_t q = 0; q < reps; ++q) HIPCHK(c, hipGraphLaunch(c->gexec[k], c->gstream));
+            HIPCHK(c, hipEventRecord(c->ev_graph, c->gstream));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_graph, 0));
+            it += reps * c->graph_iters;   // graph_iters is even: the buffers are back where they were
+            continue;
         }
-        a.P = cur;
-        a.Pn = nxt;
-        a.Q = Q_of(c, cur);
-        a.Qn = Q_of(c, nxt);
-        // dU/dtheta samples in the H0 ensemble (lambda at its start value)
         const bool sample = has_eam && c->adj_every > 0 && it < it_last && it % c->adj_every == 0 &&
                             c->lam_valid && c->lam_h[it] == c->lam_h[0];
-        a.rho_out = sample ? (double*)c->rho_d.p : nullptr;
-        OK(mark(c, 0, 0));
-        LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
-        OK(mark(c, 0, 1));
-        if (sample) {
-            OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out));
-            ++c->adj_samples;
-        }
-        OK(mark(c, 1, 0));
-        LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
-        OK(mark(c, 1, 1));
+        OK(one_iteration(c, a, cur, nxt, has_eam, c->stream, sample, it));
         std::swap(cur, nxt);
+        ++it;
     }
     *cur_io = cur;
     return EAMFE_OK;
@@ -711,6 +787,10 @@ int eamfe_destroy(eamfe_ctx* c)
     release(c->snap_v);
     release(c->snap_w);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->ev_user) (void)hipEventDestroy(c->ev_user);
+    if (c->ev_graph) (void)hipEventDestroy(c->ev_graph);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     delete c;
     return EAMFE_OK;
 }
@@ -737,6 +817,20 @@ int eamfe_set_launch(eamfe_ctx* c, int lanes, int block)
         (void)hipSetDevice(c->device);
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return build_tiles(c);
+    }
+    return EAMFE_OK;
+}
+
+int eamfe_set_graph(eamfe_ctx* c, int iters)
+{
+    if (!c || iters < 0) return EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    drop_graphs(c);
+    c->graph_iters = (iters + 1) / 2 * 2;
+    if (c->graph_iters && !c->gstream) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_graph, hipEventDisableTiming));
     }
     return EAMFE_OK;
 }
@@ -988,6 +1082,7 @@ namespace {
 int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int64_t s1, double* x, double* v,
               double* dHdl_out, double* W_out, int64_t stride, int64_t trace_off, double c1, bool has_eam)
 {
+    drop_graphs(c);   // captured kernel arguments belong to one call (pointers, protocol, shapes)
     OK(pack(c, x));
     double4* cur = PA(c);
     if (has_eam) OK(ensure_lists(c, p->skin, cur));
@@ -1034,6 +1129,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
             OK(plan_lists(c, c->skin, new_cap));
             OK(set_rebuild_all(c));
+            drop_graphs(c);
             cur = start;
             HIPCHK(c, hipMemcpyAsync(cur, c->snap_P.p, p4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(Q_of(c, cur), c->snap_Q.p, q4, hipMemcpyDeviceToDevice, c->stream));
@@ -1153,10 +1249,10 @@ int eamfe_adjoint_samples(const eamfe_ctx* c, int64_t* n)
     return EAMFE_OK;
 }
 
-int eamfe_set_kernel_timing(eamfe_ctx* c, int on)
+int eamfe_set_kernel_timing(eamfe_ctx* c, int stride)
 {
-    if (!c) return EAMFE_EINVAL;
-    c->timing = on ? 1 : 0;
+    if (!c || stride < 0) return EAMFE_EINVAL;
+    c->timing = stride;
     c->ev_used = 0;
     c->ev_kind.clear();
     return EAMFE_OK;

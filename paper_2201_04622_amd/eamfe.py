@@ -63,6 +63,7 @@ def lib():
         "eamfe_set_launch": (i32, [vp, i32, i32]),
         "eamfe_get_launch": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "eamfe_set_grid": (i32, [vp, i32]),
+        "eamfe_set_graph": (i32, [vp, i32]),
         "eamfe_get_grid": (i32, [vp, C.POINTER(i32)]),
         "eamfe_set_xcd_affinity": (i32, [vp, i32]),
         "eamfe_check": (i32, [vp]),
@@ -213,6 +214,9 @@ class Context:
         self._c(self._lib.eamfe_get_launch(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def set_graph(self, iters):
+        self._c(self._lib.eamfe_set_graph(self._h, int(iters)))
+
     def set_grid(self, blocks):
         self._c(self._lib.eamfe_set_grid(self._h, int(blocks)))
 
@@ -233,8 +237,9 @@ class Context:
                                          C.byref(a), C.byref(b), C.byref(ms)))
         return a.value, b.value, ms.value
 
-    def set_kernel_timing(self, on=True):
-        self._c(self._lib.eamfe_set_kernel_timing(self._h, int(bool(on))))
+    def set_kernel_timing(self, stride=1):
+        """Time the kernels of every stride-th iteration with HIP events (0 = off)."""
+        self._c(self._lib.eamfe_set_kernel_timing(self._h, int(stride)))
 
     def kernel_timing(self):
         """{'density'|'force'|'lists': (total ms, launches)} since timing was enabled."""

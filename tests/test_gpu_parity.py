@@ -314,3 +314,37 @@ def test_neighbour_rows_match_brute_force(shift):
             assert need <= set(row.tolist()), (r, il)
             assert np.all(dist[il, row] < rl + 2e-3)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_graph_replay_matches_eager(prec):
+    """Middle iterations replayed from a captured graph give bit-identical
+    trajectories and work traces; every replay is checked, with eager work
+    and synchronisations between replays (several calls, several chunks)."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()[:4]
+    p = E.protocol("fl", 30, 80, 20, 30)
+    S = 30 + 160 + 20 + 30
+    cuts = [0, 37, 90, 91, 170, S]
+    out = {}
+    for graph in (0, 8):
+        ctx, x0, arrs = make_ctx(reps, prec, 2, 256)
+        ctx.set_chunk(40)
+        ctx.set_graph(graph)
+        x = x0.clone()
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        W = torch.zeros(len(reps), S, dtype=torch.float64, device="cuda")
+        snaps = []
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            ctx.run_switching(p, x, v, a, b, None, None, W)
+            torch.cuda.synchronize()
+            snaps.append((x.cpu().numpy().copy(), v.cpu().numpy().copy()))
+            _ = (x * 2.0).sum().item()          # eager work between replays
+        out[graph] = (snaps, W.cpu().numpy())
+        ctx.close()
+    for (xe, ve), (xg, vg) in zip(out[0][0], out[8][0]):
+        assert np.array_equal(xe, xg) and np.array_equal(ve, vg)
+    assert np.array_equal(out[0][1], out[8][1])
