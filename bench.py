@@ -132,14 +132,16 @@ def cpu_baseline(target_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6000)
+    # default: the 2000-step equilibration untimed, then every remaining step of
+    # the protocol (forward switch, hold, backward switch) timed
+    ap.add_argument("--steps", type=int, default=42000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--skin", type=float, default=0.5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
