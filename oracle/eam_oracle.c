@@ -32,9 +32,9 @@
  *   fixed CM: the per-replica mean of the thermostat noise is removed, and the
  *             initial velocities have zero total momentum.
  *
- * Parity unpinned: the Philox bit stream itself (no published known-answer
- * vectors are available here); it is checked only statistically and by
- * agreement with the GPU path.
+ * Pins: every function here is checked by the tests against closed forms,
+ * invariants, library routines or published values; the Philox bit stream
+ * against the generator's published known-answer vectors.
  */
 #include <math.h>
 #include <stdint.h>

@@ -1,11 +1,13 @@
 """Pins of the oracle's noise stream and switching schedules.
 
-The Philox bit stream itself is parity-unpinned (no published known-answer
-vectors are available offline); it is pinned here only by its statistics and
-by its determinism.  The schedules are pinned by the properties the paper
+The Philox bit stream is pinned by the generator's published known-answer
+vectors (tests/golden/philox4x32_10_kat.txt), the Gaussian deviates by their
+statistics and by their determinism.  The schedules are pinned by the properties the paper
 states for lambda(tau): end points, vanishing end slopes, the closed-form
 slope 630 tau^4 (1-tau)^4 of the polynomial, and the RS form giving a
 temperature linear in tau."""
+import os
+
 import numpy as np
 import pytest
 from scipy import stats
@@ -13,6 +15,15 @@ from scipy import stats
 
 def _draws(O, n, seed=0, step=0, stream=0):
     return np.array([O.gauss3(seed, i, step, stream) for i in range(n)])
+
+
+def test_philox_known_answers(oracle_lib):
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(v, 16) for v in r]
+        assert list(oracle_lib.philox(w[0:4], w[4:6])) == w[6:10]
 
 
 def test_gaussian_moments(oracle_lib):
