@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2201_04622_amd/csrc/eamfe_kernels.hip", "paper_2201_04622_amd/csrc/eamfe_internal.h")
 # HIP-event pairs around the kernels of one iteration in this many: each pair
 # costs ~10 us of stream time, so sampling keeps the timed region unperturbed
 KERNEL_TIMING_STRIDE = 50
@@ -46,6 +47,37 @@ def density_bytes_per_atom(n_list, prec):
     """x read, row length and row, F' and F written."""
     fp = 4 if prec == "fp32" else 8
     return 24 + 4 + 4 * n_list + fp + 8
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, prec, launch):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the factor the same
+    counter reads for a plain copy), or None when there is no summary for this
+    kernel, workload, precision and launch shape, or the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if kv.get("launch") != f"lanes {launch[0]} block {launch[1]}":
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None):
@@ -109,7 +141,7 @@ def cpu_baseline(target_s=12.0):
     from oracle import oracle as O
     from paper_2201_04622_amd import inputs as I
     O.build()
-    wl = I.workload("cfg2")
+    wl = I.workload("batch64")
     r = wl.replicas[4]
     pot = O.Potential.from_knots(I.synthetic_eam_knots())
     prm = O.RunParams(mode="fl", T=r.T, k=r.k, seed=r.seed, fix_com=True, skin=0.3, nlist_cap=512)
@@ -136,7 +168,7 @@ def main():
     # the protocol (forward switch, hold, backward switch) timed
     ap.add_argument("--steps", type=int, default=42000)
     ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="batch64")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -171,10 +203,12 @@ def main():
     bpa = (force_bytes_per_atom if dom == "force" else density_bytes_per_atom)(main_run["mean_nl"], args.precision)
     bytes_launch = bpa * main_run["natoms"]
     achieved = bytes_launch / (avg_ms / 1e3) / 1e9
+    kname = "k_force" if dom == "force" else "k_density"
+    traffic = measured_traffic(kname, args.workload, args.precision, main_run["launch"])
 
     plain = None
     if not args.no_fp64:
-        pr = run_gpu("cfg1", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0])
+        pr = run_gpu("fl_mid", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0])
         plain = {
             "value": pr["natoms"] * 2000 / (pr["ms"] / 1e3), "unit": "atom-steps/s",
             "workload": "one FL replica, bcc 10^3 (2000 atoms), T=1400 K, k=3, FP64, autotuned launch",
@@ -210,9 +244,10 @@ def main():
             "kernel_launches": {k: v[1] for k, v in kt.items()},
         },
         "roofline": {
-            "bound": "hbm", "kernel": "k_force" if dom == "force" else "k_density",
+            "bound": "hbm", "kernel": kname,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "bytes_per_atom": bpa, "avg_launch_us": avg_ms * 1e3,
+            "traffic": traffic, "algorithmic_bytes": bytes_launch, "bytes_per_atom": bpa,
+            "avg_launch_us": avg_ms * 1e3,
         },
         "fp64_plain_single_replica": plain,
         "cpu_baseline": cpu,

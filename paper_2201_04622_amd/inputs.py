@@ -161,38 +161,47 @@ class Workload:
         return self.natoms * self.schedule.total_steps
 
 
-def _cfg2_shapes(a_bcc: float, a_fcc: float):
+def _batch_shapes(a_bcc: float, a_fcc: float):
     return [("bcc", n, a_bcc) for n in range(6, 13)] + [("fcc", n, a_fcc) for n in range(5, 11)]
 
 
 def workload(name: str, stable: bool = False) -> Workload:
-    """The five configured workloads.  ``stable`` swaps in the synthetic
+    """The five workloads, by name:
+
+    fl_bcc4   FL in FP64, one bcc 4^3 replica (128 atoms), T=100 K, k=5
+    fl_mid    FL, one bcc 10^3 (2000) and one fcc 8^3 (2048) replica, T=1400 K, k=3
+    batch64   64 FL replicas of uneven size (bcc 6..12^3, fcc 5..10^3; 113,090
+              atoms), T = 100 (1 + r mod 16) K, k=5, seeds 0..63
+    rs_scan   RS scan 100 -> 1600 K, 8 bcc 20^3 replicas (128,000 atoms)
+    fl_large  FL, 16 bcc 30^3 + 16 fcc 24^3 replicas (1,748,736 atoms), T=1200 K
+
+    ``stable`` swaps in the synthetic
     potential's own zero-pressure lattice constants (and the smallest box that
     keeps L > 2*(r_cut + skin))."""
     ab = A_BCC_STABLE if stable else A_BCC_VERBATIM
     af = A_FCC_STABLE if stable else A_FCC_VERBATIM
-    if name == "cfg0":
+    if name == "fl_bcc4":
         n = 6 if stable else 4
         reps = [Replica("bcc", n, ab, 100.0, 5.0, 0)]
         sch = Schedule("fl", 1000, 2000, 500, 500, function=2)
         desc = f"FL FP64, 1 x bcc {n}^3, T=100 K, k=5"
-    elif name == "cfg1":
+    elif name == "fl_mid":
         reps = [Replica("bcc", 10, ab, 1400.0, 3.0, 0), Replica("fcc", 8, af, 1400.0, 3.0, 0)]
         sch = Schedule("fl", 10000, 50000, 10000, 10000, function=2)
         desc = "FL single replicas bcc 10^3 / fcc 8^3, T=1400 K, k=3"
-    elif name == "cfg2":
-        shapes = _cfg2_shapes(ab, af)
+    elif name == "batch64":
+        shapes = _batch_shapes(ab, af)
         reps = []
         for r in range(64):
             kind, n, a = shapes[r % len(shapes)]
             reps.append(Replica(kind, n, a, 100.0 * (1 + (r % 16)), 5.0, r))
         sch = Schedule("fl", 2000, 20000, 2000, 0, function=2)
         desc = "64 batched FL replicas, bcc 6..12^3 / fcc 5..10^3, T in 100..1600 K, k=5"
-    elif name == "cfg3":
+    elif name == "rs_scan":
         reps = [Replica("bcc", 20, ab, 100.0, 5.0, s) for s in range(8)]
         sch = Schedule("rs", 10000, 100000, 10000, 0, lambda_f=100.0 / 1600.0)
         desc = "RS scan 100->1600 K, 8 x bcc 20^3"
-    elif name == "cfg4":
+    elif name == "fl_large":
         reps = [Replica("bcc", 30, ab, 1200.0, 5.0, s) for s in range(16)]
         reps += [Replica("fcc", 24, af, 1200.0, 5.0, s) for s in range(16)]
         sch = Schedule("fl", 3000, 30000, 3000, 0, function=2)
