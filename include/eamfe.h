@@ -161,8 +161,9 @@ int eamfe_kernel_timing(eamfe_ctx* ctx, double* ms_total, int64_t* launches);
 int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capacity);
 
 /* Copy the current Verlet rows (for inspection): nnb_dev[N_tot] row lengths,
- * nbr_dev[N_tot][cap] global atom ids (may be NULL; cap >= the row capacity
- * reported by eamfe_list_stats).  Device int32 arrays.  Synchronises. */
+ * nbr_dev[N_tot][cap] global atom ids in row order, -1 past each row's end
+ * (may be NULL; cap >= the row capacity reported by eamfe_list_stats).
+ * Device int32 arrays.  Synchronises. */
 int eamfe_copy_lists(eamfe_ctx* ctx, int32_t* nnb_dev, int32_t* nbr_dev, int cap);
 
 /* ---- potential --------------------------------------------------------- */
@@ -187,8 +188,10 @@ int eamfe_system_setup(eamfe_ctx* ctx, int n_rep, const eamfe_replica* reps, con
 /* Build the Verlet lists at positions x (device SoA) with cutoff r_cut+skin:
  * cell binning with cells of edge >= r_cut+skin where a box holds at least
  * three per edge, all-pairs otherwise.  max_neighbors bounds each atom's row
- * (rounded up to a multiple of 32; 0 = estimate from the densest replica).
- * EAMFE_EBOX if an edge <= 2(r_cut+skin). */
+ * (rounded up to a multiple of 32): a row that does not fit is reported as
+ * EAMFE_ENEIGH_OVERFLOW.  With max_neighbors = 0 the capacity is estimated
+ * from the densest replica and enlarged until every row (and cell bin) of
+ * this configuration fits.  EAMFE_EBOX if an edge <= 2(r_cut+skin). */
 int neigh_build(eamfe_ctx* ctx, const double* x_dev, double skin, int max_neighbors);
 
 /* ---- evaluation -------------------------------------------------------- */

@@ -986,14 +986,26 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     OK(plan_lists(c, skin, max_neighbors));
     c->have_list = true;
-    OK(set_rebuild_all(c));
     OK(pack(c, x));
-    NeighArgs na = neigh_args(c, PA(c));
-    LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
-    // the flags are cleared by the next density pass; clear them here too
-    hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
-                       (int32_t*)c->rebuild_d.p, c->n_rep, 0);
-    HIPCHK(c, hipGetLastError());
+    for (int attempt = 0;; ++attempt) {
+        OK(set_rebuild_all(c));
+        NeighArgs na = neigh_args(c, PA(c));
+        LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+        // the flags are cleared by the next density pass; clear them here too
+        hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
+                           (int32_t*)c->rebuild_d.p, c->n_rep, 0);
+        HIPCHK(c, hipGetLastError());
+        if (max_neighbors > 0 || attempt >= 6) break;
+        // automatic capacity: enlarge rows or bins until this configuration fits
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int st = 0;
+        HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW))) break;
+        HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
+        const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
+        if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
+        OK(plan_lists(c, skin, new_cap));
+    }
     return read_status(c);
 }
 
@@ -1376,8 +1388,8 @@ int eamfe_copy_lists(eamfe_ctx* c, int32_t* nnb_dev, int32_t* nbr_dev, int cap)
     HIPCHK(c, hipMemcpyAsync(nnb_dev, c->nnb_d.p, (size_t)c->N * sizeof(int32_t), hipMemcpyDeviceToDevice,
                              c->stream));
     if (nbr_dev)
-        HIPCHK(c, hipMemcpy2DAsync(nbr_dev, (size_t)cap * sizeof(int32_t), c->nbr_d.p, (size_t)c->cap * sizeof(int32_t),
-                                   (size_t)c->cap * sizeof(int32_t), c->N, hipMemcpyDeviceToDevice, c->stream));
+        LCHK(c, launch_rows_rowmajor((const int32_t*)c->nbr_d.p, (const int32_t*)c->nnb_d.p, c->N, c->cap, nbr_dev,
+                                     cap, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return EAMFE_OK;
 }

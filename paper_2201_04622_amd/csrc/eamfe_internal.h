@@ -175,6 +175,9 @@ int launch_adjoint(const AdjointArgs& a, int precision, int grid, hipStream_t s)
 // scratch: device doubles, >= 3 * 3 * nmax per output row.
 int launch_adjoint_finish(const AdjointArgs& a, const double* w, int reduce, double* out, double* scratch,
                           hipStream_t s);
+// Rows in [N][out_cap] row-major order (slots past the row length = -1).
+int launch_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap, int32_t* out, int out_cap,
+                         hipStream_t s);
 int launch_rho(const StepArgs& a, double* rho_out, int precision, int lanes, int block, hipStream_t s);
 
 }  // namespace eamfe

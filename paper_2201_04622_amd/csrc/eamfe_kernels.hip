@@ -157,16 +157,20 @@ struct Root<double> {
     }
 };
 
-// Neighbour ids of slots [b0, b0+SB) of a row (SB = 4, 16-byte aligned since
-// rows start at multiples of the capacity, a multiple of 32); slots at or
-// beyond n read as the atom itself, whose contribution is masked out.
-__device__ __forceinline__ int4 row_ids(const int32_t* row, int b0, int n, int self)
+// Neighbour rows are stored in slabs of four slots: slot s of atom i is at
+// nbr[((s / 4) * N + i) * 4 + s % 4].  A lane reads four consecutive slots
+// with one 16-byte load, and the lanes of a wavefront, which hold
+// consecutive atoms, read consecutive 16-byte words.  The list builder pads
+// every row with the atom's own id up to a multiple of four, so whole slabs
+// below the row length are always valid ids.
+__device__ __forceinline__ size_t slot_index(int i, int s, int N)
 {
-    int4 j = *(const int4*)(row + b0);
-    if (b0 + 1 >= n) j.y = self;
-    if (b0 + 2 >= n) j.z = self;
-    if (b0 + 3 >= n) j.w = self;
-    return j;
+    return ((size_t)(s >> 2) * (size_t)N + (size_t)i) * 4 + (size_t)(s & 3);
+}
+
+__device__ __forceinline__ int4 row_slab(const int32_t* nbr, int i, int b0, int N)
+{
+    return *(const int4*)(nbr + ((size_t)(b0 >> 2) * (size_t)N + (size_t)i) * 4);
 }
 
 // --------------------------------------------------------------------------
@@ -420,7 +424,6 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
         const uint4 qi = a.Q[i];
         const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
                     sz = (float)(R.L[2] * 2.3283064365386963e-10);
-        int32_t* row = a.nbr + (size_t)i * a.cap;
         int cnt = 0;
         auto test = [&](int jl) {
             const uint4 qj = a.Q[R.off + jl];
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
         auto append = [&](bool acc, int j) {
             const uint64_t m = __ballot(acc);
             const int rank = __popcll(m & below);
-            if (acc && cnt + rank < a.cap) row[cnt + rank] = j;
+            if (acc && cnt + rank < a.cap) a.nbr[slot_index(i, cnt + rank, a.N)] = j;
             cnt += __popcll(m);
         };
         if (R.nc[0] == 0) {
@@ -479,6 +482,9 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
             }
             __builtin_amdgcn_wave_barrier();
         }
+        // pad the last slab with the atom itself (cap is a multiple of 32)
+        const int pad_end = min((cnt + 3) & ~3, a.cap);
+        if (cnt + lw < pad_end) a.nbr[slot_index(i, cnt + lw, a.N)] = i;
         if (lw == 0) {
             if (cnt > a.cap) {
                 atomicOr(a.status, ST_NEIGH_OVERFLOW);
@@ -527,10 +533,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 qsz = (float)(R.L[2] * 2.3283064365386963e-10);
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
-        const int32_t* row = a.nbr + (size_t)i * a.cap;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
         const int step = T * SB;
-        int4 jn = lane * SB < n ? row_ids(row, lane * SB, n, i) : make_int4(i, i, i, i);
+        int4 jn = lane * SB < n ? row_slab(a.nbr, i, lane * SB, N) : make_int4(i, i, i, i);
         for (int b0 = lane * SB; b0 < n; b0 += step) {
             const int js[SB] = {jn.x, jn.y, jn.z, jn.w};
             double4 pj[kQ ? 1 : SB];
@@ -540,7 +545,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 if constexpr (kQ) qj[s] = a.Q[js[s]];
                 else pj[s] = a.P[js[s]];
             }
-            if (b0 + step < n) jn = row_ids(row, b0 + step, n, i);   // next block's ids, one iteration ahead
+            // next block's ids, one iteration ahead; unconditional (the last block re-reads
+            // its own slab) so that the load needs no wait until its use
+            jn = row_slab(a.nbr, i, b0 + step < n ? b0 + step : b0, N);
             real r[SB], t[SB];
             int m[SB];
             bool in[SB];
@@ -660,11 +667,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, ep = 0.0;
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
-        const int32_t* row = a.nbr + (size_t)i * a.cap;
         const real Fpi = kQ ? (real)__uint_as_float(qi.w) : (real)pi.w;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
         const int step = T * SB;
-        int4 jn = lane * SB < n ? row_ids(row, lane * SB, n, i) : make_int4(i, i, i, i);
+        int4 jn = lane * SB < n ? row_slab(a.nbr, i, lane * SB, N) : make_int4(i, i, i, i);
         for (int b0 = lane * SB; b0 < n; b0 += step) {
             const int js[SB] = {jn.x, jn.y, jn.z, jn.w};
             double4 pj[kQ ? 1 : SB];
@@ -674,7 +680,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 if constexpr (kQ) qj[s] = a.Q[js[s]];
                 else pj[s] = a.P[js[s]];
             }
-            if (b0 + step < n) jn = row_ids(row, b0 + step, n, i);   // next block's ids, one iteration ahead
+            // next block's ids, one iteration ahead; unconditional (the last block re-reads
+            // its own slab) so that the load needs no wait until its use
+            jn = row_slab(a.nbr, i, b0 + step < n ? b0 + step : b0, N);
             real rx[SB], ry[SB], rz[SB], ir[SB], t[SB], fpj[SB];
             int m[SB];
             bool in[SB];
@@ -891,6 +899,23 @@ int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s
     return (int)hipGetLastError();
 }
 
+__global__ void k_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap, int32_t* out, int out_cap)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int n = nnb[i] < cap ? nnb[i] : cap;
+    for (int q = 0; q < n; ++q) out[(size_t)i * out_cap + q] = nbr[slot_index(i, q, N)];
+    for (int q = n; q < out_cap; ++q) out[(size_t)i * out_cap + q] = -1;
+}
+
+int launch_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap, int32_t* out, int out_cap,
+                         hipStream_t s)
+{
+    if (N <= 0) return 0;
+    hipLaunchKernelGGL(k_rows_rowmajor, dim3(grid1(N, 256)), dim3(256), 0, s, nbr, nnb, N, cap, out, out_cap);
+    return (int)hipGetLastError();
+}
+
 template <typename real>
 static size_t lds_bytes(const StepArgs& a, int tables)
 {
@@ -1027,11 +1052,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(AdjointArgs a)
                 const uint4 qi = kQ ? a.Q[i] : make_uint4(0u, 0u, 0u, 0u);
                 const double wgt = WHICH == 0 ? 0.5 : (kQ ? (double)__uint_as_float(qi.w) : pi.w);
                 const int n = a.nnb[i];
-                const int32_t* row = a.nbr + (size_t)i * a.cap;
                 for (int q = lane; q < n; q += kAdjLanes) {
                     // geometry in float64 in both forms: the basis weights B(t) vary on the
                     // scale of one interval, so t needs more than single precision
-                    const int j = row[q];
+                    const int j = a.nbr[slot_index(i, q, a.N)];
                     double dx, dy, dz;
                     if constexpr (kQ) {
                         const uint4 qj = a.Q[j];
