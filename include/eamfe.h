@@ -122,9 +122,20 @@ int eamfe_set_stream(eamfe_ctx* ctx, void* hip_stream);
 int eamfe_set_launch(eamfe_ctx* ctx, int lanes_per_atom, int block_threads);
 int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threads);
 
-/* Blocks launched for the density and force passes (rounded up to a
- * multiple of 8); each block stages the spline table once and strides over
- * the tiles.  0 = one block per tile (default). */
+/* Autotuner: time `trial_steps` steps of protocol p from `step` at every
+ * launch shape (lanes per atom x block threads x persistent grid) on copies
+ * of the caller's state (x_dev, v_dev are not modified; the work carried by
+ * the context is restored) and keep the fastest shape.  Outputs (may be
+ * NULL): the chosen lanes and block threads, and its time per step in ms. */
+int eamfe_autotune(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step, const double* x_dev,
+                   const double* v_dev, int trial_steps, int* lanes_out, int* block_out, double* ms_per_step);
+
+/* Persistent blocks launched for the density and force passes (rounded up
+ * to a multiple of 8).  Each block stages the spline table once; each of its
+ * wavefronts then takes a fixed stride of work units (the atoms of one
+ * wavefront, 64/lanes atoms of one replica).  0 = as many blocks as the chip
+ * holds resident at this launch shape, or fewer when every unit has its own
+ * wavefront (default). */
 int eamfe_set_grid(eamfe_ctx* ctx, int blocks);
 int eamfe_get_grid(const eamfe_ctx* ctx, int* blocks);
 
@@ -135,8 +146,9 @@ int eamfe_get_grid(const eamfe_ctx* ctx, int* blocks);
  * stream with events.  Kernel timing or adjoint sampling switch it off. */
 int eamfe_set_graph(eamfe_ctx* ctx, int iters);
 
-/* 1: place every replica's tiles on one XCD (workgroup id mod 8), balancing
- * atoms across the eight XCDs; 0: replica-major order.  Default 1. */
+/* 1: bin the replicas into eight groups balanced by atom count; group x is
+ * spread over the blocks on XCD x (workgroup id mod 8), so a replica's atoms
+ * stay in one XCD's L2.  0: one group.  Default 1. */
 int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
 
 /* Synchronise the stream and return the first latched device condition

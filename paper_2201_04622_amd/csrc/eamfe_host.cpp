@@ -25,7 +25,7 @@ struct eamfe_ctx {
     int precision = EAMFE_FP64;
     int lanes = 4;
     int block = 256;
-    int grid = 0;      // pair-kernel blocks (0: one per tile), a multiple of 8
+    int grid = 0;      // persistent pair-kernel blocks (0: every resident slot), a multiple of 8
     int n_cu = 256;
     int xcd = 1;
     std::string err;
@@ -43,11 +43,13 @@ struct eamfe_ctx {
     int N = 0;
     std::vector<eamfe_replica> reps_in;
     std::vector<RepDesc> reps;
-    std::vector<Tile> tiles;
-    int n_tiles = 0;   // real tiles
+    std::vector<Tile> tiles;   // work units in queue order
+    int n_tiles = 0;           // work units
+    int nq = 1;                // unit groups (one per XCD with affinity)
+    int qoff[9] = {0};         // group q holds tiles[qoff[q] .. qoff[q+1])
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
-    DevBuf noise_part_d, energy_part_d, noise_sum_d, U_rep_d, W_state_d;
-    DevBuf cnt_density_d, cnt_force_d, cnt_all_d, iter_d, rebuild_d, status_d;
+    DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
+    DevBuf iter_d, rebuild_d, status_d;
 
     // neighbour lists
     bool have_list = false;
@@ -216,14 +218,15 @@ Tables tables_of(const eamfe_ctx* c)
     return t;
 }
 
-// Tile table for the current launch shape.  With XCD affinity (and at least
-// eight replicas) replicas are packed into eight bins of about equal atom
-// count and the tiles of bin x are placed at grid positions p with p % 8 == x,
-// so a replica's workgroups share one XCD's L2; unused positions are padding
-// tiles (count 0).
+// Work-unit table for the current launch shape: every replica is cut into
+// units of 64/lanes atoms (one wavefront's atoms), in replica-major order
+// (consecutive wavefronts of a block share a replica's neighbourhoods in the
+// CU's caches); unit slots (tile_base) follow the replica index.  With XCD affinity (and at least 8 replicas) replicas
+// are binned greedily by atom count into 8 groups (group x is spread over the
+// blocks on XCD x); otherwise one group.
 int build_tiles(eamfe_ctx* c)
 {
-    const int A = c->block / c->lanes;
+    const int A = 64 / c->lanes;
     c->tiles.clear();
     std::vector<std::vector<Tile>> per(c->n_rep);
     int base = 0;
@@ -242,29 +245,34 @@ int build_tiles(eamfe_ctx* c)
         }
     }
     c->n_tiles = base;
+    for (int q = 0; q < 9; ++q) c->qoff[q] = 0;
     if (c->xcd && c->n_rep >= 8) {
         std::vector<int> order(c->n_rep);
         for (int r = 0; r < c->n_rep; ++r) order[r] = r;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->reps[a].n > c->reps[b].n; });
         std::vector<long> load(8, 0);
-        std::vector<std::vector<Tile>> bins(8);
+        std::vector<std::vector<int>> bins(8);
         for (int r : order) {
             const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             load[x] += c->reps[r].n;
-            bins[x].insert(bins[x].end(), per[r].begin(), per[r].end());
+            bins[x].push_back(r);
         }
-        size_t len = 0;
-        for (auto& b : bins) len = std::max(len, b.size());
-        Tile pad{0, 0, 0, 0};
-        for (size_t q = 0; q < len; ++q)
-            for (int x = 0; x < 8; ++x) c->tiles.push_back(q < bins[x].size() ? bins[x][q] : pad);
+        for (int x = 0; x < 8; ++x) {
+            std::sort(bins[x].begin(), bins[x].end());
+            for (int r : bins[x]) c->tiles.insert(c->tiles.end(), per[r].begin(), per[r].end());
+            c->qoff[x + 1] = (int)c->tiles.size();
+        }
+        c->nq = 8;
     } else {
         for (auto& v : per) c->tiles.insert(c->tiles.end(), v.begin(), v.end());
+        c->qoff[1] = (int)c->tiles.size();
+        c->nq = 1;
     }
-    OK(ensure(c, c->tiles_d, c->tiles.size() * sizeof(Tile)));
-    HIPCHK(c, hipMemcpy(c->tiles_d.p, c->tiles.data(), c->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    OK(ensure(c, c->noise_part_d, (size_t)c->n_tiles * 3 * sizeof(double)));
-    OK(ensure(c, c->energy_part_d, (size_t)c->n_tiles * 2 * sizeof(double)));
+    OK(ensure(c, c->tiles_d, std::max<size_t>(1, c->tiles.size()) * sizeof(Tile)));
+    if (!c->tiles.empty())
+        HIPCHK(c, hipMemcpy(c->tiles_d.p, c->tiles.data(), c->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    OK(ensure(c, c->noise_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
+    OK(ensure(c, c->energy_part_d, (size_t)std::max(1, c->n_tiles) * 2 * sizeof(double)));
     OK(ensure(c, c->reps_d, c->reps.size() * sizeof(RepDesc)));
     HIPCHK(c, hipMemcpy(c->reps_d.p, c->reps.data(), c->reps.size() * sizeof(RepDesc), hipMemcpyHostToDevice));
     return EAMFE_OK;
@@ -294,7 +302,6 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
     a.cell_rep = (const int32_t*)c->cell_rep_d.p;
     a.P = P;
     a.Q = Q_of(c, P);
-    a.n_grid = (int)c->tiles.size();
     a.n_rep = c->n_rep;
     a.xref = (double*)c->xref_d.p;
     a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
@@ -334,12 +341,8 @@ StepArgs step_args(eamfe_ctx* c)
     a.e_emb = (double*)c->e_emb_d.p;
     a.xi = (double*)c->xi_d.p;
     a.noise_part = (double*)c->noise_part_d.p;
-    a.noise_sum = (double*)c->noise_sum_d.p;
     a.energy_part = (double*)c->energy_part_d.p;
     a.U_rep = (double*)c->U_rep_d.p;
-    a.cnt_density = (uint32_t*)c->cnt_density_d.p;
-    a.cnt_force = (uint32_t*)c->cnt_force_d.p;
-    a.cnt_all = (uint32_t*)c->cnt_all_d.p;
     a.rebuild = (int32_t*)c->rebuild_d.p;
     a.status = (int32_t*)c->status_d.p;
     a.iter = (int64_t*)c->iter_d.p;
@@ -347,8 +350,11 @@ StepArgs step_args(eamfe_ctx* c)
     a.tab = tables_of(c);
     a.N = c->N;
     a.n_tiles = c->n_tiles;
-    a.n_grid = (int)c->tiles.size();
+    a.n_rep = c->n_rep;
     a.grid_blocks = c->grid;
+    a.n_cu = c->n_cu;
+    a.nq = c->nq;
+    for (int q = 0; q < 9; ++q) a.qoff[q] = c->qoff[q];
     a.half_skin2 = 0.25 * c->skin * c->skin;
     return a;
 }
@@ -567,7 +573,7 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
     a.tab = tables_of(c);
     a.N = c->N;
     a.n_rep = c->n_rep;
-    a.tile_atoms = c->block / c->lanes;
+    a.tile_atoms = 64 / c->lanes;
     a.n_units = c->n_tiles;
     const int grid = std::max(1, std::min(c->n_tiles, 2 * c->n_cu));
     LCHK(c, launch_adjoint(a, c->precision, grid, c->stream));
@@ -625,6 +631,7 @@ int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool ha
     }
     OK(mark(c, 1, 0));
     LCHK(c, launch_force(a, c->precision, c->lanes, c->block, st));
+    LCHK(c, launch_finish(a, st));
     OK(mark(c, 1, 1));
     return EAMFE_OK;
 }
@@ -748,13 +755,12 @@ int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
             c->n_cu = cus;
     }
     int r = EAMFE_OK;
-    if ((r = ensure(c, c->cnt_all_d, sizeof(uint32_t))) || (r = ensure(c, c->iter_d, sizeof(int64_t))) ||
+    if ((r = ensure(c, c->iter_d, sizeof(int64_t))) ||
         (r = ensure(c, c->status_d, sizeof(int32_t)))) {
         eamfe_destroy(c);
         return r;
     }
-    if (hipMemset(c->cnt_all_d.p, 0, sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(c->status_d.p, 0, sizeof(int32_t)) != hipSuccess) {
+    if (hipMemset(c->status_d.p, 0, sizeof(int32_t)) != hipSuccess) {
         eamfe_destroy(c);
         return EAMFE_EDEVICE;
     }
@@ -770,8 +776,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->noise_sum_d, &c->U_rep_d, &c->W_state_d, &c->cnt_density_d,
-                      &c->cnt_force_d, &c->cnt_all_d, &c->iter_d, &c->rebuild_d, &c->status_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->status_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -953,11 +958,8 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->xi_d, v3));
     OK(ensure(c, c->e_emb_d, (size_t)N * sizeof(double)));
     OK(ensure(c, c->rep_of_d, (size_t)N * sizeof(int32_t)));
-    OK(ensure(c, c->noise_sum_d, (size_t)n_rep * 3 * sizeof(double)));
     OK(ensure(c, c->U_rep_d, (size_t)n_rep * 2 * sizeof(double)));
     OK(ensure(c, c->W_state_d, (size_t)n_rep * sizeof(double)));
-    OK(ensure(c, c->cnt_density_d, (size_t)n_rep * sizeof(uint32_t)));
-    OK(ensure(c, c->cnt_force_d, (size_t)n_rep * sizeof(uint32_t)));
     OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
@@ -968,11 +970,8 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->Qb_d.p, 0, (size_t)N * sizeof(uint4)));
     HIPCHK(c, hipMemset(c->e_emb_d.p, 0, (size_t)N * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->rep_of_d.p, rep_of.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemset(c->noise_sum_d.p, 0, (size_t)n_rep * 3 * sizeof(double)));
     HIPCHK(c, hipMemset(c->U_rep_d.p, 0, (size_t)n_rep * 2 * sizeof(double)));
     HIPCHK(c, hipMemset(c->W_state_d.p, 0, (size_t)n_rep * sizeof(double)));
-    HIPCHK(c, hipMemset(c->cnt_density_d.p, 0, (size_t)n_rep * sizeof(uint32_t)));
-    HIPCHK(c, hipMemset(c->cnt_force_d.p, 0, (size_t)n_rep * sizeof(uint32_t)));
     HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
     c->have_list = false;
     return build_tiles(c);
@@ -1032,6 +1031,7 @@ int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_at
         a.e_atom_out = e_atom;
         LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
         LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+        LCHK(c, launch_finish(a, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         int st = 0;
         HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -1319,7 +1319,7 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
     HIPCHK(c, hipEventCreate(&e1));
     int rc = EAMFE_OK;
     const int lanes_c[] = {1, 2, 4, 8, 16};
-    const int block_c[] = {64, 128, 256, 512, 1024};
+    const int block_c[] = {64, 128, 256, 512, 640, 768, 1024};
     const int grid_c[] = {0, c->n_cu, 2 * c->n_cu, 4 * c->n_cu};
     for (int L : lanes_c) {
         for (int B : block_c) {
@@ -1328,7 +1328,6 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
             c->lanes = L;
             c->block = B;
             c->grid = (G + 7) / 8 * 8;
-            if (G && (int)((c->n_atoms_total() + B / L - 1) / (B / L)) <= c->grid) continue;   // no fewer blocks than tiles
             if ((rc = build_tiles(c))) goto done;
             if (hipMemcpyAsync(c->tune_x.p, x, v3, hipMemcpyDeviceToDevice, c->stream) ||
                 hipMemcpyAsync(c->tune_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream)) {

@@ -35,8 +35,8 @@ constexpr double kFixInv = 2.3283064365386963e-10;  // 2^-32
 struct RepDesc {
     int32_t off;        // first global atom
     int32_t n;          // atoms
-    int32_t tile_base;  // first slot of this replica in per-tile partial arrays
-    int32_t n_tiles;
+    int32_t tile_base;  // first slot of this replica in per-unit partial arrays
+    int32_t n_tiles;    // work units of this replica
     int32_t cell_base;  // first global cell
     int32_t nc[3];      // cells per edge; nc[0] == 0 selects all-pairs lists
     double L[3];
@@ -48,12 +48,13 @@ struct RepDesc {
     uint64_t seed;
 };
 
-// A tile is a contiguous run of atoms of one replica handled by one block.
+// A tile (work unit) is a contiguous run of at most 64/T atoms of one
+// replica: the atoms of one wavefront of the pair kernels.
 struct Tile {
     int32_t rep;
     int32_t first;   // global atom index of the first atom
-    int32_t count;   // atoms in the tile (0 for padding tiles)
-    int32_t idx;     // tile index within its replica
+    int32_t count;   // atoms in the unit
+    int32_t idx;     // unit index within its replica
 };
 
 // Spline tables (device pointers, element type set by precision).
@@ -82,7 +83,6 @@ struct NeighArgs {
     int32_t* rebuild;           // [n_rep] flags
     int32_t* status;
     int N, n_cells, ccap, cap;
-    int n_grid;                 // tiles launched (including padding)
     int n_rep;
     double rl2;                 // (r_cut + skin)^2
     float rl2_f;                // (r_cut + skin + margin)^2 for the single-precision candidate test
@@ -105,13 +105,9 @@ struct StepArgs {
     int cap;
     double* e_emb;          // [N] F(rho_i)
     double* xi;             // [3][N] thermostat noise of this step
-    double* noise_part;     // [tiles][3]
-    double* noise_sum;      // [n_rep][3]
-    double* energy_part;    // [tiles][2]
+    double* noise_part;     // [units][3] thermostat noise summed per unit
+    double* energy_part;    // [units][2] U_EAM and |x - x0|^2 summed per unit
     double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
-    uint32_t* cnt_density;  // [n_rep]
-    uint32_t* cnt_force;    // [n_rep]
-    uint32_t* cnt_all;      // [1]
     int32_t* rebuild;       // [n_rep]
     int32_t* status;
     const double* lam;      // lambda table [S+1]
@@ -131,9 +127,12 @@ struct StepArgs {
     int mode;
     int fix_com;
     int has_eam;
-    int n_tiles;            // real (non-padding) tiles
-    int n_grid;             // tiles including padding
-    int grid_blocks;        // blocks launched for the pair kernels (<= n_grid; multiple of 8)
+    int n_tiles;            // work units (one wavefront's atoms of one replica each)
+    int n_rep;
+    int grid_blocks;        // persistent blocks of the pair kernels (0: fill every resident slot)
+    int n_cu;               // compute units of the device
+    int nq;                 // unit groups (8 with XCD affinity, else 1)
+    int qoff[9];            // units of group q: tiles[qoff[q] .. qoff[q+1])
     int step_kernel;        // 1: integrate; 0: evaluate only (eam_forces)
     double dt;
     double c1;
@@ -168,6 +167,8 @@ int launch_check_displacement(const NeighArgs& a, hipStream_t s);
 int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s);
 int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
+// per-replica energies, dH/dl, work and the iteration counter after a force pass
+int launch_finish(const StepArgs& a, hipStream_t s);
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);
 int launch_adjoint(const AdjointArgs& a, int precision, int grid, hipStream_t s);
 // Coefficient-bin sums -> knot gradients.  out[r][f][k] += w[r] dU_r/dtheta_{f,k}

@@ -19,6 +19,8 @@
 // reproducible.
 #include "eamfe_internal.h"
 
+#include <vector>
+
 namespace eamfe {
 
 constexpr int SB = 4;           // neighbour slots per lane block
@@ -174,67 +176,68 @@ __device__ __forceinline__ int4 row_slab(const int32_t* nbr, int i, int b0, int 
 }
 
 // --------------------------------------------------------------------------
-// Deterministic block reductions
+// Work distribution and deterministic reductions
+//
+// The pair kernels run persistent blocks whose wavefronts each take a fixed
+// stride of work units (one unit = the atoms of one wavefront, 64/T atoms of
+// one replica).  With XCD affinity the units are split into eight groups
+// (the replicas binned to XCD x) and group x is spread over the blocks with
+// blockIdx.x % 8 == x, the blocks the hardware places on XCD x.  Per-replica
+// sums are never finished inside a pass: each unit writes its partial to a
+// fixed slot, and a later kernel (the stream orders them) adds a replica's
+// slots in unit order.  Results therefore do not depend on which wavefront
+// took which unit, and the pair kernels need no atomics or fences.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ int wave_lane() { return (int)(threadIdx.x & 63u); }
+
+// sum over the 64 lanes of a wavefront in a fixed butterfly order
 template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* sh)
+__device__ __forceinline__ void wave_sum(double (&v)[K])
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], o, 64);
-    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < K; ++k) sh[w * K + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < nw; ++q) s += sh[q * K + k];
-            v[k] = s;
-        }
-    }
-    __syncthreads();
 }
 
-// Sum K per-thread values over the block, store the block total as this
-// tile's partial for its replica; the last block of the replica to arrive
-// reduces all partials in tile order into `out` (K values) and returns true
-// in every thread of that block.  Every thread of the block must call it.
+// Store the wavefront's sum of K per-lane values as unit `idx`'s partial.
 template <int K>
-__device__ bool replica_reduce(const double (&vin)[K], double* part, uint32_t* cnt, const RepDesc& R, int tile_idx,
-                               double* out, double* sh)
+__device__ __forceinline__ void unit_partial(const double (&vin)[K], double* part, const RepDesc& R, int idx)
 {
-    __shared__ int last;
     double v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = vin[k];
-    block_sum<K>(v, sh);
-    if (threadIdx.x == 0) {
+    wave_sum<K>(v);
+    if (wave_lane() == 0)
 #pragma unroll
-        for (int k = 0; k < K; ++k) part[(size_t)(R.tile_base + tile_idx) * K + k] = v[k];
-        __threadfence();
-        const uint32_t prev = atomicAdd(cnt, 1u);
-        last = (prev == (uint32_t)(R.n_tiles - 1));
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double s[K];
+        for (int k = 0; k < K; ++k) part[(size_t)(R.tile_base + idx) * K + k] = v[k];
+}
+
+// A replica's total of the partials written by an earlier kernel: lanes take
+// the units in a fixed stride, then a fixed butterfly; every lane gets it.
+template <int K>
+__device__ __forceinline__ void replica_total(const double* part, const RepDesc& R, double (&out)[K])
+{
 #pragma unroll
-    for (int k = 0; k < K; ++k) s[k] = 0.0;
-    for (int t = threadIdx.x; t < R.n_tiles; t += blockDim.x)
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+    for (int t = wave_lane(); t < R.n_tiles; t += 64)
 #pragma unroll
-        for (int k = 0; k < K; ++k) s[k] += part[(size_t)(R.tile_base + t) * K + k];
-    block_sum<K>(s, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) out[k] = s[k];
-        *cnt = 0u;
-    }
-    return true;
+        for (int k = 0; k < K; ++k) out[k] += part[(size_t)(R.tile_base + t) * K + k];
+    wave_sum<K>(out);
+}
+
+// Run body(u) for every unit of this wavefront's stride.  Uniform loop
+// bounds (scalar values) keep the whole body wave-uniform.
+template <typename Body>
+__device__ __forceinline__ void for_each_unit(const int* qoff, int nq, Body&& body)
+{
+    const int wpb = (int)(blockDim.x >> 6);
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int x = nq > 1 ? (int)(blockIdx.x % (unsigned)nq) : 0;
+    const int lb = (int)(blockIdx.x / (unsigned)nq);                 // block index among group x's blocks
+    const int nb = ((int)gridDim.x - x + nq - 1) / nq;             // blocks serving group x
+    const int first = qoff[x], len = qoff[x + 1] - qoff[x];
+    for (int u = lb * wpb + wib; u < len; u += nb * wpb) body(first + u);
 }
 
 // --------------------------------------------------------------------------
@@ -506,23 +509,21 @@ template <typename real, int T>
 __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
-    __shared__ double sh[16 * 3];
     constexpr bool kLds = sizeof(real) == 4;
     constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter : 0;
     const int nr = a.tab.n_r;
-    if (kLds && a.has_eam) {   // table staged once per block; blocks then stride over tiles
+    if (kLds && a.has_eam) {   // table staged once per block; its wavefronts then take units
         const float4* g = (const float4*)a.tab.rho;
         for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
         __syncthreads();
     }
-    for (int tix = blockIdx.x; tix < a.n_grid; tix += gridDim.x) {
+    for_each_unit(a.qoff, a.nq, [&](int tix) {
     const Tile tl = a.tiles[tix];
-    if (tl.count == 0) continue;   // padding tile (uniform in the block)
     const RepDesc& R = a.reps[tl.rep];
-    const int lane = threadIdx.x % T;
-    const int la = threadIdx.x / T;
+    const int lane = wave_lane() % T;
+    const int la = wave_lane() / T;
     const bool valid = la < tl.count;
     const int i = tl.first + (valid ? la : 0);
 
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         if (rho > a.tab.rho_max) atomicOr(a.status, ST_TABLE_RANGE);
         if (!isfinite(rho)) atomicOr(a.status, ST_NONFINITE);
     }
-    if (tl.idx == 0 && threadIdx.x == 0) a.rebuild[tl.rep] = 0;   // lists are current now
+    if (tl.idx == 0 && wave_lane() == 0) a.rebuild[tl.rep] = 0;   // lists are current now
 
     // thermostat noise of step `it` and (fixed centre of mass) its replica sum
     if (a.step_kernel && it < a.it_last) {
@@ -613,10 +614,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
             a.xi[N + i] = z[1];
             a.xi[2 * N + i] = z[2];
         }
-        if (a.fix_com)
-            replica_reduce<3>(z, a.noise_part, a.cnt_density + tl.rep, R, tl.idx, a.noise_sum + 3 * tl.rep, sh);
+        if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
     }
-    }   // tiles
+    });   // units
 }
 
 // --------------------------------------------------------------------------
@@ -640,23 +640,21 @@ template <typename real, int T>
 __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
-    __shared__ double sh[16 * 2];
     constexpr bool kLds = sizeof(real) == 4;
     constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter : 0;
     const int nr = a.tab.n_r;
-    if (kLds && a.has_eam) {   // table staged once per block; blocks then stride over tiles
+    if (kLds && a.has_eam) {   // table staged once per block; its wavefronts then take units
         const float4* g = (const float4*)a.tab.pair;
         for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
         __syncthreads();
     }
-    for (int tix = blockIdx.x; tix < a.n_grid; tix += gridDim.x) {
+    for_each_unit(a.qoff, a.nq, [&](int tix) {
     const Tile tl = a.tiles[tix];
-    if (tl.count == 0) continue;   // padding tile (uniform in the block)
     const RepDesc& R = a.reps[tl.rep];
-    const int lane = threadIdx.x % T;
-    const int la = threadIdx.x / T;
+    const int lane = wave_lane() % T;
+    const int la = wave_lane() / T;
     const bool valid = la < tl.count;
     const int i = tl.first + (valid ? la : 0);
 
@@ -743,6 +741,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         ep += __shfl_xor(ep, o, T);
     }
 
+    // the replica's thermostat noise of this step, from the density pass's unit partials
+    double zsum[3] = {0.0, 0.0, 0.0};
+    if (a.step_kernel && it < a.it_last && a.fix_com) replica_total<3>(a.noise_part, R, zsum);
+
     double e[2] = {0.0, 0.0};   // U_EAM contribution, |x - x0|^2
     if (valid && lane == 0) {
         const double fe[3] = {Acc<real>::fin(f0), Acc<real>::fin(f1), Acc<real>::fin(f2)};
@@ -773,7 +775,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 for (int c = 0; c < 3; ++c) {
                     v[c] += hdt_m * F[c];
                     x[c] += 0.5 * a.dt * v[c];
-                    const double m = a.fix_com ? a.noise_sum[3 * tl.rep + c] * inv_n : 0.0;
+                    const double m = a.fix_com ? zsum[c] * inv_n : 0.0;
                     v[c] = a.c1 * v[c] + R.c2 * (a.xi[c * N + i] - m);
                     x[c] += 0.5 * a.dt * v[c];
                 }
@@ -788,11 +790,38 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         }
     }
 
-    double tot[2];
-    if (replica_reduce<2>(e, a.energy_part, a.cnt_force + tl.rep, R, tl.idx, tot, sh)) {
-        if (threadIdx.x == 0) {
-            a.U_rep[2 * tl.rep] = tot[0];
-            a.U_rep[2 * tl.rep + 1] = tot[1];
+    unit_partial<2>(e, a.energy_part, R, tl.idx);
+    });   // units
+}
+
+// After every force pass: each replica's U_EAM and |x - x0|^2 from the unit
+// partials (fixed order), dH/dl and the work increment of Eq. w_irr, and the
+// iteration counter.  One block; g lanes per replica (the largest power of
+// two up to 64 that fits the block), so all replicas load in parallel.
+__global__ __launch_bounds__(1024) void k_finish(StepArgs a)
+{
+    const int64_t it = a.step_kernel ? *a.iter : 0;
+    int g = 64;
+    while (g > 1 && g * a.n_rep > (int)blockDim.x) g >>= 1;
+    const int grp = (int)threadIdx.x / g, sub = (int)threadIdx.x % g, ngrp = (int)blockDim.x / g;
+    for (int r0 = 0; r0 < a.n_rep; r0 += ngrp) {
+        const int r = r0 + grp;
+        double tot[2] = {0.0, 0.0};
+        if (r < a.n_rep) {
+            const RepDesc& R = a.reps[r];
+            for (int t = sub; t < R.n_tiles; t += g) {
+                tot[0] += a.energy_part[(size_t)(R.tile_base + t) * 2];
+                tot[1] += a.energy_part[(size_t)(R.tile_base + t) * 2 + 1];
+            }
+        }
+        for (int o = g / 2; o > 0; o >>= 1) {
+            tot[0] += __shfl_xor(tot[0], o, g);
+            tot[1] += __shfl_xor(tot[1], o, g);
+        }
+        if (r < a.n_rep && sub == 0) {
+            const RepDesc& R = a.reps[r];
+            a.U_rep[2 * r] = tot[0];
+            a.U_rep[2 * r + 1] = tot[1];
             if (a.step_kernel && it < a.it_last) {
                 const double UE = 0.5 * R.k * tot[1];
                 double dH;
@@ -802,24 +831,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 case MODE_HH: dH = 0.5 * (R.k2 - R.k) * tot[1]; break;
                 default: dH = UE; break;
                 }
-                const double W = a.W_state[tl.rep] + (a.lam[it + 1] - a.lam[it]) * dH;
-                a.W_state[tl.rep] = W;
-                const size_t o = (size_t)tl.rep * a.S + (size_t)(it - a.trace_off);
+                const double W = a.W_state[r] + (a.lam[it + 1] - a.lam[it]) * dH;
+                a.W_state[r] = W;
+                const size_t o = (size_t)r * a.S + (size_t)(it - a.trace_off);
                 if (a.dHdl_out) a.dHdl_out[o] = dH;
                 if (a.W_out) a.W_out[o] = W;
             }
         }
     }
-    // the last block of the whole grid advances the iteration counter
-    if (a.step_kernel && threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(a.cnt_all, 1u);
-        if (prev == (uint32_t)(a.n_tiles - 1)) {
-            *a.iter = it + 1;
-            *a.cnt_all = 0u;
-        }
-    }
-    }   // tiles
+    __syncthreads();   // every thread has read the counter
+    if (a.step_kernel && threadIdx.x == 0) *a.iter = it + 1;
 }
 
 // --------------------------------------------------------------------------
@@ -827,9 +848,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 // --------------------------------------------------------------------------
 __global__ void k_init_v(StepArgs a, int fix_com)
 {
-    __shared__ double sh[16 * 3];
+    // one wavefront (block) per unit, one lane per atom
     const Tile tl = a.tiles[blockIdx.x];
-    if (tl.count == 0) return;
     const RepDesc& R = a.reps[tl.rep];
     const bool valid = (int)threadIdx.x < tl.count;
     const int i = tl.first + (valid ? (int)threadIdx.x : 0);
@@ -842,18 +862,20 @@ __global__ void k_init_v(StepArgs a, int fix_com)
             a.v[c * a.N + i] = z[c];
         }
     }
-    if (fix_com) replica_reduce<3>(z, a.noise_part, a.cnt_density + tl.rep, R, tl.idx, a.noise_sum + 3 * tl.rep, sh);
+    if (fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
 }
 
 __global__ void k_sub_mean_v(StepArgs a)
 {
     const Tile tl = a.tiles[blockIdx.x];
-    if (tl.count == 0 || (int)threadIdx.x >= tl.count) return;
     const RepDesc& R = a.reps[tl.rep];
+    double m[3];
+    replica_total<3>(a.noise_part, R, m);
+    if ((int)threadIdx.x >= tl.count) return;
     const int i = tl.first + threadIdx.x;
     const double inv_n = 1.0 / (double)R.n;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.v[c * a.N + i] -= a.noise_sum[3 * tl.rep + c] * inv_n;
+    for (int c = 0; c < 3; ++c) a.v[c * a.N + i] -= m[c] * inv_n;
 }
 
 // --------------------------------------------------------------------------
@@ -922,22 +944,68 @@ static size_t lds_bytes(const StepArgs& a, int tables)
     return (sizeof(real) == 4 && a.has_eam) ? (size_t)tables * (a.tab.n_r - 1) * sizeof(float4) : 0;
 }
 
-static int pair_grid(const StepArgs& a)
+// Resident blocks per CU of a pair kernel at this block size and LDS use
+// (cached per kernel and shape; the query is host-only).
+static int blocks_per_cu(const void* f, int block, size_t lds)
 {
-    return (a.grid_blocks > 0 && a.grid_blocks < a.n_grid) ? a.grid_blocks : a.n_grid;
+    struct Entry {
+        const void* f;
+        int block;
+        size_t lds;
+        int nb;
+    };
+    static thread_local std::vector<Entry> cache;
+    for (const auto& e : cache)
+        if (e.f == f && e.block == block && e.lds == lds) return e.nb;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds) != hipSuccess || nb < 1) nb = 1;
+    cache.push_back({f, block, lds, nb});
+    return nb;
+}
+
+// Persistent grid: every resident slot of the chip (or the caller's block
+// count), but no more wavefronts than units.
+static int pair_grid(const StepArgs& a, const void* f, int block, size_t lds)
+{
+    const int waves = block / 64;
+    int need = 0;   // blocks that give every unit its own wavefront, per group
+    for (int q = 0; q < a.nq; ++q) {
+        const int len = a.qoff[q + 1] - a.qoff[q];
+        need = need > (len + waves - 1) / waves ? need : (len + waves - 1) / waves;
+    }
+    need *= a.nq;
+    int g = a.grid_blocks > 0 ? a.grid_blocks : a.n_cu * blocks_per_cu(f, block, lds);
+    g = g < need ? g : need;
+    return (g + a.nq - 1) / a.nq * a.nq;   // every group has blocks
+}
+
+template <typename real, int T>
+static void density_one(const StepArgs& a, int block, hipStream_t s)
+{
+    const size_t sh = lds_bytes<real>(a, 1);
+    const void* f = reinterpret_cast<const void*>(&k_density<real, T>);
+    hipLaunchKernelGGL((k_density<real, T>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
+}
+
+template <typename real, int T>
+static void force_one(const StepArgs& a, int block, hipStream_t s)
+{
+    const size_t sh = lds_bytes<real>(a, 2);
+    const void* f = reinterpret_cast<const void*>(&k_force<real, T>);
+    hipLaunchKernelGGL((k_force<real, T>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
 }
 
 template <typename real>
 static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t s)
 {
-    dim3 g(pair_grid(a)), b(block);
-    const size_t sh = lds_bytes<real>(a, 1);
+    if (a.n_tiles <= 0) return 0;
+    if (block < 64 || block > kMaxBlock || block % 64) return (int)hipErrorInvalidValue;
     switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_density<real, 1>), g, b, sh, s, a); break;
-    case 2: hipLaunchKernelGGL((k_density<real, 2>), g, b, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((k_density<real, 4>), g, b, sh, s, a); break;
-    case 8: hipLaunchKernelGGL((k_density<real, 8>), g, b, sh, s, a); break;
-    case 16: hipLaunchKernelGGL((k_density<real, 16>), g, b, sh, s, a); break;
+    case 1: density_one<real, 1>(a, block, s); break;
+    case 2: density_one<real, 2>(a, block, s); break;
+    case 4: density_one<real, 4>(a, block, s); break;
+    case 8: density_one<real, 8>(a, block, s); break;
+    case 16: density_one<real, 16>(a, block, s); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
@@ -946,16 +1014,23 @@ static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t
 template <typename real>
 static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s)
 {
-    dim3 g(pair_grid(a)), b(block);
-    const size_t sh = lds_bytes<real>(a, 2);
+    if (a.n_tiles <= 0) return 0;
+    if (block < 64 || block > kMaxBlock || block % 64) return (int)hipErrorInvalidValue;
     switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_force<real, 1>), g, b, sh, s, a); break;
-    case 2: hipLaunchKernelGGL((k_force<real, 2>), g, b, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((k_force<real, 4>), g, b, sh, s, a); break;
-    case 8: hipLaunchKernelGGL((k_force<real, 8>), g, b, sh, s, a); break;
-    case 16: hipLaunchKernelGGL((k_force<real, 16>), g, b, sh, s, a); break;
+    case 1: force_one<real, 1>(a, block, s); break;
+    case 2: force_one<real, 2>(a, block, s); break;
+    case 4: force_one<real, 4>(a, block, s); break;
+    case 8: force_one<real, 8>(a, block, s); break;
+    case 16: force_one<real, 16>(a, block, s); break;
     default: return (int)hipErrorInvalidValue;
     }
+    return (int)hipGetLastError();
+}
+
+int launch_finish(const StepArgs& a, hipStream_t s)
+{
+    if (a.n_rep <= 0) return 0;
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a);
     return (int)hipGetLastError();
 }
 
@@ -972,9 +1047,10 @@ int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStre
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s)
 {
     (void)n_rep;
-    // tiles hold at most block/lanes <= 1024 atoms; one thread per atom
-    hipLaunchKernelGGL(k_init_v, dim3(a.n_grid), dim3(kMaxBlock), 0, s, a, fix_com);
-    if (fix_com) hipLaunchKernelGGL(k_sub_mean_v, dim3(a.n_grid), dim3(kMaxBlock), 0, s, a);
+    // units hold at most 64 atoms; one wavefront per unit, one lane per atom
+    if (a.n_tiles <= 0) return 0;
+    hipLaunchKernelGGL(k_init_v, dim3(a.n_tiles), dim3(64), 0, s, a, fix_com);
+    if (fix_com) hipLaunchKernelGGL(k_sub_mean_v, dim3(a.n_tiles), dim3(64), 0, s, a);
     return (int)hipGetLastError();
 }
 
