@@ -49,7 +49,7 @@ struct eamfe_ctx {
     int qoff[9] = {0};         // group q holds tiles[qoff[q] .. qoff[q+1])
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, status_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, status_d;
 
     // neighbour lists
     bool have_list = false;
@@ -310,6 +310,7 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
     a.nbr = (int32_t*)c->nbr_d.p;
     a.nnb = (int32_t*)c->nnb_d.p;
     a.rebuild = (int32_t*)c->rebuild_d.p;
+    a.flag_pre = (int32_t*)c->flag_pre_d.p;
     a.status = (int32_t*)c->status_d.p;
     a.N = c->N;
     a.n_cells = c->n_cells;
@@ -344,6 +345,7 @@ StepArgs step_args(eamfe_ctx* c)
     a.energy_part = (double*)c->energy_part_d.p;
     a.U_rep = (double*)c->U_rep_d.p;
     a.rebuild = (int32_t*)c->rebuild_d.p;
+    a.flag_pre = (int32_t*)c->flag_pre_d.p;
     a.status = (int32_t*)c->status_d.p;
     a.iter = (int64_t*)c->iter_d.p;
     a.W_state = (double*)c->W_state_d.p;
@@ -462,6 +464,7 @@ int set_rebuild_all(eamfe_ctx* c)
     hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream, (int32_t*)c->rebuild_d.p,
                        c->n_rep, 1);
     HIPCHK(c, hipGetLastError());
+    LCHK(c, launch_flag_prefix(neigh_args(c, PA(c)), c->stream));
     return EAMFE_OK;
 }
 
@@ -537,6 +540,7 @@ int ensure_lists(eamfe_ctx* c, double skin, const double4* P)
     } else {
         NeighArgs na = neigh_args(c, P);
         LCHK(c, launch_check_displacement(na, c->stream));
+        LCHK(c, launch_flag_prefix(na, c->stream));
     }
     return EAMFE_OK;
 }
@@ -776,7 +780,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->status_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->status_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -961,6 +965,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->U_rep_d, (size_t)n_rep * 2 * sizeof(double)));
     OK(ensure(c, c->W_state_d, (size_t)n_rep * sizeof(double)));
     OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
+    OK(ensure(c, c->flag_pre_d, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
@@ -973,6 +978,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->U_rep_d.p, 0, (size_t)n_rep * 2 * sizeof(double)));
     HIPCHK(c, hipMemset(c->W_state_d.p, 0, (size_t)n_rep * sizeof(double)));
     HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
+    HIPCHK(c, hipMemset(c->flag_pre_d.p, 0, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
     c->have_list = false;
     return build_tiles(c);
 }
@@ -994,6 +1000,7 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
         hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
                            (int32_t*)c->rebuild_d.p, c->n_rep, 0);
         HIPCHK(c, hipGetLastError());
+        LCHK(c, launch_flag_prefix(neigh_args(c, PA(c)), c->stream));
         if (max_neighbors > 0 || attempt >= 6) break;
         // automatic capacity: enlarge rows or bins until this configuration fits
         HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -81,6 +81,7 @@ struct NeighArgs {
     int32_t* nbr;               // [N][cap] global atom ids
     int32_t* nnb;               // [N]
     int32_t* rebuild;           // [n_rep] flags
+    int32_t* flag_pre;          // [2 (n_rep + 1)] prefix of flagged atoms, then of flagged cells
     int32_t* status;
     int N, n_cells, ccap, cap;
     int n_rep;
@@ -109,6 +110,7 @@ struct StepArgs {
     double* energy_part;    // [units][2] U_EAM and |x - x0|^2 summed per unit
     double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
     int32_t* rebuild;       // [n_rep]
+    int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix for the next list pass (written by k_finish)
     int32_t* status;
     const double* lam;      // lambda table [S+1]
     int64_t* iter;          // device iteration counter (global step index)
@@ -165,6 +167,8 @@ int launch_pack(double4* P, uint4* Q, const double* x, const int32_t* rep_of, co
 int launch_unpack(double* x, const double4* P, int N, hipStream_t s);
 int launch_check_displacement(const NeighArgs& a, hipStream_t s);
 int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s);
+// prefix of the flagged replicas' atoms and cells (after the flags change on the host side)
+int launch_flag_prefix(const NeighArgs& a, hipStream_t s);
 int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 // per-replica energies, dH/dl, work and the iteration counter after a force pass

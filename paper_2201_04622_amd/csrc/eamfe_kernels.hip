@@ -296,6 +296,73 @@ __device__ __forceinline__ double3 sep(const RepDesc& R, const double4& a, const
 // every row is the in-order concatenation of the 27 surrounding cells'
 // members within r_cut + skin, so rows have a fixed order.
 // --------------------------------------------------------------------------
+// Prefix sums over the replicas of the atoms and of the cells to rebuild:
+// pre[r] (atoms of flagged replicas before r), pre[n_rep + 1 + r] (cells of
+// flagged replicas before r), totals at index n_rep and 2 n_rep + 1.  One
+// block (any size, multiple of 64); the list kernels take their work items
+// from these, so each of them needs no pass over all atoms or cells.
+__device__ void flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_rep, int32_t* pre)
+{
+    __shared__ int wa[16], wc[16];
+    const int lw = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int ca = 0, cc = 0;
+    for (int base = 0; base < n_rep; base += blockDim.x) {
+        const int r = base + threadIdx.x;
+        int va = 0, vc = 0;
+        if (r < n_rep && rebuild[r]) {
+            va = reps[r].n;
+            vc = reps[r].nc[0] * reps[r].nc[1] * reps[r].nc[2];
+        }
+        int xa = va, xc = vc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int ya = __shfl_up(xa, o, 64), yc = __shfl_up(xc, o, 64);
+            if (lw >= o) {
+                xa += ya;
+                xc += yc;
+            }
+        }
+        if (lw == 63) {
+            wa[w] = xa;
+            wc[w] = xc;
+        }
+        __syncthreads();
+        int oa = 0, oc = 0, ta = 0, tc = 0;
+        for (int q = 0; q < nw; ++q) {
+            oa += q < w ? wa[q] : 0;
+            oc += q < w ? wc[q] : 0;
+            ta += wa[q];
+            tc += wc[q];
+        }
+        if (r < n_rep) {
+            pre[r] = ca + oa + xa - va;
+            pre[n_rep + 1 + r] = cc + oc + xc - vc;
+        }
+        ca += ta;
+        cc += tc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pre[n_rep] = ca;
+        pre[2 * n_rep + 1] = cc;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_flag_prefix(NeighArgs a) { flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre); }
+
+// Replica holding work item f of a prefix p[0..n_rep]: p[r] <= f < p[r+1]
+// (replicas with no items are skipped by taking the last such r).
+__device__ __forceinline__ int item_replica(const int32_t* p, int n_rep, int f)
+{
+    int lo = 0, hi = n_rep;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (p[mid] <= f) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void k_check_displacement(NeighArgs a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -313,31 +380,38 @@ __device__ __forceinline__ int cell_coord(double x, double L, double invL, int n
     return c >= nc ? nc - 1 : c;
 }
 
+// Binning of the flagged replicas' atoms (work items from the prefix).
 __global__ void k_bin(NeighArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const int r = a.rep_of[i];
-    if (!a.rebuild[r]) return;
-    const RepDesc& R = a.reps[r];
-    if (R.nc[0] == 0) return;
-    const uint4 q = a.Q[i];
-    const int cx = box_cell(q.x, R.nc[0]), cy = box_cell(q.y, R.nc[1]), cz = box_cell(q.z, R.nc[2]);
-    const int c = R.cell_base + (cx * R.nc[1] + cy) * R.nc[2] + cz;
-    const int slot = atomicAdd(&a.cell_cnt[c], 1);
-    if (slot < a.ccap)
-        a.cell_atoms[(size_t)c * a.ccap + slot] = i - R.off;
-    else
-        atomicOr(a.status, ST_CELL_OVERFLOW);
+    const int32_t* pre = a.flag_pre;
+    const int total = pre[a.n_rep];
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < total; f += gridDim.x * blockDim.x) {
+        const int r = item_replica(pre, a.n_rep, f);
+        const RepDesc& R = a.reps[r];
+        if (R.nc[0] == 0) continue;   // all-pairs rows: no cells
+        const int il = f - pre[r];
+        const uint4 q = a.Q[R.off + il];
+        const int c = R.cell_base + (box_cell(q.x, R.nc[0]) * R.nc[1] + box_cell(q.y, R.nc[1])) * R.nc[2] +
+                      box_cell(q.z, R.nc[2]);
+        const int slot = atomicAdd(&a.cell_cnt[c], 1);
+        if (slot < a.ccap)
+            a.cell_atoms[(size_t)c * a.ccap + slot] = il;
+        else
+            atomicOr(a.status, ST_CELL_OVERFLOW);
+    }
 }
 
-// One 64-thread block per cell (grid-stride): bitonic sort of the cell's
-// atom ids in LDS, occupancy copied to cell_n, bin counter reset.
+// Sorting of the flagged replicas' cells: 64-thread blocks take the cells
+// (work items from the prefix) in a stride; a cell's atom ids are sorted in
+// LDS (bitonic), the occupancy copied to cell_n and the bin counter reset.
 __global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
 {
     extern __shared__ int32_t sv[];
-    for (int c = blockIdx.x; c < a.n_cells; c += gridDim.x) {
-        if (!a.rebuild[a.cell_rep[c]]) continue;   // uniform in the block
+    const int32_t* pre = a.flag_pre + a.n_rep + 1;
+    const int total = pre[a.n_rep];
+    for (int f = blockIdx.x; f < total; f += gridDim.x) {
+        const int r = item_replica(pre, a.n_rep, f);
+        const int c = a.reps[r].cell_base + (f - pre[r]);
         int n = a.cell_cnt[c];
         n = n > a.ccap ? a.ccap : n;
         int32_t* p = a.cell_atoms + (size_t)c * a.ccap;
@@ -370,82 +444,56 @@ __global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
 }
 
 // Rows: one wavefront per atom of a flagged replica (waves of the whole grid
-// stride over the flagged atoms; each block first forms the prefix of
-// flagged replica sizes in LDS).  The 27 stencil cells' members form one
+// stride over the flagged atoms, work items from the prefix).  The 27 stencil cells' members form one
 // candidate stream in a fixed order (cells by offset, atoms by id); each pass
 // tests 64 candidates with exact minimum-image box coordinates and appends
-// the accepted ones in stream order (ballot + prefix count).
+// the accepted ones in stream order (ballot + prefix count) to a row buffer
+// in LDS, which is written out as whole 16-byte slabs at the end (row stores
+// inside the loop would make every pass's loads wait for them).
 constexpr int kListBlock = 256;
 constexpr int kListGrid = 1024;
 
 __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 {
-    __shared__ int pre[kMaxRepsList + 1];
-    __shared__ int wsum[kListBlock / 64];
+    extern __shared__ int rowbuf[];             // [waves][cap] accepted ids of each wavefront's atom
     __shared__ int cend[kListBlock / 64][28];   // per wave: inclusive prefix of stencil cell sizes
     __shared__ int cid[kListBlock / 64][28];    // per wave: global stencil cell ids
     const int lw = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int carry = 0;
-    for (int base = 0; base < n_rep; base += kListBlock) {
-        const int r = base + threadIdx.x;
-        const int v = (r < n_rep && a.rebuild[r]) ? a.reps[r].n : 0;
-        int x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lw >= o) x += y;
-        }
-        if (lw == 63) wsum[w] = x;
-        __syncthreads();
-        int off = 0, tot = 0;
-#pragma unroll
-        for (int q = 0; q < kListBlock / 64; ++q) {
-            off += q < w ? wsum[q] : 0;
-            tot += wsum[q];
-        }
-        if (r < n_rep) pre[r] = carry + off + x - v;
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) pre[n_rep] = carry;
-    __syncthreads();
+    const int cap = a.cap, N = a.N;
+    const float rl2 = a.rl2_f;
+    int* row = rowbuf + (size_t)w * cap;
+    const int32_t* pre = a.flag_pre;
     const int total = pre[n_rep];
-    if (total == 0) return;
-
     const uint64_t below = (1ull << lw) - 1ull;
     const int waves = gridDim.x * (kListBlock / 64);
     for (int f = blockIdx.x * (kListBlock / 64) + w; f < total; f += waves) {
-        int lo = 0, hi = n_rep;   // replica holding flagged atom f: pre[lo] <= f < pre[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pre[mid] <= f) lo = mid;
-            else hi = mid;
-        }
+        const int lo = item_replica(pre, n_rep, f);
         const RepDesc& R = a.reps[lo];
+        const int roff = R.off, rn = R.n;
         const int il = f - pre[lo];
-        const int i = R.off + il;
+        const int i = roff + il;
         const uint4 qi = a.Q[i];
         const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
                     sz = (float)(R.L[2] * 2.3283064365386963e-10);
         int cnt = 0;
         auto test = [&](int jl) {
-            const uint4 qj = a.Q[R.off + jl];
+            const uint4 qj = a.Q[roff + jl];
             const float dx = (float)(int)(qi.x - qj.x) * sx, dy = (float)(int)(qi.y - qj.y) * sy,
                         dz = (float)(int)(qi.z - qj.z) * sz;
-            return jl != il && dx * dx + dy * dy + dz * dz < a.rl2_f;
+            return jl != il && dx * dx + dy * dy + dz * dz < rl2;
         };
         auto append = [&](bool acc, int j) {
             const uint64_t m = __ballot(acc);
             const int rank = __popcll(m & below);
-            if (acc && cnt + rank < a.cap) a.nbr[slot_index(i, cnt + rank, a.N)] = j;
+            if (acc && cnt + rank < cap) row[cnt + rank] = j;
             cnt += __popcll(m);
         };
         if (R.nc[0] == 0) {
-            for (int s0 = 0; s0 < R.n; s0 += 64) {
+            for (int s0 = 0; s0 < rn; s0 += 64) {
                 const int jl = s0 + lw;
-                append(jl < R.n && test(jl), R.off + jl);
+                append(jl < rn && test(jl), roff + jl);
             }
-        } else {
+        } else {   // cells
             const int cx = box_cell(qi.x, R.nc[0]), cy = box_cell(qi.y, R.nc[1]), cz = box_cell(qi.z, R.nc[2]);
             int n_c = 0, c = 0;
             if (lw < 27) {
@@ -467,38 +515,56 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
             }
             __builtin_amdgcn_wave_barrier();
             const int tot_c = __shfl(incl, 26, 64);
-            for (int k0 = 0; k0 < tot_c; k0 += 64) {
-                const int k = k0 + lw;
-                bool acc = false;
-                int j = 0;
-                if (k < tot_c) {
-                    int q = 0;   // first stencil cell whose inclusive end exceeds k
+            // four passes per iteration: their independent loads are in flight together
+            constexpr int U = 4;
+            for (int k0 = 0; k0 < tot_c; k0 += 64 * U) {
+                int jl[U];
+                uint4 qj[U];
 #pragma unroll
-                    for (int step = 16; step > 0; step >>= 1)
-                        if (q + step <= 26 && cend[w][q + step - 1] <= k) q += step;
-                    const int slot = k - (q ? cend[w][q - 1] : 0);
-                    const int jl = a.cell_atoms[(size_t)cid[w][q] * a.ccap + slot];
-                    j = R.off + jl;
-                    acc = test(jl);
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + 64 * u + lw;
+                    jl[u] = -1;
+                    if (k < tot_c) {
+                        int q = 0;   // first stencil cell whose inclusive end exceeds k
+#pragma unroll
+                        for (int step = 16; step > 0; step >>= 1)
+                            if (q + step <= 26 && cend[w][q + step - 1] <= k) q += step;
+                        const int slot = k - (q ? cend[w][q - 1] : 0);
+                        jl[u] = a.cell_atoms[(size_t)cid[w][q] * a.ccap + slot];
+                    }
                 }
-                append(acc, j);
+#pragma unroll
+                for (int u = 0; u < U; ++u) qj[u] = a.Q[roff + (jl[u] < 0 ? il : jl[u])];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const float dx = (float)(int)(qi.x - qj[u].x) * sx, dy = (float)(int)(qi.y - qj[u].y) * sy,
+                                dz = (float)(int)(qi.z - qj[u].z) * sz;
+                    const bool acc = jl[u] >= 0 && jl[u] != il && dx * dx + dy * dy + dz * dz < rl2;
+                    append(acc, roff + jl[u]);
+                }
             }
-            __builtin_amdgcn_wave_barrier();
         }
-        // pad the last slab with the atom itself (cap is a multiple of 32)
-        const int pad_end = min((cnt + 3) & ~3, a.cap);
-        if (cnt + lw < pad_end) a.nbr[slot_index(i, cnt + lw, a.N)] = i;
+        // pad the last slab with the atom itself (cap is a multiple of 32), then
+        // write the row as whole slabs
+        const int used = cnt < cap ? cnt : cap;
+        const int pad_end = min((used + 3) & ~3, cap);
+        if (used + lw < pad_end) row[used + lw] = i;
+        __builtin_amdgcn_wave_barrier();
+        for (int b = lw; 4 * b < pad_end; b += 64)
+            *(int4*)(a.nbr + ((size_t)b * (size_t)N + (size_t)i) * 4) =
+                make_int4(row[4 * b], row[4 * b + 1], row[4 * b + 2], row[4 * b + 3]);
         if (lw == 0) {
-            if (cnt > a.cap) {
+            if (cnt > cap) {
                 atomicOr(a.status, ST_NEIGH_OVERFLOW);
-                cnt = a.cap;
+                cnt = cap;
             }
             a.nnb[i] = cnt;
             const double4 pi = a.P[i];
             a.xref[i] = pi.x;
-            a.xref[a.N + i] = pi.y;
-            a.xref[2 * a.N + i] = pi.z;
+            a.xref[N + i] = pi.y;
+            a.xref[2 * N + i] = pi.z;
         }
+        __builtin_amdgcn_wave_barrier();   // the row buffer is reused by the next atom
     }
 }
 
@@ -841,6 +907,8 @@ __global__ __launch_bounds__(1024) void k_finish(StepArgs a)
     }
     __syncthreads();   // every thread has read the counter
     if (a.step_kernel && threadIdx.x == 0) *a.iter = it + 1;
+    // rebuild work of the next iteration, from the flags this force pass set
+    if (a.flag_pre) flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
 }
 
 // --------------------------------------------------------------------------
@@ -905,19 +973,29 @@ int launch_check_displacement(const NeighArgs& a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
+int launch_flag_prefix(const NeighArgs& a, hipStream_t s)
+{
+    if (a.n_rep <= 0) return 0;
+    hipLaunchKernelGGL(k_flag_prefix, dim3(1), dim3(1024), 0, s, a);
+    return (int)hipGetLastError();
+}
+
 int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s)
 {
     if (a.N <= 0) return 0;
-    hipLaunchKernelGGL(k_bin, dim3(grid1(a.N, 256)), dim3(256), 0, s, a);
     if (a.n_cells > 0) {
+        // a replica's atoms or cells spread over the grid; replicas are walked in turn
+        hipLaunchKernelGGL(k_bin, dim3(256), dim3(256), 0, s, a);
         int p2 = 1;
         while (p2 < a.ccap) p2 <<= 1;
-        hipLaunchKernelGGL(k_cellsort, dim3(a.n_cells < 4096 ? a.n_cells : 4096), dim3(64), p2 * sizeof(int32_t), s,
-                           a);
+        hipLaunchKernelGGL(k_cellsort, dim3(1024), dim3(64), p2 * sizeof(int32_t), s, a);
     }
     (void)lanes;
     (void)block;
-    hipLaunchKernelGGL(k_list, dim3(kListGrid), dim3(kListBlock), 0, s, a, a.n_rep);
+    // one row buffer per wavefront
+    const size_t lds = (size_t)((kListBlock / 64) * a.cap) * sizeof(int);
+    if (lds > 64 * 1024) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_list, dim3(kListGrid), dim3(kListBlock), lds, s, a, a.n_rep);
     return (int)hipGetLastError();
 }
 
