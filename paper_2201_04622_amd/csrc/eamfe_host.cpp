@@ -49,7 +49,7 @@ struct eamfe_ctx {
     int qoff[9] = {0};         // group q holds tiles[qoff[q] .. qoff[q+1])
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, status_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d;
 
     // neighbour lists
     bool have_list = false;
@@ -346,6 +346,7 @@ StepArgs step_args(eamfe_ctx* c)
     a.U_rep = (double*)c->U_rep_d.p;
     a.rebuild = (int32_t*)c->rebuild_d.p;
     a.flag_pre = (int32_t*)c->flag_pre_d.p;
+    a.pending = (int32_t*)c->pending_d.p;
     a.status = (int32_t*)c->status_d.p;
     a.iter = (int64_t*)c->iter_d.p;
     a.W_state = (double*)c->W_state_d.p;
@@ -464,7 +465,6 @@ int set_rebuild_all(eamfe_ctx* c)
     hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream, (int32_t*)c->rebuild_d.p,
                        c->n_rep, 1);
     HIPCHK(c, hipGetLastError());
-    LCHK(c, launch_flag_prefix(neigh_args(c, PA(c)), c->stream));
     return EAMFE_OK;
 }
 
@@ -540,7 +540,6 @@ int ensure_lists(eamfe_ctx* c, double skin, const double4* P)
     } else {
         NeighArgs na = neigh_args(c, P);
         LCHK(c, launch_check_displacement(na, c->stream));
-        LCHK(c, launch_flag_prefix(na, c->stream));
     }
     return EAMFE_OK;
 }
@@ -610,7 +609,10 @@ int mark(eamfe_ctx* c, int kind, int end)
 // Iterations it_first .. it_last of a protocol starting from packed
 // positions *cur (one of the two internal buffers); on return *cur is the
 // buffer holding the final positions.
-// One MD iteration on stream st: list upkeep, density pass, force pass.
+// One MD iteration on stream st: list upkeep (whose first kernel finishes
+// the previous iteration's force pass), density pass, force pass.  Without
+// EAM there is no list pass and the force pass is finished at once; with it
+// the caller finishes the last iteration's force pass.
 int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool has_eam, hipStream_t st, bool sample,
                   int64_t it)
 {
@@ -618,7 +620,7 @@ int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool ha
     if (has_eam) {
         NeighArgs na = neigh_args(c, cur);
         OK(mark(c, 2, 0));
-        LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, st));
+        LCHK(c, launch_neigh_rebuild(na, a, c->lanes, c->block, st));
         OK(mark(c, 2, 1));
     }
     a.P = cur;
@@ -635,7 +637,7 @@ int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool ha
     }
     OK(mark(c, 1, 0));
     LCHK(c, launch_force(a, c->precision, c->lanes, c->block, st));
-    LCHK(c, launch_finish(a, st));
+    if (!has_eam) LCHK(c, launch_finish(a, st));
     OK(mark(c, 1, 1));
     return EAMFE_OK;
 }
@@ -716,6 +718,7 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
         std::swap(cur, nxt);
         ++it;
     }
+    if (has_eam && it > it_first) LCHK(c, launch_finish(a, c->stream));   // the last force pass
     *cur_io = cur;
     return EAMFE_OK;
 }
@@ -780,7 +783,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->status_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -966,6 +969,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->W_state_d, (size_t)n_rep * sizeof(double)));
     OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
     OK(ensure(c, c->flag_pre_d, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
+    OK(ensure(c, c->pending_d, sizeof(int32_t)));
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
@@ -979,6 +983,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->W_state_d.p, 0, (size_t)n_rep * sizeof(double)));
     HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->flag_pre_d.p, 0, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
+    HIPCHK(c, hipMemset(c->pending_d.p, 0, sizeof(int32_t)));
     c->have_list = false;
     return build_tiles(c);
 }
@@ -995,12 +1000,11 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
     for (int attempt = 0;; ++attempt) {
         OK(set_rebuild_all(c));
         NeighArgs na = neigh_args(c, PA(c));
-        LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+        LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
         // the flags are cleared by the next density pass; clear them here too
         hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
                            (int32_t*)c->rebuild_d.p, c->n_rep, 0);
         HIPCHK(c, hipGetLastError());
-        LCHK(c, launch_flag_prefix(neigh_args(c, PA(c)), c->stream));
         if (max_neighbors > 0 || attempt >= 6) break;
         // automatic capacity: enlarge rows or bins until this configuration fits
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1024,7 +1028,7 @@ int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_at
     OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
     for (int attempt = 0;; ++attempt) {
         NeighArgs na = neigh_args(c, PA(c));
-        LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+        LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
         StepArgs a = step_args(c);
         a.P = PA(c);
         a.Pn = nullptr;
@@ -1237,7 +1241,7 @@ int eamfe_adjoint_theta(eamfe_ctx* c, const double* x, const double* w_host, int
     OK(pack(c, x));
     OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
     NeighArgs na = neigh_args(c, PA(c));
-    LCHK(c, launch_neigh_rebuild(na, c->lanes, c->block, c->stream));
+    LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
     StepArgs a = step_args(c);
     a.P = PA(c);
     a.Q = QA(c);

@@ -110,7 +110,8 @@ struct StepArgs {
     double* energy_part;    // [units][2] U_EAM and |x - x0|^2 summed per unit
     double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
     int32_t* rebuild;       // [n_rep]
-    int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix for the next list pass (written by k_finish)
+    int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix (formed by the list pass's first kernel)
+    int32_t* pending;       // [1] 1 while a force pass of a step awaits its finish
     int32_t* status;
     const double* lam;      // lambda table [S+1]
     int64_t* iter;          // device iteration counter (global step index)
@@ -166,12 +167,13 @@ int launch_pack(double4* P, uint4* Q, const double* x, const int32_t* rep_of, co
                 hipStream_t s);
 int launch_unpack(double* x, const double4* P, int N, hipStream_t s);
 int launch_check_displacement(const NeighArgs& a, hipStream_t s);
-int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s);
-// prefix of the flagged replicas' atoms and cells (after the flags change on the host side)
-int launch_flag_prefix(const NeighArgs& a, hipStream_t s);
+// List pass.  Its first kernel also forms the prefix of the flagged replicas
+// and finishes the force pass before it when that is due (st.pending).
+int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int block, hipStream_t s);
 int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
-// per-replica energies, dH/dl, work and the iteration counter after a force pass
+// per-replica energies, dH/dl, work and the iteration counter after a force
+// pass that no list pass follows
 int launch_finish(const StepArgs& a, hipStream_t s);
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);
 int launch_adjoint(const AdjointArgs& a, int precision, int grid, hipStream_t s);

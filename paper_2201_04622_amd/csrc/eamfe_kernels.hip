@@ -1,22 +1,27 @@
 // gfx950 kernels of the EAM switching engine.
 //
-// One MD iteration is two launches over a table of tiles (a tile = a run of
-// atoms of one replica; every replica of the batch is in the same launch):
+// One MD iteration of a batch (every replica in the same launches):
 //
-//   k_density : rho_i = sum_j rho(r_ij) over the Verlet row, F(rho_i), F'(rho_i),
-//               and the thermostat noise of the step with its replica sum;
-//   k_force   : pair + embedding forces, the Einstein spring, the lambda blend
-//               (Eq. interp) or scale (Eq. H_rs), the closing B half-kick of the
-//               previous step and B-A-O-A of the next one (BAOAB), per-replica
-//               energy sums, dH/dl, and the work increment (Eq. w_irr).
+//   k_bin      : finish of the previous force pass (replica energies, dH/dl,
+//                the work increment of Eq. w_irr, iteration counter) and the
+//                prefix of the replicas whose lists are due, in block 0;
+//                binning of those replicas' atoms into cells in the others;
+//   k_cellsort : each due cell's atom ids sorted, so rows have a fixed order;
+//   k_list     : Verlet rows within r_cut + skin, one wavefront per atom;
+//   k_density  : rho_i = sum_j rho(r_ij) over the row, F(rho_i), F'(rho_i),
+//                and the thermostat noise of the step with its replica sum;
+//   k_force    : pair + embedding forces, the Einstein spring, the lambda
+//                blend (Eq. interp) or scale (Eq. H_rs), the closing B
+//                half-kick of the previous step and B-A-O-A of the next one
+//                (BAOAB), per-unit energy partials and the list-due flags.
 //
-// T lanes cooperate on one atom; lane t takes blocks of SB consecutive
-// neighbour slots t, t+T, ...  In FP32 each block's partial sum is rounded
-// to a 2^-32 grid and added as an exact integer held in a float64, so the
-// per-atom sums do not depend on T or on the block size.  List rows have a
-// fixed order (cells sorted by atom id) and per-replica reductions use a
-// fixed tree and a "last block finishes" pass, so runs are bitwise
-// reproducible.
+// The pair kernels run a persistent grid over work units (one wavefront's
+// atoms of one replica); T lanes cooperate on one atom, lane t taking blocks
+// of SB consecutive neighbour slots t, t+T, ...  In FP32 each block's
+// partial sum is rounded to a 2^-32 grid and added as an exact integer held
+// in a float64, so the per-atom sums do not depend on T or on the block
+// size.  Rows have a fixed order and per-replica sums are taken over unit
+// partials in a fixed order, so runs are bitwise reproducible.
 #include "eamfe_internal.h"
 
 #include <vector>
@@ -348,8 +353,6 @@ __device__ void flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_r
     }
 }
 
-__global__ __launch_bounds__(1024) void k_flag_prefix(NeighArgs a) { flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre); }
-
 // Replica holding work item f of a prefix p[0..n_rep]: p[r] <= f < p[r+1]
 // (replicas with no items are skipped by taking the last such r).
 __device__ __forceinline__ int item_replica(const int32_t* p, int n_rep, int f)
@@ -380,22 +383,38 @@ __device__ __forceinline__ int cell_coord(double x, double L, double invL, int n
     return c >= nc ? nc - 1 : c;
 }
 
-// Binning of the flagged replicas' atoms (work items from the prefix).
-__global__ void k_bin(NeighArgs a)
+__device__ void finish_body(const StepArgs& a);   // below, with the force pass
+
+// First kernel of a list pass; its blocks take three independent jobs.
+// Block 0 finishes the force pass before it when that is due (replica
+// energies, work, the iteration counter); block 1 forms the prefix of the
+// flagged replicas' atoms and cells that the next two kernels take their
+// work items from; the other blocks bin the atoms of the flagged replicas,
+// one atom per thread with a flag test each (the prefix is not formed yet).
+constexpr int kBinBlock = 1024;
+
+__global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
 {
-    const int32_t* pre = a.flag_pre;
-    const int total = pre[a.n_rep];
-    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < total; f += gridDim.x * blockDim.x) {
-        const int r = item_replica(pre, a.n_rep, f);
+    if (blockIdx.x == 0) {
+        if (*s.pending) finish_body(s);
+        return;
+    }
+    if (blockIdx.x == 1) {
+        flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
+        return;
+    }
+    const int stride = (gridDim.x - 2) * blockDim.x;
+    for (int i = (blockIdx.x - 2) * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+        const int r = a.rep_of[i];
+        if (!a.rebuild[r]) continue;
         const RepDesc& R = a.reps[r];
         if (R.nc[0] == 0) continue;   // all-pairs rows: no cells
-        const int il = f - pre[r];
-        const uint4 q = a.Q[R.off + il];
+        const uint4 q = a.Q[i];
         const int c = R.cell_base + (box_cell(q.x, R.nc[0]) * R.nc[1] + box_cell(q.y, R.nc[1])) * R.nc[2] +
                       box_cell(q.z, R.nc[2]);
         const int slot = atomicAdd(&a.cell_cnt[c], 1);
         if (slot < a.ccap)
-            a.cell_atoms[(size_t)c * a.ccap + slot] = il;
+            a.cell_atoms[(size_t)c * a.ccap + slot] = i - R.off;
         else
             atomicOr(a.status, ST_CELL_OVERFLOW);
     }
@@ -716,6 +735,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
         __syncthreads();
     }
+    if (a.step_kernel && blockIdx.x == 0 && threadIdx.x == 0) *a.pending = 1;   // finish due before the next pass
     for_each_unit(a.qoff, a.nq, [&](int tix) {
     const Tile tl = a.tiles[tix];
     const RepDesc& R = a.reps[tl.rep];
@@ -860,11 +880,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     });   // units
 }
 
-// After every force pass: each replica's U_EAM and |x - x0|^2 from the unit
+// After a force pass: each replica's U_EAM and |x - x0|^2 from the unit
 // partials (fixed order), dH/dl and the work increment of Eq. w_irr, and the
-// iteration counter.  One block; g lanes per replica (the largest power of
-// two up to 64 that fits the block), so all replicas load in parallel.
-__global__ __launch_bounds__(1024) void k_finish(StepArgs a)
+// iteration counter.  Run by one block of any size (multiple of 64), every
+// thread of which calls it: g lanes per replica (the largest power of two up
+// to 64 that fits the block), so the replicas load in parallel.
+__device__ void finish_body(const StepArgs& a)
 {
     const int64_t it = a.step_kernel ? *a.iter : 0;
     int g = 64;
@@ -872,6 +893,10 @@ __global__ __launch_bounds__(1024) void k_finish(StepArgs a)
     const int grp = (int)threadIdx.x / g, sub = (int)threadIdx.x % g, ngrp = (int)blockDim.x / g;
     for (int r0 = 0; r0 < a.n_rep; r0 += ngrp) {
         const int r = r0 + grp;
+        const bool work = r < a.n_rep && sub == 0 && a.step_kernel && it < a.it_last;
+        // loads of the work state go out with the partials' loads
+        const double W0 = work ? a.W_state[r] : 0.0;
+        const double dl = work ? a.lam[it + 1] - a.lam[it] : 0.0;
         double tot[2] = {0.0, 0.0};
         if (r < a.n_rep) {
             const RepDesc& R = a.reps[r];
@@ -888,7 +913,7 @@ __global__ __launch_bounds__(1024) void k_finish(StepArgs a)
             const RepDesc& R = a.reps[r];
             a.U_rep[2 * r] = tot[0];
             a.U_rep[2 * r + 1] = tot[1];
-            if (a.step_kernel && it < a.it_last) {
+            if (work) {
                 const double UE = 0.5 * R.k * tot[1];
                 double dH;
                 switch (a.mode) {
@@ -897,7 +922,7 @@ __global__ __launch_bounds__(1024) void k_finish(StepArgs a)
                 case MODE_HH: dH = 0.5 * (R.k2 - R.k) * tot[1]; break;
                 default: dH = UE; break;
                 }
-                const double W = a.W_state[r] + (a.lam[it + 1] - a.lam[it]) * dH;
+                const double W = W0 + dl * dH;
                 a.W_state[r] = W;
                 const size_t o = (size_t)r * a.S + (size_t)(it - a.trace_off);
                 if (a.dHdl_out) a.dHdl_out[o] = dH;
@@ -906,10 +931,15 @@ __global__ __launch_bounds__(1024) void k_finish(StepArgs a)
         }
     }
     __syncthreads();   // every thread has read the counter
-    if (a.step_kernel && threadIdx.x == 0) *a.iter = it + 1;
-    // rebuild work of the next iteration, from the flags this force pass set
-    if (a.flag_pre) flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
+    if (threadIdx.x == 0) {
+        if (a.step_kernel) *a.iter = it + 1;
+        *a.pending = 0;
+    }
 }
+
+// Finish of a force pass that no list pass follows: evaluation-only passes,
+// the last pass of a range, and the modes without EAM.
+__global__ __launch_bounds__(1024) void k_finish(StepArgs a) { finish_body(a); }
 
 // --------------------------------------------------------------------------
 // Initial velocities: v = sqrt(kT/m) z(stream 1, step 0), centre of mass removed
@@ -973,19 +1003,12 @@ int launch_check_displacement(const NeighArgs& a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
-int launch_flag_prefix(const NeighArgs& a, hipStream_t s)
-{
-    if (a.n_rep <= 0) return 0;
-    hipLaunchKernelGGL(k_flag_prefix, dim3(1), dim3(1024), 0, s, a);
-    return (int)hipGetLastError();
-}
-
-int launch_neigh_rebuild(const NeighArgs& a, int lanes, int block, hipStream_t s)
+int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int block, hipStream_t s)
 {
     if (a.N <= 0) return 0;
+    const int bin_blocks = 2 + std::min(1024, (a.N + kBinBlock - 1) / kBinBlock);
+    hipLaunchKernelGGL(k_bin, dim3(bin_blocks), dim3(kBinBlock), 0, s, a, st);
     if (a.n_cells > 0) {
-        // a replica's atoms or cells spread over the grid; replicas are walked in turn
-        hipLaunchKernelGGL(k_bin, dim3(256), dim3(256), 0, s, a);
         int p2 = 1;
         while (p2 < a.ccap) p2 <<= 1;
         hipLaunchKernelGGL(k_cellsort, dim3(1024), dim3(64), p2 * sizeof(int32_t), s, a);
