@@ -193,13 +193,14 @@ int eam_setup(eamfe_ctx* ctx, int n_r, double r_cut, const double* phi_knots,
 /* ---- system ------------------------------------------------------------ */
 
 /* Describe n_rep replicas (host array, 1 <= n_rep <= 8192) and their lattice
- * sites x0 (device, SoA [3][N_tot], copied).  N_tot = sum n_atoms.  Replaces
- * any previous system. */
+ * sites x0 (device, SoA [3][N_tot], copied).  N_tot = sum n_atoms < 2^28
+ * (EAMFE_EINVAL otherwise).  Replaces any previous system. */
 int eamfe_system_setup(eamfe_ctx* ctx, int n_rep, const eamfe_replica* reps, const double* x0_dev);
 
 /* Build the Verlet lists at positions x (device SoA) with cutoff r_cut+skin:
- * cell binning with cells of edge >= r_cut+skin where a box holds at least
- * three per edge, all-pairs otherwise.  max_neighbors bounds each atom's row
+ * cell binning with cells of edge >= (r_cut+skin)/2 and a 5 x 5 x 5 cell
+ * stencil where a box holds at least five such cells per edge, all-pairs
+ * otherwise.  max_neighbors bounds each atom's row
  * (rounded up to a multiple of 32): a row that does not fit is reported as
  * EAMFE_ENEIGH_OVERFLOW.  With max_neighbors = 0 the capacity is estimated
  * from the densest replica and enlarged until every row (and cell bin) of

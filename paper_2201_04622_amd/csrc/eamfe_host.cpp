@@ -377,11 +377,13 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
                 return fail(c, EAMFE_EBOX, "box edge " + std::to_string(R.L[d]) + " of replica " +
                                                std::to_string(r) + " is not larger than 2 (r_cut + skin)");
         dens_max = std::max(dens_max, R.n / V);
+        // cells of edge >= rl / 2: a 5 x 5 x 5 stencil holds every pair within
+        // rl, and five or more cells per edge keep its cells distinct
         int nc[3];
         bool cells = true;
         for (int d = 0; d < 3; ++d) {
-            nc[d] = (int)std::floor(R.L[d] / rl);
-            if (nc[d] < 3) cells = false;
+            nc[d] = (int)std::floor(2.0 * R.L[d] / rl);
+            if (nc[d] < 5) cells = false;
         }
         R.cell_base = n_cells;
         if (cells) {
@@ -927,7 +929,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
             return fail(c, EAMFE_EINVAL, "replica " + std::to_string(r) + ": bad description");
         N += q.n_atoms;
     }
-    if (N > (1L << 30)) return fail(c, EAMFE_EINVAL, "too many atoms");
+    if (N >= (1L << 28)) return fail(c, EAMFE_EINVAL, "too many atoms (at most 2^28 - 1)");
     c->n_rep = n_rep;
     c->N = (int)N;
     c->reps_in.assign(in, in + n_rep);

@@ -180,6 +180,94 @@ __device__ __forceinline__ int4 row_slab(const int32_t* nbr, int i, int b0, int 
     return *(const int4*)(nbr + ((size_t)(b0 >> 2) * (size_t)N + (size_t)i) * 4);
 }
 
+// Records of one lane block's SB neighbours: box coordinates and F' bits
+// (FP32 form; a 32-bit byte offset from the array base, N < 2^28) or packed
+// positions (FP64 form).
+template <bool kQ>
+struct Nb;
+template <>
+struct Nb<true> {
+    uint4 v[SB];
+};
+template <>
+struct Nb<false> {
+    double4 v[SB];
+};
+
+template <bool kQ>
+__device__ __forceinline__ Nb<kQ> gather(const double4* P, const uint4* Q, int4 j)
+{
+    Nb<kQ> g;
+    const int js[SB] = {j.x, j.y, j.z, j.w};
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+        if constexpr (kQ) g.v[s] = *(const uint4*)((const char*)Q + (uint32_t)js[s] * 16u);
+        else g.v[s] = P[js[s]];
+    }
+    return g;
+}
+
+// One lane's walk over the row of atom i (n slots): its blocks k = 0..nb-1
+// hold slots lane SB + k T SB .. + SB - 1 (slab lane + k T).  Software
+// pipeline: while block k is computed, the ids of block k+2 and (FP32 form;
+// the FP64 records are too large to hold twice) the records of block k+1
+// are in flight, so a wavefront does not wait on memory between blocks.
+// Each iteration issues the slab load before the gathers, so the next
+// iteration's wait for the ids does not also wait for those gathers.  Past
+// the end the last block's slab and records are read again (in bounds,
+// unused).  The scheduling barrier keeps the loads ahead of the arithmetic
+// they overlap.
+template <bool kQ, int T, typename Body>
+__device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, const uint4* Q, int N, int i,
+                                         int lane, int n, Body&& body)
+{
+    const int first = lane * SB;
+    if (first >= n) return;
+    const int nb = (n - first + T * SB - 1) / (T * SB);
+    const size_t str = (size_t)T * N;
+    const int4* slab = (const int4*)nbr + (size_t)lane * N + i;
+    const int4* last = slab + (size_t)(nb - 1) * str;
+    if constexpr (kQ) {
+        // two record buffers in turn (no copies between iterations)
+        // both slab loads ahead of the first gathers, as in the loop, so the
+        // loop's waits on entry are the same as on its back edge
+        const int4 id0 = slab[0];
+        const int4* pn = nb > 1 ? slab + str : last;   // slab of block k+1
+        int4 ids = *pn;
+        __builtin_amdgcn_sched_barrier(0);
+        Nb<true> A = gather<true>(P, Q, id0), B;
+        for (int k = 0;;) {
+            int4 idn = ids;
+            pn = pn == last ? last : pn + str;          // block k+2
+            ids = *pn;
+            __builtin_amdgcn_sched_barrier(0);
+            B = gather<true>(P, Q, idn);
+            __builtin_amdgcn_sched_barrier(0);
+            body(A, first + k * T * SB);
+            if (++k == nb) break;
+            idn = ids;
+            pn = pn == last ? last : pn + str;
+            ids = *pn;
+            __builtin_amdgcn_sched_barrier(0);
+            A = gather<true>(P, Q, idn);
+            __builtin_amdgcn_sched_barrier(0);
+            body(B, first + k * T * SB);
+            if (++k == nb) break;
+        }
+    } else {
+        const int4* pn = slab;
+        int4 ids = *pn;
+        for (int k = 0; k < nb; ++k) {
+            const int4 idc = ids;
+            pn = pn == last ? last : pn + str;          // block k+1
+            ids = *pn;
+            const Nb<false> cur = gather<false>(P, Q, idc);
+            __builtin_amdgcn_sched_barrier(0);
+            body(cur, first + k * T * SB);
+        }
+    }
+}
+
 // --------------------------------------------------------------------------
 // Work distribution and deterministic reductions
 //
@@ -297,9 +385,10 @@ __device__ __forceinline__ double3 sep(const RepDesc& R, const double4& a, const
 // --------------------------------------------------------------------------
 // Neighbour lists.  Rebuilds run only for replicas whose flag is set (an
 // atom moved more than skin/2 since the last build).  Atoms are binned into
-// cells of edge >= r_cut + skin, each cell's atoms are sorted by id, and
-// every row is the in-order concatenation of the 27 surrounding cells'
-// members within r_cut + skin, so rows have a fixed order.
+// cells of edge >= (r_cut + skin) / 2, each cell's atoms are sorted by id,
+// and every row is the in-order concatenation of the members within
+// r_cut + skin of the 5 x 5 x 5 cells around the atom's own, so rows have a
+// fixed order.
 // --------------------------------------------------------------------------
 // Prefix sums over the replicas of the atoms and of the cells to rebuild:
 // pre[r] (atoms of flagged replicas before r), pre[n_rep + 1 + r] (cells of
@@ -463,20 +552,22 @@ __global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
 }
 
 // Rows: one wavefront per atom of a flagged replica (waves of the whole grid
-// stride over the flagged atoms, work items from the prefix).  The 27 stencil cells' members form one
-// candidate stream in a fixed order (cells by offset, atoms by id); each pass
+// stride over the flagged atoms, work items from the prefix).  The 125
+// stencil cells' members form one candidate stream in a fixed order (cells
+// by offset, atoms by id); each pass
 // tests 64 candidates with exact minimum-image box coordinates and appends
 // the accepted ones in stream order (ballot + prefix count) to a row buffer
 // in LDS, which is written out as whole 16-byte slabs at the end (row stores
 // inside the loop would make every pass's loads wait for them).
 constexpr int kListBlock = 256;
 constexpr int kListGrid = 1024;
+constexpr int kStencil = 125;   // 5 x 5 x 5 cells
 
 __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 {
     extern __shared__ int rowbuf[];             // [waves][cap] accepted ids of each wavefront's atom
-    __shared__ int cend[kListBlock / 64][28];   // per wave: inclusive prefix of stencil cell sizes
-    __shared__ int cid[kListBlock / 64][28];    // per wave: global stencil cell ids
+    __shared__ int cend[kListBlock / 64][kStencil];   // per wave: inclusive prefix of stencil cell sizes
+    __shared__ int cid[kListBlock / 64][kStencil];    // per wave: global stencil cell ids
     const int lw = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int cap = a.cap, N = a.N;
     const float rl2 = a.rl2_f;
@@ -514,26 +605,31 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
             }
         } else {   // cells
             const int cx = box_cell(qi.x, R.nc[0]), cy = box_cell(qi.y, R.nc[1]), cz = box_cell(qi.z, R.nc[2]);
-            int n_c = 0, c = 0;
-            if (lw < 27) {
-                const int ux = (cx + lw / 9 - 1 + R.nc[0]) % R.nc[0];
-                const int uy = (cy + (lw / 3) % 3 - 1 + R.nc[1]) % R.nc[1];
-                const int uz = (cz + lw % 3 - 1 + R.nc[2]) % R.nc[2];
-                c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
-                n_c = a.cell_n[c];
-            }
-            int incl = n_c;
+            int tot_c = 0;   // running total of the stencil cells' sizes
+            for (int q0 = 0; q0 < kStencil; q0 += 64) {
+                const int q = q0 + lw;
+                int n_c = 0, c = 0;
+                if (q < kStencil) {
+                    const int ux = (cx + q / 25 - 2 + R.nc[0]) % R.nc[0];
+                    const int uy = (cy + (q / 5) % 5 - 2 + R.nc[1]) % R.nc[1];
+                    const int uz = (cz + q % 5 - 2 + R.nc[2]) % R.nc[2];
+                    c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
+                    n_c = a.cell_n[c];
+                }
+                int incl = n_c;
 #pragma unroll
-            for (int o = 1; o < 32; o <<= 1) {
-                const int y = __shfl_up(incl, o, 64);
-                if (lw >= o) incl += y;
-            }
-            if (lw < 27) {
-                cend[w][lw] = incl;
-                cid[w][lw] = c;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o, 64);
+                    if (lw >= o) incl += y;
+                }
+                incl += tot_c;
+                if (q < kStencil) {
+                    cend[w][q] = incl;
+                    cid[w][q] = c;
+                }
+                tot_c = __builtin_amdgcn_readlane(incl, 63);
             }
             __builtin_amdgcn_wave_barrier();
-            const int tot_c = __shfl(incl, 26, 64);
             // four passes per iteration: their independent loads are in flight together
             constexpr int U = 4;
             for (int k0 = 0; k0 < tot_c; k0 += 64 * U) {
@@ -546,8 +642,8 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
                     if (k < tot_c) {
                         int q = 0;   // first stencil cell whose inclusive end exceeds k
 #pragma unroll
-                        for (int step = 16; step > 0; step >>= 1)
-                            if (q + step <= 26 && cend[w][q + step - 1] <= k) q += step;
+                        for (int step = 64; step > 0; step >>= 1)
+                            if (q + step <= kStencil - 1 && cend[w][q + step - 1] <= k) q += step;
                         const int slot = k - (q ? cend[w][q - 1] : 0);
                         jl[u] = a.cell_atoms[(size_t)cid[w][q] * a.ccap + slot];
                     }
@@ -620,20 +716,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        const int step = T * SB;
-        int4 jn = lane * SB < n ? row_slab(a.nbr, i, lane * SB, N) : make_int4(i, i, i, i);
-        for (int b0 = lane * SB; b0 < n; b0 += step) {
-            const int js[SB] = {jn.x, jn.y, jn.z, jn.w};
-            double4 pj[kQ ? 1 : SB];
-            uint4 qj[kQ ? SB : 1];
-#pragma unroll
-            for (int s = 0; s < SB; ++s) {   // all gathers in flight together
-                if constexpr (kQ) qj[s] = a.Q[js[s]];
-                else pj[s] = a.P[js[s]];
-            }
-            // next block's ids, one iteration ahead; unconditional (the last block re-reads
-            // its own slab) so that the load needs no wait until its use
-            jn = row_slab(a.nbr, i, b0 + step < n ? b0 + step : b0, N);
+        walk_row<kQ, T>(a.nbr, a.P, a.Q, N, i, lane, n, [&](const Nb<kQ>& g, int b0) {
             real r[SB], t[SB];
             int m[SB];
             bool in[SB];
@@ -641,11 +724,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
             for (int s = 0; s < SB; ++s) {
                 real rx, ry, rz;
                 if constexpr (kQ) {
-                    rx = (real)(int)(qi.x - qj[s].x) * qsx;
-                    ry = (real)(int)(qi.y - qj[s].y) * qsy;
-                    rz = (real)(int)(qi.z - qj[s].z) * qsz;
+                    rx = (real)(int)(qi.x - g.v[s].x) * qsx;
+                    ry = (real)(int)(qi.y - g.v[s].y) * qsy;
+                    rz = (real)(int)(qi.z - g.v[s].z) * qsz;
                 } else {
-                    const double3 d = sep(R, pi, pj[s]);
+                    const double3 d = sep(R, pi, g.v[s]);
                     rx = (real)d.x;
                     ry = (real)d.y;
                     rz = (real)d.z;
@@ -670,7 +753,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 part += in[s] ? v : (real)0;
             }
             acc += Acc<real>::q(part);
-        }
+        });
     }
 #pragma unroll
     for (int o = T / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, T);
@@ -753,36 +836,23 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         const int n = a.nnb[i];
         const real Fpi = kQ ? (real)__uint_as_float(qi.w) : (real)pi.w;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        const int step = T * SB;
-        int4 jn = lane * SB < n ? row_slab(a.nbr, i, lane * SB, N) : make_int4(i, i, i, i);
-        for (int b0 = lane * SB; b0 < n; b0 += step) {
-            const int js[SB] = {jn.x, jn.y, jn.z, jn.w};
-            double4 pj[kQ ? 1 : SB];
-            uint4 qj[kQ ? SB : 1];
-#pragma unroll
-            for (int s = 0; s < SB; ++s) {   // all gathers in flight together
-                if constexpr (kQ) qj[s] = a.Q[js[s]];
-                else pj[s] = a.P[js[s]];
-            }
-            // next block's ids, one iteration ahead; unconditional (the last block re-reads
-            // its own slab) so that the load needs no wait until its use
-            jn = row_slab(a.nbr, i, b0 + step < n ? b0 + step : b0, N);
+        walk_row<kQ, T>(a.nbr, a.P, a.Q, N, i, lane, n, [&](const Nb<kQ>& g, int b0) {
             real rx[SB], ry[SB], rz[SB], ir[SB], t[SB], fpj[SB];
             int m[SB];
             bool in[SB];
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
                 if constexpr (kQ) {
-                    rx[s] = (real)(int)(qi.x - qj[s].x) * qsx;
-                    ry[s] = (real)(int)(qi.y - qj[s].y) * qsy;
-                    rz[s] = (real)(int)(qi.z - qj[s].z) * qsz;
-                    fpj[s] = (real)__uint_as_float(qj[s].w);
+                    rx[s] = (real)(int)(qi.x - g.v[s].x) * qsx;
+                    ry[s] = (real)(int)(qi.y - g.v[s].y) * qsy;
+                    rz[s] = (real)(int)(qi.z - g.v[s].z) * qsz;
+                    fpj[s] = (real)__uint_as_float(g.v[s].w);
                 } else {
-                    const double3 d = sep(R, pi, pj[s]);
+                    const double3 d = sep(R, pi, g.v[s]);
                     rx[s] = (real)d.x;
                     ry[s] = (real)d.y;
                     rz[s] = (real)d.z;
-                    fpj[s] = (real)pj[s].w;
+                    fpj[s] = (real)g.v[s].w;
                 }
                 const real r2 = rx[s] * rx[s] + ry[s] * ry[s] + rz[s] * rz[s];
                 in[s] = (b0 + s < n) && r2 < rc2;
@@ -817,7 +887,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
             f1 += Acc<real>::q(p1);
             f2 += Acc<real>::q(p2);
             ep += Acc<real>::q(pe);
-        }
+        });
     }
 #pragma unroll
     for (int o = T / 2; o > 0; o >>= 1) {
