@@ -442,15 +442,22 @@ __device__ void flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_r
     }
 }
 
-// Replica holding work item f of a prefix p[0..n_rep]: p[r] <= f < p[r+1]
-// (replicas with no items are skipped by taking the last such r).
+// Replica holding work item f of a prefix p[0..n_rep] (non-decreasing,
+// p[n_rep] > f): the last r with p[r] <= f, which skips replicas with no
+// items.  Called by a whole wavefront with a uniform f: each round its 64
+// lanes probe 64 evenly spaced entries and a ballot counts those <= f, so
+// up to 64 replicas take one round of loads (a binary search, one load per
+// level, would chain six).
 __device__ __forceinline__ int item_replica(const int32_t* p, int n_rep, int f)
 {
-    int lo = 0, hi = n_rep;
+    const int lw = threadIdx.x & 63;
+    int lo = 0, hi = n_rep;   // p[lo] <= f < p[hi]
     while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (p[mid] <= f) lo = mid;
-        else hi = mid;
+        const int stride = (hi - lo + 63) >> 6;
+        const int idx = lo + stride * (lw + 1);
+        const uint64_t le = __ballot(idx < hi && p[idx] <= f);
+        lo += stride * __popcll(le);   // the probes <= f are a prefix of the lanes
+        hi = min(hi, lo + stride);
     }
     return lo;
 }
@@ -560,7 +567,7 @@ __global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
 // in LDS, which is written out as whole 16-byte slabs at the end (row stores
 // inside the loop would make every pass's loads wait for them).
 constexpr int kListBlock = 256;
-constexpr int kListGrid = 1024;
+constexpr int kListGrid = 2048;
 constexpr int kStencil = 125;   // 5 x 5 x 5 cells
 
 __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
