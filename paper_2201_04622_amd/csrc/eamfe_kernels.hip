@@ -1088,7 +1088,7 @@ int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int 
     if (a.n_cells > 0) {
         int p2 = 1;
         while (p2 < a.ccap) p2 <<= 1;
-        hipLaunchKernelGGL(k_cellsort, dim3(1024), dim3(64), p2 * sizeof(int32_t), s, a);
+        hipLaunchKernelGGL(k_cellsort, dim3(4096), dim3(64), p2 * sizeof(int32_t), s, a);
     }
     (void)lanes;
     (void)block;
