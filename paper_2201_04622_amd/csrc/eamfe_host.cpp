@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,7 @@ struct eamfe_ctx {
     int block = 256;
     int grid = 0;      // persistent pair-kernel blocks (0: every resident slot), a multiple of 8
     int n_cu = 256;
+    int max_lds = 65536;   // LDS bytes one block may allocate
     int xcd = 1;
     std::string err;
 
@@ -47,6 +49,9 @@ struct eamfe_ctx {
     int n_tiles = 0;           // work units
     int nq = 1;                // unit groups (one per XCD with affinity)
     int qoff[9] = {0};         // group q holds tiles[qoff[q] .. qoff[q+1])
+    std::vector<int2> slices;  // per block of a staged pair launch: first unit, unit count (one replica)
+    int max_rep_atoms = 0;
+    DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
     DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d;
@@ -224,6 +229,52 @@ Tables tables_of(const eamfe_ctx* c)
 // CU's caches); unit slots (tile_base) follow the replica index.  With XCD affinity (and at least 8 replicas) replicas
 // are binned greedily by atom count into 8 groups (group x is spread over the
 // blocks on XCD x); otherwise one group.
+// Blocks of the staged pair launches (each stages one replica's records in
+// LDS): every replica of a unit group gets at least one block and the
+// group's n_cu / nq blocks go to the replicas with the largest slices, whose
+// units are then split into near-equal contiguous runs.  Block b serves
+// group b % nq, so a replica's blocks share an XCD (and its L2) as its units
+// do in the persistent form.
+void build_slices(eamfe_ctx* c)
+{
+    std::vector<std::vector<int2>> per_group(c->nq);
+    size_t most = 0;
+    for (int x = 0; x < c->nq; ++x) {
+        // the group's replicas: runs of units with one replica each
+        std::vector<int2> runs;   // first unit, units
+        for (int u = c->qoff[x]; u < c->qoff[x + 1];) {
+            int e = u;
+            while (e < c->qoff[x + 1] && c->tiles[e].rep == c->tiles[u].rep) ++e;
+            runs.push_back(make_int2(u, e - u));
+            u = e;
+        }
+        const int target = std::max((int)runs.size(), c->n_cu / c->nq);
+        std::vector<int> nb(runs.size(), 1);
+        // largest slice first: a max-heap of (units per block, run)
+        std::priority_queue<std::pair<double, int>> heap;
+        for (size_t k = 0; k < runs.size(); ++k) heap.push({(double)runs[k].y, (int)k});
+        for (int left = target - (int)runs.size(); left > 0 && !heap.empty(); --left) {
+            const int k = heap.top().second;
+            heap.pop();
+            if (nb[k] >= runs[k].y) continue;   // one unit per block at most
+            ++nb[k];
+            heap.push({(double)runs[k].y / nb[k], k});
+        }
+        for (size_t k = 0; k < runs.size(); ++k) {
+            const int n = runs[k].y, m = nb[k];
+            for (int j = 0, at = runs[k].x; j < m; ++j) {
+                const int len = n / m + (j < n % m ? 1 : 0);
+                per_group[x].push_back(make_int2(at, len));
+                at += len;
+            }
+        }
+        most = std::max(most, per_group[x].size());
+    }
+    c->slices.assign(most * c->nq, make_int2(0, 0));
+    for (int x = 0; x < c->nq; ++x)
+        for (size_t k = 0; k < per_group[x].size(); ++k) c->slices[k * c->nq + x] = per_group[x][k];
+}
+
 int build_tiles(eamfe_ctx* c)
 {
     const int A = 64 / c->lanes;
@@ -245,6 +296,8 @@ int build_tiles(eamfe_ctx* c)
         }
     }
     c->n_tiles = base;
+    c->max_rep_atoms = 0;
+    for (const auto& R : c->reps) c->max_rep_atoms = std::max(c->max_rep_atoms, R.n);
     for (int q = 0; q < 9; ++q) c->qoff[q] = 0;
     if (c->xcd && c->n_rep >= 8) {
         std::vector<int> order(c->n_rep);
@@ -271,6 +324,10 @@ int build_tiles(eamfe_ctx* c)
     OK(ensure(c, c->tiles_d, std::max<size_t>(1, c->tiles.size()) * sizeof(Tile)));
     if (!c->tiles.empty())
         HIPCHK(c, hipMemcpy(c->tiles_d.p, c->tiles.data(), c->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    build_slices(c);
+    OK(ensure(c, c->slices_d, std::max<size_t>(1, c->slices.size()) * sizeof(int2)));
+    if (!c->slices.empty())
+        HIPCHK(c, hipMemcpy(c->slices_d.p, c->slices.data(), c->slices.size() * sizeof(int2), hipMemcpyHostToDevice));
     OK(ensure(c, c->noise_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
     OK(ensure(c, c->energy_part_d, (size_t)std::max(1, c->n_tiles) * 2 * sizeof(double)));
     OK(ensure(c, c->reps_d, c->reps.size() * sizeof(RepDesc)));
@@ -358,6 +415,14 @@ StepArgs step_args(eamfe_ctx* c)
     a.n_cu = c->n_cu;
     a.nq = c->nq;
     for (int q = 0; q < 9; ++q) a.qoff[q] = c->qoff[q];
+    // FP32 form: stage each block's replica records in LDS when they fit
+    // beside the pair table (and no persistent grid was asked for)
+    a.slices = (const int2*)c->slices_d.p;
+    a.stage_atoms = c->max_rep_atoms;
+    const long lds_force = 32L * c->n_r + 16L * c->max_rep_atoms;
+    a.slice_grid = (c->precision == EAMFE_FP32 && c->have_pot && c->grid == 0 && lds_force <= c->max_lds)
+                       ? (int)c->slices.size()
+                       : 0;
     a.half_skin2 = 0.25 * c->skin * c->skin;
     return a;
 }
@@ -762,6 +827,9 @@ int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
             c->n_cu = cus;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+            c->max_lds = lds;
     }
     int r = EAMFE_OK;
     if ((r = ensure(c, c->iter_d, sizeof(int64_t))) ||
@@ -785,7 +853,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);

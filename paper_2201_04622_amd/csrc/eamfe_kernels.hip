@@ -135,6 +135,18 @@ __device__ __forceinline__ int interval(real x, real inv_h, int n, real& t)
     return m;
 }
 
+// The same without the clamp, for the FP32 tables in LDS: they carry one
+// padding interval past the last knot (the end value, zero slope), so any
+// 0 <= x <= x_max (1 + a few ulp), which is what the callers pass, stays in
+// range.  x = r comes from a masked r^2 and is finite.
+__device__ __forceinline__ int interval_pad(float x, float inv_h, float& t)
+{
+    const float p = x * inv_h;
+    const int m = (int)p;
+    t = p - (float)m;
+    return m;
+}
+
 __device__ __forceinline__ void min_image(const RepDesc& R, double& dx, double& dy, double& dz)
 {
     dx -= R.L[0] * rint(dx * R.invL[0]);
@@ -181,8 +193,9 @@ __device__ __forceinline__ int4 row_slab(const int32_t* nbr, int i, int b0, int 
 }
 
 // Records of one lane block's SB neighbours: box coordinates and F' bits
-// (FP32 form; a 32-bit byte offset from the array base, N < 2^28) or packed
-// positions (FP64 form).
+// (FP32 form: record j - qoff of Q, a 32-bit byte offset from its base, with
+// Q the global array and qoff 0, or a replica's records staged in LDS and
+// qoff its first atom) or packed positions (FP64 form).
 template <bool kQ>
 struct Nb;
 template <>
@@ -195,13 +208,13 @@ struct Nb<false> {
 };
 
 template <bool kQ>
-__device__ __forceinline__ Nb<kQ> gather(const double4* P, const uint4* Q, int4 j)
+__device__ __forceinline__ Nb<kQ> gather(const double4* P, const uint4* Q, int qoff, int4 j)
 {
     Nb<kQ> g;
     const int js[SB] = {j.x, j.y, j.z, j.w};
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
-        if constexpr (kQ) g.v[s] = *(const uint4*)((const char*)Q + (uint32_t)js[s] * 16u);
+        if constexpr (kQ) g.v[s] = *(const uint4*)((const char*)Q + (uint32_t)(js[s] - qoff) * 16u);
         else g.v[s] = P[js[s]];
     }
     return g;
@@ -218,8 +231,8 @@ __device__ __forceinline__ Nb<kQ> gather(const double4* P, const uint4* Q, int4 
 // unused).  The scheduling barrier keeps the loads ahead of the arithmetic
 // they overlap.
 template <bool kQ, int T, typename Body>
-__device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, const uint4* Q, int N, int i,
-                                         int lane, int n, Body&& body)
+__device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, const uint4* Q, int qoff, int N,
+                                         int i, int lane, int n, Body&& body)
 {
     const int first = lane * SB;
     if (first >= n) return;
@@ -235,13 +248,13 @@ __device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, c
         const int4* pn = nb > 1 ? slab + str : last;   // slab of block k+1
         int4 ids = *pn;
         __builtin_amdgcn_sched_barrier(0);
-        Nb<true> A = gather<true>(P, Q, id0), B;
+        Nb<true> A = gather<true>(P, Q, qoff, id0), B;
         for (int k = 0;;) {
             int4 idn = ids;
             pn = pn == last ? last : pn + str;          // block k+2
             ids = *pn;
             __builtin_amdgcn_sched_barrier(0);
-            B = gather<true>(P, Q, idn);
+            B = gather<true>(P, Q, qoff, idn);
             __builtin_amdgcn_sched_barrier(0);
             body(A, first + k * T * SB);
             if (++k == nb) break;
@@ -249,7 +262,7 @@ __device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, c
             pn = pn == last ? last : pn + str;
             ids = *pn;
             __builtin_amdgcn_sched_barrier(0);
-            A = gather<true>(P, Q, idn);
+            A = gather<true>(P, Q, qoff, idn);
             __builtin_amdgcn_sched_barrier(0);
             body(B, first + k * T * SB);
             if (++k == nb) break;
@@ -261,7 +274,7 @@ __device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, c
             const int4 idc = ids;
             pn = pn == last ? last : pn + str;          // block k+1
             ids = *pn;
-            const Nb<false> cur = gather<false>(P, Q, idc);
+            const Nb<false> cur = gather<false>(P, Q, qoff, idc);
             __builtin_amdgcn_sched_barrier(0);
             body(cur, first + k * T * SB);
         }
@@ -331,6 +344,27 @@ __device__ __forceinline__ void for_each_unit(const int* qoff, int nq, Body&& bo
     const int nb = ((int)gridDim.x - x + nq - 1) / nq;             // blocks serving group x
     const int first = qoff[x], len = qoff[x + 1] - qoff[x];
     for (int u = lb * wpb + wib; u < len; u += nb * wpb) body(first + u);
+}
+
+// Units of a pair launch.  Persistent form: for_each_unit over the unit
+// groups.  Staged form: block b serves slice b (a run of units of one
+// replica): it copies that replica's records into LDS at st and its
+// wavefronts take the slice's units in turn, gathering neighbours from LDS.
+template <bool kStage, typename Body>
+__device__ __forceinline__ void run_units(const StepArgs& a, uint4* st, Body&& body)
+{
+    if constexpr (kStage) {
+        const int2 sl = a.slices[blockIdx.x];
+        if (sl.y <= 0) return;   // uniform over the block
+        const RepDesc& R = a.reps[a.tiles[sl.x].rep];
+        for (int k = threadIdx.x; k < R.n; k += blockDim.x) st[k] = a.Q[R.off + k];
+        __syncthreads();
+        const int wpb = (int)(blockDim.x >> 6);
+        const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        for (int u = wib; u < sl.y; u += wpb) body(sl.x + u);
+    } else {
+        for_each_unit(a.qoff, a.nq, body);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -693,7 +727,7 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 // --------------------------------------------------------------------------
 // Density pass.  FP32 tables are staged in LDS (32 KB for rho).
 // --------------------------------------------------------------------------
-template <typename real, int T>
+template <typename real, int T, bool kStage = false>
 __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
@@ -705,9 +739,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     if (kLds && a.has_eam) {   // table staged once per block; its wavefronts then take units
         const float4* g = (const float4*)a.tab.rho;
         for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
+        if (threadIdx.x == 0) {   // padding interval: the value at r_cut
+            const float4 c = g[nr - 2];
+            lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
+        }
         __syncthreads();
     }
-    for_each_unit(a.qoff, a.nq, [&](int tix) {
+    uint4* const st = (uint4*)(lds_tab + nr);   // staged form: the block's replica records, after the table
+    auto unit = [&](int tix) {
     const Tile tl = a.tiles[tix];
     const RepDesc& R = a.reps[tl.rep];
     const int lane = wave_lane() % T;
@@ -723,7 +762,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        walk_row<kQ, T>(a.nbr, a.P, a.Q, N, i, lane, n, [&](const Nb<kQ>& g, int b0) {
+        const uint32_t rc2m1 = __float_as_uint((float)a.tab.rc2) - 1u;   // FP32 form's cutoff test
+        walk_row<kQ, T>(a.nbr, a.P, kStage ? st : a.Q, kStage ? R.off : 0, N, i, lane, n,
+                        [&](const Nb<kQ>& g, int b0) {
             real r[SB], t[SB];
             int m[SB];
             bool in[SB];
@@ -741,10 +782,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                     rz = (real)d.z;
                 }
                 const real r2 = rx * rx + ry * ry + rz * rz;
-                in[s] = (b0 + s < n) && r2 < rc2;
                 real ir;
-                Root<real>::of(r2, r[s], ir);
-                m[s] = interval<real>(in[s] ? r[s] : (real)0, inv_h, nr, t[s]);
+                if constexpr (kQ) {
+                    // 0 < r^2 < rc^2 in one unsigned compare of the bits; the
+                    // self-padded slots of a row's last slab give r^2 = 0
+                    in[s] = __float_as_uint(r2) - 1u < rc2m1;
+                    Root<real>::of(in[s] ? r2 : (real)1, r[s], ir);
+                    m[s] = interval_pad(r[s], inv_h, t[s]);
+                } else {
+                    in[s] = (b0 + s < n) && r2 < rc2;
+                    Root<real>::of(r2, r[s], ir);
+                    m[s] = interval<real>(in[s] ? r[s] : (real)0, inv_h, nr, t[s]);
+                }
             }
             real part = (real)0;
 #pragma unroll
@@ -757,7 +806,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                     const auto c = Tab<real>::ld4(a.tab.rho, m[s]);
                     v = c.x + t[s] * (c.y + t[s] * (c.z + t[s] * c.w));
                 }
-                part += in[s] ? v : (real)0;
+                if constexpr (kQ) part += v * (in[s] ? 1.f : 0.f);   // a product: the table read stays unconditional
+                else part += in[s] ? v : (real)0;
             }
             acc += Acc<real>::q(part);
         });
@@ -791,7 +841,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         }
         if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
     }
-    });   // units
+    };   // unit
+    run_units<kStage>(a, st, unit);
 }
 
 // --------------------------------------------------------------------------
@@ -811,7 +862,7 @@ __device__ __forceinline__ void total_force(int mode, const double (&fe)[3], con
     }
 }
 
-template <typename real, int T>
+template <typename real, int T, bool kStage = false>
 __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
@@ -823,10 +874,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     if (kLds && a.has_eam) {   // table staged once per block; its wavefronts then take units
         const float4* g = (const float4*)a.tab.pair;
         for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
+        if (threadIdx.x == 0) {   // padding interval: phi(r_cut), zero slopes
+            const float4 c = g[2 * (nr - 2)];
+            lds_tab[2 * (nr - 1)] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
+            lds_tab[2 * (nr - 1) + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         __syncthreads();
     }
     if (a.step_kernel && blockIdx.x == 0 && threadIdx.x == 0) *a.pending = 1;   // finish due before the next pass
-    for_each_unit(a.qoff, a.nq, [&](int tix) {
+    uint4* const st = (uint4*)(lds_tab + 2 * nr);   // staged form: the block's replica records, after the table
+    auto unit = [&](int tix) {
     const Tile tl = a.tiles[tix];
     const RepDesc& R = a.reps[tl.rep];
     const int lane = wave_lane() % T;
@@ -843,7 +900,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         const int n = a.nnb[i];
         const real Fpi = kQ ? (real)__uint_as_float(qi.w) : (real)pi.w;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
-        walk_row<kQ, T>(a.nbr, a.P, a.Q, N, i, lane, n, [&](const Nb<kQ>& g, int b0) {
+        const uint32_t rc2m1 = __float_as_uint((float)a.tab.rc2) - 1u;   // FP32 form's cutoff test
+        walk_row<kQ, T>(a.nbr, a.P, kStage ? st : a.Q, kStage ? R.off : 0, N, i, lane, n,
+                        [&](const Nb<kQ>& g, int b0) {
             real rx[SB], ry[SB], rz[SB], ir[SB], t[SB], fpj[SB];
             int m[SB];
             bool in[SB];
@@ -862,10 +921,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                     fpj[s] = (real)g.v[s].w;
                 }
                 const real r2 = rx[s] * rx[s] + ry[s] * ry[s] + rz[s] * rz[s];
-                in[s] = (b0 + s < n) && r2 < rc2;
                 real r;
-                Root<real>::of(in[s] ? r2 : (real)1, r, ir[s]);
-                m[s] = interval<real>(in[s] ? r : (real)0, inv_h, nr, t[s]);
+                if constexpr (kQ) {
+                    in[s] = __float_as_uint(r2) - 1u < rc2m1;   // 0 < r^2 < rc^2, as in the density pass
+                    Root<real>::of(in[s] ? r2 : (real)1, r, ir[s]);
+                    m[s] = interval_pad(r, inv_h, t[s]);
+                } else {
+                    in[s] = (b0 + s < n) && r2 < rc2;
+                    Root<real>::of(in[s] ? r2 : (real)1, r, ir[s]);
+                    m[s] = interval<real>(in[s] ? r : (real)0, inv_h, nr, t[s]);
+                }
             }
             real p0 = (real)0, p1 = (real)0, p2 = (real)0, pe = (real)0;
 #pragma unroll
@@ -880,15 +945,32 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                     ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
                 }
                 const real ts = t[s];
-                const real phi = ua + ts * (ub + ts * (uc + ts * ud));
-                const real dphi = (ub + ts * ((real)2 * uc + (real)3 * ts * ud)) * inv_h;
-                const real drho = wb + ts * (wc + ts * wd);
-                const real g = dphi + (Fpi + fpj[s]) * drho;   // dU/dr_ij
-                const real sc = in[s] ? -g * ir[s] : (real)0;
-                p0 += sc * rx[s];
-                p1 += sc * ry[s];
-                p2 += sc * rz[s];
-                pe += in[s] ? phi : (real)0;
+                if constexpr (kQ) {
+                    // phi and h dphi/dr = b + 2 c t + 3 d t^2 share their Horner
+                    // terms; pairs outside the cutoff are weighted by zero (a
+                    // product, not a select, so every table read stays one 16-byte load)
+                    const float cu = uc + ts * ud, cv = ub + ts * cu;
+                    const float phi = ua + ts * cv;
+                    const float dphi_h = cv + ts * (cu + ts * ud);
+                    const float drho = wb + ts * (wc + ts * wd);
+                    const float fm = in[s] ? 1.f : 0.f;
+                    const float g = dphi_h * inv_h + (Fpi + fpj[s]) * drho;   // dU/dr_ij
+                    const float sc = -g * (ir[s] * fm);
+                    p0 += sc * rx[s];
+                    p1 += sc * ry[s];
+                    p2 += sc * rz[s];
+                    pe += phi * fm;
+                } else {
+                    const real phi = ua + ts * (ub + ts * (uc + ts * ud));
+                    const real dphi = (ub + ts * ((real)2 * uc + (real)3 * ts * ud)) * inv_h;
+                    const real drho = wb + ts * (wc + ts * wd);
+                    const real g = dphi + (Fpi + fpj[s]) * drho;   // dU/dr_ij
+                    const real sc = in[s] ? -g * ir[s] : (real)0;
+                    p0 += sc * rx[s];
+                    p1 += sc * ry[s];
+                    p2 += sc * rz[s];
+                    pe += in[s] ? phi : (real)0;
+                }
             }
             f0 += Acc<real>::q(p0);
             f1 += Acc<real>::q(p1);
@@ -954,7 +1036,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     }
 
     unit_partial<2>(e, a.energy_part, R, tl.idx);
-    });   // units
+    };   // unit
+    run_units<kStage>(a, st, unit);
 }
 
 // After a force pass: each replica's U_EAM and |x - x0|^2 from the unit
@@ -1119,7 +1202,8 @@ int launch_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap,
 template <typename real>
 static size_t lds_bytes(const StepArgs& a, int tables)
 {
-    return (sizeof(real) == 4 && a.has_eam) ? (size_t)tables * (a.tab.n_r - 1) * sizeof(float4) : 0;
+    // n_r - 1 intervals and one padding interval per table
+    return (sizeof(real) == 4 && a.has_eam) ? (size_t)tables * a.tab.n_r * sizeof(float4) : 0;
 }
 
 // Resident blocks per CU of a pair kernel at this block size and LDS use
@@ -1157,9 +1241,37 @@ static int pair_grid(const StepArgs& a, const void* f, int block, size_t lds)
     return (g + a.nq - 1) / a.nq * a.nq;   // every group has blocks
 }
 
+// Dynamic LDS beyond the default limit needs the kernel's attribute raised
+// once per size.
+static void allow_lds(const void* f, size_t bytes)
+{
+    static thread_local std::vector<std::pair<const void*, size_t>> done;
+    for (auto& d : done)
+        if (d.first == f && d.second >= bytes) return;
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done.push_back({f, bytes});
+}
+
+// Staged launch of the FP32 pair kernels: one block per slice, the table
+// and the largest replica's records in LDS.
+template <typename real>
+static bool staged(const StepArgs& a)
+{
+    return sizeof(real) == 4 && a.has_eam && a.slice_grid > 0;
+}
+
 template <typename real, int T>
 static void density_one(const StepArgs& a, int block, hipStream_t s)
 {
+    if constexpr (sizeof(real) == 4) {
+        if (staged<real>(a)) {
+            const size_t sh = lds_bytes<real>(a, 1) + (size_t)a.stage_atoms * sizeof(uint4);
+            const void* f = reinterpret_cast<const void*>(&k_density<real, T, true>);
+            allow_lds(f, sh);
+            hipLaunchKernelGGL((k_density<real, T, true>), dim3(a.slice_grid), dim3(block), sh, s, a);
+            return;
+        }
+    }
     const size_t sh = lds_bytes<real>(a, 1);
     const void* f = reinterpret_cast<const void*>(&k_density<real, T>);
     hipLaunchKernelGGL((k_density<real, T>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
@@ -1168,6 +1280,15 @@ static void density_one(const StepArgs& a, int block, hipStream_t s)
 template <typename real, int T>
 static void force_one(const StepArgs& a, int block, hipStream_t s)
 {
+    if constexpr (sizeof(real) == 4) {
+        if (staged<real>(a)) {
+            const size_t sh = lds_bytes<real>(a, 2) + (size_t)a.stage_atoms * sizeof(uint4);
+            const void* f = reinterpret_cast<const void*>(&k_force<real, T, true>);
+            allow_lds(f, sh);
+            hipLaunchKernelGGL((k_force<real, T, true>), dim3(a.slice_grid), dim3(block), sh, s, a);
+            return;
+        }
+    }
     const size_t sh = lds_bytes<real>(a, 2);
     const void* f = reinterpret_cast<const void*>(&k_force<real, T>);
     hipLaunchKernelGGL((k_force<real, T>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
