@@ -112,6 +112,7 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     natoms = int(arrs["x0"].shape[0])
     torch.cuda.synchronize()
     ctx.set_kernel_timing(KERNEL_TIMING_STRIDE)
+    ctx.row_history(reset=True)   # list work of the timed passes only
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -123,12 +124,13 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     ms = e0.elapsed_time(e1)
     kt = ctx.kernel_timing()
     ctx.check()
-    mean_nl, max_nl, cap = ctx.list_stats()
+    mean_nl, passes = ctx.row_history()   # time average over the timed force passes
+    end_nl, max_nl, cap = ctx.list_stats()
     launch = ctx.get_launch()
     ctx.close()
     return {
         "natoms": natoms, "n_rep": len(reps), "ms": ms, "wall_s": wall, "kt": kt, "mean_nl": mean_nl,
-        "max_nl": max_nl, "cap": cap, "launch": launch, "tuned": tuned, "desc": wl.description,
+        "passes": passes, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch, "tuned": tuned, "desc": wl.description,
     }
 
 
@@ -235,8 +237,10 @@ def main():
             "atoms": main_run["natoms"],
             "precision": ("f32 pair terms and densities, f64 positions/velocities/energies/work, "
                           "2^-32 fixed-point per-atom sums") if args.precision == "fp32" else "f64 throughout",
-            "mean_neighbour_row": round(main_run["mean_nl"], 2),
+            "mean_neighbour_row": round(main_run["mean_nl"], 2),   # over the timed force passes
+            "final_neighbour_row": round(main_run["end_nl"], 2),
             "max_neighbour_row": main_run["max_nl"],
+            "force_passes": main_run["passes"],
             "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
                        "autotuned": main_run["tuned"] is not None},
             "skin": args.skin,

@@ -172,6 +172,14 @@ int eamfe_kernel_timing(eamfe_ctx* ctx, double* ms_total, int64_t* launches);
  * maximum row length over all atoms, and the row capacity. */
 int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capacity);
 
+/* List work of the step force passes (run_switching, switch_step) since the
+ * last reset: their number, and the Verlet row length averaged over those
+ * passes and over all atoms (each pass weighted by the rows it used), the
+ * n_L of the per-atom algorithmic byte count.  Synchronises.  reset != 0
+ * clears the history after reading.  A range replayed after a row or bin
+ * overflow is counted once. */
+int eamfe_row_history(eamfe_ctx* ctx, double* mean_len, int64_t* passes, int reset);
+
 /* Copy the current Verlet rows (for inspection): nnb_dev[N_tot] row lengths,
  * nbr_dev[N_tot][cap] global atom ids in row order, -1 past each row's end
  * (may be NULL; cap >= the row capacity reported by eamfe_list_stats).

@@ -54,7 +54,7 @@ struct eamfe_ctx {
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d;
 
     // neighbour lists
     bool have_list = false;
@@ -85,7 +85,7 @@ struct eamfe_ctx {
     int64_t chunk = 1000;
     int min_ccap = 0;
     int64_t replays = 0;
-    DevBuf snap_P, snap_Q, snap_v, snap_w;
+    DevBuf snap_P, snap_Q, snap_v, snap_w, snap_rows;
 
     // adjoint: densities, fixed-point bins, finish scratch, weights
     DevBuf rho_d, bins_d, adj_scratch_d, adj_w_d;
@@ -329,7 +329,7 @@ int build_tiles(eamfe_ctx* c)
     if (!c->slices.empty())
         HIPCHK(c, hipMemcpy(c->slices_d.p, c->slices.data(), c->slices.size() * sizeof(int2), hipMemcpyHostToDevice));
     OK(ensure(c, c->noise_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
-    OK(ensure(c, c->energy_part_d, (size_t)std::max(1, c->n_tiles) * 2 * sizeof(double)));
+    OK(ensure(c, c->energy_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
     OK(ensure(c, c->reps_d, c->reps.size() * sizeof(RepDesc)));
     HIPCHK(c, hipMemcpy(c->reps_d.p, c->reps.data(), c->reps.size() * sizeof(RepDesc), hipMemcpyHostToDevice));
     return EAMFE_OK;
@@ -404,6 +404,7 @@ StepArgs step_args(eamfe_ctx* c)
     a.rebuild = (int32_t*)c->rebuild_d.p;
     a.flag_pre = (int32_t*)c->flag_pre_d.p;
     a.pending = (int32_t*)c->pending_d.p;
+    a.row_acc = (double*)c->row_acc_d.p;
     a.status = (int32_t*)c->status_d.p;
     a.iter = (int64_t*)c->iter_d.p;
     a.W_state = (double*)c->W_state_d.p;
@@ -853,7 +854,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -868,6 +869,7 @@ int eamfe_destroy(eamfe_ctx* c)
     release(c->snap_Q);
     release(c->snap_v);
     release(c->snap_w);
+    release(c->snap_rows);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     drop_graphs(c);
     if (c->ev_user) (void)hipEventDestroy(c->ev_user);
@@ -1040,6 +1042,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
     OK(ensure(c, c->flag_pre_d, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
     OK(ensure(c, c->pending_d, sizeof(int32_t)));
+    OK(ensure(c, c->row_acc_d, (size_t)(n_rep + 1) * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
@@ -1054,6 +1057,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->flag_pre_d.p, 0, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->pending_d.p, 0, sizeof(int32_t)));
+    HIPCHK(c, hipMemset(c->row_acc_d.p, 0, (size_t)(n_rep + 1) * sizeof(double)));
     c->have_list = false;
     return build_tiles(c);
 }
@@ -1188,6 +1192,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
         OK(ensure(c, c->snap_P, p4));
         OK(ensure(c, c->snap_v, v3));
         OK(ensure(c, c->snap_w, wb));
+        OK(ensure(c, c->snap_rows, wb + sizeof(double)));
     }
     for (int64_t b = s0; b < s1; b += c->chunk) {
         const int64_t e = std::min(s1, b + c->chunk);
@@ -1196,6 +1201,8 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             HIPCHK(c, hipMemcpyAsync(c->snap_Q.p, Q_of(c, cur), q4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->snap_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->snap_w.p, c->W_state_d.p, wb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->snap_rows.p, c->row_acc_d.p, wb + sizeof(double), hipMemcpyDeviceToDevice,
+                                     c->stream));
         }
         for (int attempt = 0;; ++attempt) {
             StepArgs a = step_args(c);
@@ -1228,6 +1235,8 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             HIPCHK(c, hipMemcpyAsync(Q_of(c, cur), c->snap_Q.p, q4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(v, c->snap_v.p, v3, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->W_state_d.p, c->snap_w.p, wb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->row_acc_d.p, c->snap_rows.p, wb + sizeof(double), hipMemcpyDeviceToDevice,
+                                     c->stream));
             ++c->replays;
         }
     }
@@ -1483,6 +1492,22 @@ __global__ void k_list_stats(const int32_t* nnb, int n, unsigned long long* out)
     }
     atomicAdd(&out[0], s);
     atomicMax(&out[1], mx);
+}
+
+int eamfe_row_history(eamfe_ctx* c, double* mean_len, int64_t* passes, int reset)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    std::vector<double> h(c->n_rep + 1);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->row_acc_d.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (int r = 0; r < c->n_rep; ++r) sum += h[r];
+    const double n = h[c->n_rep];
+    if (mean_len) *mean_len = n > 0.0 ? sum / (n * c->N) : 0.0;
+    if (passes) *passes = (int64_t)n;
+    if (reset) HIPCHK(c, hipMemsetAsync(c->row_acc_d.p, 0, h.size() * sizeof(double), c->stream));
+    return EAMFE_OK;
 }
 
 int eamfe_list_stats(eamfe_ctx* c, double* mean_len, int* max_len, int* capacity)

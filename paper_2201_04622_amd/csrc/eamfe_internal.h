@@ -107,11 +107,12 @@ struct StepArgs {
     double* e_emb;          // [N] F(rho_i)
     double* xi;             // [3][N] thermostat noise of this step
     double* noise_part;     // [units][3] thermostat noise summed per unit
-    double* energy_part;    // [units][2] U_EAM and |x - x0|^2 summed per unit
+    double* energy_part;    // [units][3] U_EAM, |x - x0|^2 and row lengths summed per unit
     double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
     int32_t* rebuild;       // [n_rep]
     int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix (formed by the list pass's first kernel)
     int32_t* pending;       // [1] 1 while a force pass of a step awaits its finish
+    double* row_acc;        // [n_rep + 1] row lengths summed over the step force passes, then their count
     int32_t* status;
     const double* lam;      // lambda table [S+1]
     int64_t* iter;          // device iteration counter (global step index)

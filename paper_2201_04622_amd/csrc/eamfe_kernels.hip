@@ -990,13 +990,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     double zsum[3] = {0.0, 0.0, 0.0};
     if (a.step_kernel && it < a.it_last && a.fix_com) replica_total<3>(a.noise_part, R, zsum);
 
-    double e[2] = {0.0, 0.0};   // U_EAM contribution, |x - x0|^2
+    double e[3] = {0.0, 0.0, 0.0};   // U_EAM contribution, |x - x0|^2, row length (list work of the pass)
     if (valid && lane == 0) {
         const double fe[3] = {Acc<real>::fin(f0), Acc<real>::fin(f1), Acc<real>::fin(f2)};
         double x[3] = {pi.x, pi.y, pi.z};
         const double d[3] = {x[0] - a.x0[i], x[1] - a.x0[N + i], x[2] - a.x0[2 * N + i]};
         e[0] = a.has_eam ? a.e_emb[i] + 0.5 * Acc<real>::fin(ep) : 0.0;
         e[1] = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        e[2] = a.has_eam ? (double)a.nnb[i] : 0.0;
         if (!isfinite(fe[0] + fe[1] + fe[2] + e[0] + e[1])) atomicOr(a.status, ST_NONFINITE);
         if (a.f_out) {
             a.f_out[i] = fe[0];
@@ -1035,7 +1036,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         }
     }
 
-    unit_partial<2>(e, a.energy_part, R, tl.idx);
+    unit_partial<3>(e, a.energy_part, R, tl.idx);
     };   // unit
     run_units<kStage>(a, st, unit);
 }
@@ -1057,20 +1058,19 @@ __device__ void finish_body(const StepArgs& a)
         // loads of the work state go out with the partials' loads
         const double W0 = work ? a.W_state[r] : 0.0;
         const double dl = work ? a.lam[it + 1] - a.lam[it] : 0.0;
-        double tot[2] = {0.0, 0.0};
+        double tot[3] = {0.0, 0.0, 0.0};
         if (r < a.n_rep) {
             const RepDesc& R = a.reps[r];
-            for (int t = sub; t < R.n_tiles; t += g) {
-                tot[0] += a.energy_part[(size_t)(R.tile_base + t) * 2];
-                tot[1] += a.energy_part[(size_t)(R.tile_base + t) * 2 + 1];
-            }
+            for (int t = sub; t < R.n_tiles; t += g)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) tot[k] += a.energy_part[(size_t)(R.tile_base + t) * 3 + k];
         }
-        for (int o = g / 2; o > 0; o >>= 1) {
-            tot[0] += __shfl_xor(tot[0], o, g);
-            tot[1] += __shfl_xor(tot[1], o, g);
-        }
+        for (int o = g / 2; o > 0; o >>= 1)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) tot[k] += __shfl_xor(tot[k], o, g);
         if (r < a.n_rep && sub == 0) {
             const RepDesc& R = a.reps[r];
+            if (a.step_kernel) a.row_acc[r] += tot[2];   // list work of this pass
             a.U_rep[2 * r] = tot[0];
             a.U_rep[2 * r + 1] = tot[1];
             if (work) {
@@ -1092,7 +1092,10 @@ __device__ void finish_body(const StepArgs& a)
     }
     __syncthreads();   // every thread has read the counter
     if (threadIdx.x == 0) {
-        if (a.step_kernel) *a.iter = it + 1;
+        if (a.step_kernel) {
+            *a.iter = it + 1;
+            a.row_acc[a.n_rep] += 1.0;
+        }
         *a.pending = 0;
     }
 }

@@ -71,6 +71,7 @@ def lib():
         "eamfe_autotune": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, i32, C.POINTER(i32), C.POINTER(i32), _dp]),
         "eamfe_kernel_timing": (i32, [vp, _dp, C.POINTER(i64)]),
         "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
+        "eamfe_row_history": (i32, [vp, _dp, C.POINTER(i64), i32]),
         "eamfe_copy_lists": (i32, [vp, vp, vp, i32]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
@@ -256,6 +257,12 @@ class Context:
         nbr = torch.zeros(self.N, cap, dtype=torch.int32, device="cuda")
         self._c(self._lib.eamfe_copy_lists(self._h, C.c_void_p(nnb.data_ptr()), C.c_void_p(nbr.data_ptr()), cap))
         return nnb, nbr
+
+    def row_history(self, reset=False):
+        """(mean row length over the step force passes since the last reset, passes)."""
+        m, n = C.c_double(), C.c_int64()
+        self._c(self._lib.eamfe_row_history(self._h, C.byref(m), C.byref(n), int(bool(reset))))
+        return m.value, n.value
 
     def list_stats(self):
         m, mx, cap = C.c_double(), C.c_int(), C.c_int()

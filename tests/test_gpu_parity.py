@@ -21,11 +21,12 @@ ETOL = {FP64: 1e-13, FP32: 1e-6}
 def _mixed_batch():
     # uneven sizes, both lattices, verbatim and stable densities, all-pairs and cell lists
     return [
+        # cells of edge >= (r_cut + skin)/2 where an edge holds five (0.3 A skin: L >= 14 A)
         I.Replica("bcc", 4, I.A_BCC_VERBATIM, 300.0, 5.0, 1),    # 128 atoms, L = 11.42 -> all-pairs
-        I.Replica("fcc", 5, I.A_FCC_VERBATIM, 600.0, 5.0, 2),    # 500, cells 3^3
-        I.Replica("bcc", 7, I.A_BCC_STABLE, 900.0, 5.0, 3),      # 686 at high density
-        I.Replica("fcc", 5, I.A_FCC_STABLE, 1200.0, 3.0, 4),     # 500 at high density
-        I.Replica("bcc", 9, I.A_BCC_VERBATIM, 100.0, 5.0, 5),    # 1458, cells 4^3
+        I.Replica("fcc", 5, I.A_FCC_VERBATIM, 600.0, 5.0, 2),    # 500, L = 18.25 -> cells 6^3
+        I.Replica("bcc", 7, I.A_BCC_STABLE, 900.0, 5.0, 3),      # 686 at high density, all-pairs
+        I.Replica("fcc", 5, I.A_FCC_STABLE, 1200.0, 3.0, 4),     # 500 at high density, all-pairs
+        I.Replica("bcc", 9, I.A_BCC_VERBATIM, 100.0, 5.0, 5),    # 1458, L = 25.7 -> cells 9^3
     ]
 
 
@@ -313,6 +314,42 @@ def test_neighbour_rows_match_brute_force(shift):
             need = set(np.nonzero(dist[il] < rl - 1e-9)[0].tolist())
             assert need <= set(row.tolist()), (r, il)
             assert np.all(dist[il, row] < rl + 2e-3)
+    ctx.close()
+
+
+def test_row_history_weights_each_step_pass_by_its_rows():
+    """The list-work history (mean row length over the step force passes)
+    against the rows read back between one-step calls: a call over steps
+    s..s+1 runs the force passes of iterations s and s+1, whose rows are the
+    lists after the previous call and after this one.  A small skin makes the
+    lists change during the run.  A chunked run counts one pass per step plus
+    one per chunk."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()
+    ctx, x0, arrs = make_ctx(reps, FP32, 2, 256)
+    skin = 0.1
+    p = E.protocol("fl", 20, 40, 0, 0, skin=skin)
+    x = x0.clone()
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, True)
+    ctx.neigh_build(x, skin, 0)
+    rows = [ctx.list_stats()[0]]
+    ctx.row_history(reset=True)
+    K = 30
+    for s in range(K):
+        ctx.run_switching(p, x, v, s, s + 1)
+        rows.append(ctx.list_stats()[0])
+    mean, passes = ctx.row_history(reset=True)
+    assert passes == 2 * K
+    want = sum(rows[k] + rows[k + 1] for k in range(K)) / (2 * K)
+    assert abs(mean - want) <= 1e-12 * want, (mean, want)
+    assert len(set(rows)) > 1   # the lists were rebuilt during the run
+    ctx.set_chunk(7)
+    ctx.run_switching(p, x, v, K, K + 30)
+    mean2, passes2 = ctx.row_history()
+    assert passes2 == 30 + 5 and min(rows) * 0.8 < mean2 < max(rows) * 1.2
     ctx.close()
 
 
