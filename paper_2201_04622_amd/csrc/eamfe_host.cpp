@@ -49,7 +49,7 @@ struct eamfe_ctx {
     int n_tiles = 0;           // work units
     int nq = 1;                // unit groups (one per XCD with affinity)
     int qoff[9] = {0};         // group q holds tiles[qoff[q] .. qoff[q+1])
-    std::vector<int2> slices;  // per block of a staged pair launch: first unit, unit count (one replica)
+    std::vector<int4> slices;  // per block of a staged pair launch: first unit, units, replica's first atom, atoms
     int max_rep_atoms = 0;
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
@@ -270,9 +270,13 @@ void build_slices(eamfe_ctx* c)
         }
         most = std::max(most, per_group[x].size());
     }
-    c->slices.assign(most * c->nq, make_int2(0, 0));
+    c->slices.assign(most * c->nq, make_int4(0, 0, 0, 0));
     for (int x = 0; x < c->nq; ++x)
-        for (size_t k = 0; k < per_group[x].size(); ++k) c->slices[k * c->nq + x] = per_group[x][k];
+        for (size_t k = 0; k < per_group[x].size(); ++k) {
+            const int2 u = per_group[x][k];
+            const RepDesc& R = c->reps[c->tiles[u.x].rep];
+            c->slices[k * c->nq + x] = make_int4(u.x, u.y, R.off, R.n);
+        }
 }
 
 int build_tiles(eamfe_ctx* c)
@@ -325,9 +329,9 @@ int build_tiles(eamfe_ctx* c)
     if (!c->tiles.empty())
         HIPCHK(c, hipMemcpy(c->tiles_d.p, c->tiles.data(), c->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
     build_slices(c);
-    OK(ensure(c, c->slices_d, std::max<size_t>(1, c->slices.size()) * sizeof(int2)));
+    OK(ensure(c, c->slices_d, std::max<size_t>(1, c->slices.size()) * sizeof(int4)));
     if (!c->slices.empty())
-        HIPCHK(c, hipMemcpy(c->slices_d.p, c->slices.data(), c->slices.size() * sizeof(int2), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->slices_d.p, c->slices.data(), c->slices.size() * sizeof(int4), hipMemcpyHostToDevice));
     OK(ensure(c, c->noise_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
     OK(ensure(c, c->energy_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
     OK(ensure(c, c->reps_d, c->reps.size() * sizeof(RepDesc)));
@@ -418,7 +422,7 @@ StepArgs step_args(eamfe_ctx* c)
     for (int q = 0; q < 9; ++q) a.qoff[q] = c->qoff[q];
     // FP32 form: stage each block's replica records in LDS when they fit
     // beside the pair table (and no persistent grid was asked for)
-    a.slices = (const int2*)c->slices_d.p;
+    a.slices = (const int4*)c->slices_d.p;
     a.stage_atoms = c->max_rep_atoms;
     const long lds_force = 32L * c->n_r + 16L * c->max_rep_atoms;
     a.slice_grid = (c->precision == EAMFE_FP32 && c->have_pot && c->grid == 0 && lds_force <= c->max_lds)

@@ -137,7 +137,8 @@ struct StepArgs {
     int n_cu;               // compute units of the device
     int nq;                 // unit groups (8 with XCD affinity, else 1)
     int qoff[9];            // units of group q: tiles[qoff[q] .. qoff[q+1])
-    const int2* slices;     // [slice_grid] per block of a staged launch: first unit, units (one replica)
+    const int4* slices;     // [slice_grid] per block of a staged launch: first unit, units (one replica),
+                            // the replica's first atom and atom count
     int slice_grid;         // blocks of the staged FP32 pair launches (0: records gathered from global memory)
     int stage_atoms;        // records staged per block (atoms of the largest replica)
     int step_kernel;        // 1: integrate; 0: evaluate only (eam_forces)

@@ -73,6 +73,26 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint32_t atom, int64_t ste
     z2 = r1 * cos(twopi * u3);
 }
 
+// The same deviates split over two lanes that share the counter: half 0
+// gives (z0, z1) from u0, u1 and half 1 gives z2 from u2, u3, so a
+// wavefront evaluates one logarithm, one root and one sine/cosine pair for
+// the three.
+__device__ __forceinline__ void gauss3_half(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream, int half,
+                                            double& za, double& zb)
+{
+    const uint64_t st = (uint64_t)step;
+    uint32_t c0 = atom, c1 = (uint32_t)st, c2 = stream, c3 = (uint32_t)(st >> 32);
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double s = 2.3283064365386963e-10;
+    const double twopi = 6.283185307179586476925286766559;
+    const double ua = ((double)(half ? c2 : c0) + 1.0) * s, ub = ((double)(half ? c3 : c1) + 1.0) * s;
+    const double r = sqrt(-2.0 * log(ua));
+    double sn, cs;
+    sincos(twopi * ub, &sn, &cs);
+    za = r * cs;
+    zb = r * sn;
+}
+
 // --------------------------------------------------------------------------
 // Table access
 // --------------------------------------------------------------------------
@@ -350,19 +370,27 @@ __device__ __forceinline__ void for_each_unit(const int* qoff, int nq, Body&& bo
 // groups.  Staged form: block b serves slice b (a run of units of one
 // replica): it copies that replica's records into LDS at st and its
 // wavefronts take the slice's units in turn, gathering neighbours from LDS.
-template <bool kStage, typename Body>
-__device__ __forceinline__ void run_units(const StepArgs& a, uint4* st, Body&& body)
+// stage_table() copies the pair kernel's table into LDS; in the staged
+// form the records are copied in the same phase, behind one barrier (the
+// slice carries its replica's first atom and size, so nothing waits on
+// further descriptor loads).
+template <bool kStage, typename Table, typename Body>
+__device__ __forceinline__ void run_units(const StepArgs& a, uint4* st, Table&& stage_table, Body&& body)
 {
     if constexpr (kStage) {
-        const int2 sl = a.slices[blockIdx.x];
-        if (sl.y <= 0) return;   // uniform over the block
-        const RepDesc& R = a.reps[a.tiles[sl.x].rep];
-        for (int k = threadIdx.x; k < R.n; k += blockDim.x) st[k] = a.Q[R.off + k];
+        const int4 sl = a.slices[blockIdx.x];   // first unit, units, replica's first atom, atoms
+        if (sl.y <= 0) return;                  // uniform over the block
+        stage_table();
+        for (int k = threadIdx.x; k < sl.w; k += blockDim.x) st[k] = a.Q[sl.z + k];
         __syncthreads();
         const int wpb = (int)(blockDim.x >> 6);
         const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
         for (int u = wib; u < sl.y; u += wpb) body(sl.x + u);
     } else {
+        if (a.has_eam) {
+            stage_table();
+            __syncthreads();
+        }
         for_each_unit(a.qoff, a.nq, body);
     }
 }
@@ -736,15 +764,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter : 0;
     const int nr = a.tab.n_r;
-    if (kLds && a.has_eam) {   // table staged once per block; its wavefronts then take units
-        const float4* g = (const float4*)a.tab.rho;
-        for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
-        if (threadIdx.x == 0) {   // padding interval: the value at r_cut
-            const float4 c = g[nr - 2];
-            lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
+    auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
+        if constexpr (kLds) {
+            const float4* g = (const float4*)a.tab.rho;
+            for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
+            if (threadIdx.x == 0) {   // padding interval: the value at r_cut
+                const float4 c = g[nr - 2];
+                lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
+            }
         }
-        __syncthreads();
-    }
+    };
     uint4* const st = (uint4*)(lds_tab + nr);   // staged form: the block's replica records, after the table
     auto unit = [&](int tix) {
     const Tile tl = a.tiles[tix];
@@ -833,16 +862,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     // thermostat noise of step `it` and (fixed centre of mass) its replica sum
     if (a.step_kernel && it < a.it_last) {
         double z[3] = {0.0, 0.0, 0.0};
-        if (valid && lane == 0) {
-            gauss3(R.seed, (uint32_t)(i - R.off), it, 0u, z[0], z[1], z[2]);
-            a.xi[i] = z[0];
-            a.xi[N + i] = z[1];
-            a.xi[2 * N + i] = z[2];
+        if constexpr (T == 1) {
+            if (valid) {
+                gauss3(R.seed, (uint32_t)(i - R.off), it, 0u, z[0], z[1], z[2]);
+                a.xi[i] = z[0];
+                a.xi[N + i] = z[1];
+                a.xi[2 * N + i] = z[2];
+            }
+        } else if (valid && lane < 2) {   // lane 0: x and y components, lane 1: z
+            double za, zb;
+            gauss3_half(R.seed, (uint32_t)(i - R.off), it, 0u, lane, za, zb);
+            if (lane == 0) {
+                z[0] = za;
+                z[1] = zb;
+                a.xi[i] = za;
+                a.xi[N + i] = zb;
+            } else {
+                z[2] = za;
+                a.xi[2 * N + i] = za;
+            }
         }
         if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
     }
     };   // unit
-    run_units<kStage>(a, st, unit);
+    run_units<kStage>(a, st, stage_table, unit);
 }
 
 // --------------------------------------------------------------------------
@@ -871,16 +914,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter : 0;
     const int nr = a.tab.n_r;
-    if (kLds && a.has_eam) {   // table staged once per block; its wavefronts then take units
-        const float4* g = (const float4*)a.tab.pair;
-        for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
-        if (threadIdx.x == 0) {   // padding interval: phi(r_cut), zero slopes
-            const float4 c = g[2 * (nr - 2)];
-            lds_tab[2 * (nr - 1)] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
-            lds_tab[2 * (nr - 1) + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
+        if constexpr (kLds) {
+            const float4* g = (const float4*)a.tab.pair;
+            for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
+            if (threadIdx.x == 0) {   // padding interval: phi(r_cut), zero slopes
+                const float4 c = g[2 * (nr - 2)];
+                lds_tab[2 * (nr - 1)] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
+                lds_tab[2 * (nr - 1) + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
-        __syncthreads();
-    }
+    };
     if (a.step_kernel && blockIdx.x == 0 && threadIdx.x == 0) *a.pending = 1;   // finish due before the next pass
     uint4* const st = (uint4*)(lds_tab + 2 * nr);   // staged form: the block's replica records, after the table
     auto unit = [&](int tix) {
@@ -1038,7 +1082,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 
     unit_partial<3>(e, a.energy_part, R, tl.idx);
     };   // unit
-    run_units<kStage>(a, st, unit);
+    run_units<kStage>(a, st, stage_table, unit);
 }
 
 // After a force pass: each replica's U_EAM and |x - x0|^2 from the unit
