@@ -926,6 +926,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         }
     };
     if (a.step_kernel && blockIdx.x == 0 && threadIdx.x == 0) *a.pending = 1;   // finish due before the next pass
+    // this step's lambda values, read once per block
+    const double lam_it = a.step_kernel ? a.lam[it] : 0.0;
+    const double lam_next = a.step_kernel && it < a.it_last ? a.lam[it + 1] : 0.0;
     uint4* const st = (uint4*)(lds_tab + 2 * nr);   // staged form: the block's replica records, after the table
     auto unit = [&](int tix) {
     const Tile tl = a.tiles[tix];
@@ -1030,18 +1033,39 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         ep += __shfl_xor(ep, o, T);
     }
 
+    // the atom's operands of the integration, issued before the replica's
+    // noise total so that the two latencies overlap (i is in range on every lane)
+    const bool stepping = a.step_kernel != 0, opening = stepping && it < a.it_last;
+    const double x0i[3] = {a.x0[i], a.x0[N + i], a.x0[2 * N + i]};
+    const double eemb = a.has_eam ? a.e_emb[i] : 0.0;
+    const int nrow = a.has_eam ? a.nnb[i] : 0;
+    double vi[3] = {0.0, 0.0, 0.0}, xii[3] = {0.0, 0.0, 0.0}, xr[3] = {0.0, 0.0, 0.0};
+    if (stepping) {
+        vi[0] = a.v[i];
+        vi[1] = a.v[N + i];
+        vi[2] = a.v[2 * N + i];
+    }
+    if (opening) {
+        xii[0] = a.xi[i];
+        xii[1] = a.xi[N + i];
+        xii[2] = a.xi[2 * N + i];
+        xr[0] = a.xref[i];
+        xr[1] = a.xref[N + i];
+        xr[2] = a.xref[2 * N + i];
+    }
+
     // the replica's thermostat noise of this step, from the density pass's unit partials
     double zsum[3] = {0.0, 0.0, 0.0};
-    if (a.step_kernel && it < a.it_last && a.fix_com) replica_total<3>(a.noise_part, R, zsum);
+    if (opening && a.fix_com) replica_total<3>(a.noise_part, R, zsum);
 
     double e[3] = {0.0, 0.0, 0.0};   // U_EAM contribution, |x - x0|^2, row length (list work of the pass)
     if (valid && lane == 0) {
         const double fe[3] = {Acc<real>::fin(f0), Acc<real>::fin(f1), Acc<real>::fin(f2)};
         double x[3] = {pi.x, pi.y, pi.z};
-        const double d[3] = {x[0] - a.x0[i], x[1] - a.x0[N + i], x[2] - a.x0[2 * N + i]};
-        e[0] = a.has_eam ? a.e_emb[i] + 0.5 * Acc<real>::fin(ep) : 0.0;
+        const double d[3] = {x[0] - x0i[0], x[1] - x0i[1], x[2] - x0i[2]};
+        e[0] = a.has_eam ? eemb + 0.5 * Acc<real>::fin(ep) : 0.0;
         e[1] = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        e[2] = a.has_eam ? (double)a.nnb[i] : 0.0;
+        e[2] = (double)nrow;
         if (!isfinite(fe[0] + fe[1] + fe[2] + e[0] + e[1])) atomicOr(a.status, ST_NONFINITE);
         if (a.f_out) {
             a.f_out[i] = fe[0];
@@ -1049,27 +1073,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
             a.f_out[2 * N + i] = fe[2];
         }
         if (a.e_atom_out) a.e_atom_out[i] = e[0];
-        if (a.step_kernel) {
+        if (stepping) {
             const double hdt_m = 0.5 * a.dt * R.inv_m;
-            double v[3] = {a.v[i], a.v[N + i], a.v[2 * N + i]};
+            double v[3] = {vi[0], vi[1], vi[2]};
             double F[3];
             if (it > a.it_first) {   // closing kick of step it-1 at lambda_it
-                total_force(a.mode, fe, d, R.k, R.k2, a.lam[it], F);
+                total_force(a.mode, fe, d, R.k, R.k2, lam_it, F);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) v[c] += hdt_m * F[c];
             }
-            if (it < a.it_last) {    // step it: B A O A with lambda_{it+1}
-                total_force(a.mode, fe, d, R.k, R.k2, a.lam[it + 1], F);
+            if (opening) {    // step it: B A O A with lambda_{it+1}
+                total_force(a.mode, fe, d, R.k, R.k2, lam_next, F);
                 const double inv_n = 1.0 / (double)R.n;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     v[c] += hdt_m * F[c];
                     x[c] += 0.5 * a.dt * v[c];
                     const double m = a.fix_com ? zsum[c] * inv_n : 0.0;
-                    v[c] = a.c1 * v[c] + R.c2 * (a.xi[c * N + i] - m);
+                    v[c] = a.c1 * v[c] + R.c2 * (xii[c] - m);
                     x[c] += 0.5 * a.dt * v[c];
                 }
-                const double r0 = x[0] - a.xref[i], r1 = x[1] - a.xref[N + i], r2 = x[2] - a.xref[2 * N + i];
+                const double r0 = x[0] - xr[0], r1 = x[1] - xr[1], r2 = x[2] - xr[2];
                 if (r0 * r0 + r1 * r1 + r2 * r2 > a.half_skin2) a.rebuild[tl.rep] = 1;
             }
             a.Pn[i] = make_double4(x[0], x[1], x[2], 0.0);
