@@ -317,6 +317,24 @@ int eamfe_fl_free_energy(int n, const double* W_fwd, const double* W_bwd, double
                          double V, double T, double k, double mass, int add_cm,
                          double* F0, double* E_diss, double* F0_err);
 
+/* Jarzynski's equality (Eq. jarz): dF = -kB T ln(mean_i exp(-W_i / kB T))
+ * over n realizations W[n] (host, eV) of one switching leg, taken as a
+ * shifted exponential average so no exponential overflows.  dF_err (may be
+ * NULL) is the first-order error, kB T s_e / (sqrt(n) e_mean), with e the
+ * shifted exponentials and s_e their sample standard deviation (NaN for
+ * n = 1).  EAMFE_EINVAL for n < 1, T <= 0 or NULL W. */
+int eamfe_jarzynski(int n, const double* W, double T, double* dF, double* dF_err);
+
+/* The works of the two switching legs from cumulative per-step work traces
+ * W_trace[n_rep][stride] (host FP64, column s = the work after step s, as
+ * run_switching writes them) of protocol p: the forward leg is steps
+ * n_eq .. n_eq + n_sw - 1, the backward leg the n_sw steps after the first
+ * hold.  W_fwd[r] = W(n_eq + n_sw - 1) - W(n_eq - 1) (the latter 0 when
+ * n_eq = 0), W_bwd[r] likewise.  EAMFE_EINVAL if the trace is shorter than
+ * the backward leg's end. */
+int eamfe_switch_works(const eamfe_protocol* p, int n_rep, const double* W_trace, int64_t stride, double* W_fwd,
+                       double* W_bwd);
+
 /* Reversible scaling (Eq. rs): from one replica's cumulative work trace
  * W_trace[S] of an RS protocol and F0(T0), the free energy on n_T
  * temperatures T_grid in [T0, T0/lambda_f]:

@@ -1573,6 +1573,41 @@ int eamfe_fl_free_energy(int n, const double* Wf, const double* Wb, double n_eff
     return EAMFE_OK;
 }
 
+int eamfe_jarzynski(int n, const double* W, double T, double* dF, double* err)
+{
+    if (n < 1 || !W || !(T > 0.0)) return EAMFE_EINVAL;
+    const double b = 1.0 / (kB * T);
+    double m = -INFINITY;   // shift: the largest exponent
+    for (int i = 0; i < n; ++i) m = std::max(m, -b * W[i]);
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += std::exp(-b * W[i] - m);
+    const double mean = s / n;
+    if (dF) *dF = -(m + std::log(mean)) / b;
+    if (err) {
+        double var = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double d = std::exp(-b * W[i] - m) - mean;
+            var += d * d;
+        }
+        *err = n > 1 ? std::sqrt(var / (n - 1)) / (std::sqrt((double)n) * mean * b) : NAN;
+    }
+    return EAMFE_OK;
+}
+
+int eamfe_switch_works(const eamfe_protocol* p, int n_rep, const double* W, int64_t stride, double* Wf, double* Wb)
+{
+    if (check_protocol(p) || n_rep < 1 || !W || !Wf || !Wb || p->n_sw < 1) return EAMFE_EINVAL;
+    const int64_t e0 = p->n_eq, e1 = p->n_eq + p->n_sw;
+    const int64_t b0 = e1 + p->n_hold, b1 = b0 + p->n_sw;
+    if (stride < b1) return EAMFE_EINVAL;
+    for (int r = 0; r < n_rep; ++r) {
+        const double* w = W + (size_t)r * stride;
+        Wf[r] = w[e1 - 1] - (e0 > 0 ? w[e0 - 1] : 0.0);
+        Wb[r] = w[b1 - 1] - w[b0 - 1];
+    }
+    return EAMFE_OK;
+}
+
 int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W, double F0_T0, double T0, double n_eff, int n_T,
                          const double* T_grid, double* F_out)
 {

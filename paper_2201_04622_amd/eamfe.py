@@ -91,6 +91,8 @@ def lib():
         "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fl_free_energy": (i32, [i32, _dp, _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp, _dp]),
         "eamfe_rs_free_energy": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, i32, _dp, _dp]),
+        "eamfe_jarzynski": (i32, [i32, _dp, dbl, _dp, _dp]),
+        "eamfe_switch_works": (i32, [C.POINTER(Protocol), i32, _dp, i64, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -138,6 +140,23 @@ def fl_free_energy(W_fwd, W_bwd, n_eff, T, k, mass, N=None, V=None):
                                           float(N or 0), float(V or 0), float(T), float(k), float(mass), int(add),
                                           C.byref(F0), C.byref(Ed), C.byref(err)))
     return F0.value, Ed.value, err.value
+
+
+def jarzynski(W, T):
+    """(dF, standard error) of one switching leg's works (Eq. jarz)."""
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    dF, err = C.c_double(), C.c_double()
+    _chk(None, lib().eamfe_jarzynski(len(Wc), Wc.ctypes.data_as(_dp), float(T), C.byref(dF), C.byref(err)))
+    return dF.value, err.value
+
+
+def switch_works(p: Protocol, W_trace):
+    """(W_fwd, W_bwd) per replica from cumulative work traces [n_rep, S]."""
+    W = np.ascontiguousarray(np.atleast_2d(W_trace), dtype=np.float64)
+    Wf, Wb = np.zeros(W.shape[0]), np.zeros(W.shape[0])
+    _chk(None, lib().eamfe_switch_works(C.byref(p), W.shape[0], W.ctypes.data_as(_dp), W.shape[1],
+                                        Wf.ctypes.data_as(_dp), Wb.ctypes.data_as(_dp)))
+    return Wf, Wb
 
 
 def rs_free_energy(p: Protocol, W_trace, F0_T0, T0, n_eff, T_grid):

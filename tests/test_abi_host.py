@@ -98,3 +98,62 @@ def test_rs_estimator_matches_oracle():
     fw, bw = OE.rs_work_curves(W, 50, 400, 30)
     ref = OE.reversible_scaling(-4.2, 100.0, 0.0625, 127, fw, bw, T)
     assert np.abs(got - ref).max() < 1e-10
+
+
+def test_jarzynski_matches_oracle_and_its_invariants():
+    """Eq. jarz in the library against the oracle's estimator, and properties
+    that fix it independently: a constant work gives that work, a shift of
+    every work shifts the estimate by the same amount, and the exponential
+    average never exceeds the mean work (Jensen)."""
+    rng = np.random.default_rng(7)
+    for T in (100.0, 300.0, 1400.0):
+        for n in (1, 5, 64):
+            W = 0.3 + 0.08 * rng.standard_normal(n)
+            dF, err = E.jarzynski(W, T)
+            assert dF == pytest.approx(OE.jarzynski(W, T), abs=1e-12)
+            assert dF <= W.mean() + 1e-15
+            assert E.jarzynski(W + 2.5, T)[0] == pytest.approx(dF + 2.5, abs=1e-12)
+            assert (n == 1 and np.isnan(err)) or err >= 0.0
+        assert E.jarzynski(np.full(9, -1.75), T)[0] == pytest.approx(-1.75, abs=1e-14)
+    # far-apart works: the shifted average neither overflows nor underflows
+    assert E.jarzynski(np.array([-500.0, 500.0]), 100.0)[0] == pytest.approx(-500.0 + 100.0 * OE.KB * np.log(2.0))
+    with pytest.raises(E.EamfeError):
+        E.jarzynski(np.zeros(3), 0.0)
+
+
+def test_jarzynski_error_matches_the_spread_of_estimates():
+    """The reported standard error against the scatter of the estimator over
+    many independent samples of Gaussian works (whose exact value is
+    mu - sigma^2 / (2 kB T))."""
+    rng = np.random.default_rng(11)
+    T, mu, sd, n = 300.0, 0.4, 0.02, 200
+    est, errs = [], []
+    for _ in range(400):
+        dF, err = E.jarzynski(mu + sd * rng.standard_normal(n), T)
+        est.append(dF)
+        errs.append(err)
+    est = np.array(est)
+    assert np.mean(errs) == pytest.approx(est.std(ddof=1), rel=0.15)
+    assert est.mean() == pytest.approx(mu - sd ** 2 / (2 * OE.KB * T), abs=3 * est.std(ddof=1) / np.sqrt(len(est)) + 1e-4)
+
+
+def test_switch_works_take_the_two_legs():
+    """Leg works from cumulative traces: the forward leg is the n_sw steps
+    after the equilibration, the backward leg the n_sw steps after the hold."""
+    p = E.protocol("fl", 7, 11, 5, 3)
+    S = 7 + 2 * 11 + 5 + 3
+    rng = np.random.default_rng(3)
+    inc = rng.standard_normal((4, S))
+    inc[:, :7] = 0.0                       # no work while lambda is held
+    inc[:, 18:23] = 0.0
+    inc[:, 34:] = 0.0
+    W = np.cumsum(inc, axis=1)
+    Wf, Wb = E.switch_works(p, W)
+    assert np.allclose(Wf, inc[:, 7:18].sum(1), atol=1e-13)
+    assert np.allclose(Wb, inc[:, 23:34].sum(1), atol=1e-13)
+    p0 = E.protocol("fl", 0, 11, 5, 0)
+    W0 = np.cumsum(rng.standard_normal((2, 27)), axis=1)
+    Wf0, Wb0 = E.switch_works(p0, W0)
+    assert np.allclose(Wf0, W0[:, 10], atol=0) and np.allclose(Wb0, W0[:, 26] - W0[:, 15], atol=0)
+    with pytest.raises(E.EamfeError):
+        E.switch_works(p, W[:, : S - 4])   # the backward leg ends at step 33
