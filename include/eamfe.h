@@ -180,6 +180,14 @@ int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capaci
  * overflow is counted once. */
 int eamfe_row_history(eamfe_ctx* ctx, double* mean_len, int64_t* passes, int reset);
 
+/* Mean-squared displacement of each replica's atoms at x_dev (device SoA
+ * [3][N_tot] FP64) from its lattice sites x0, with the replica's
+ * centre-of-mass displacement removed (Eq. msd and the spring-constant
+ * choice around it: k = 3 kB T / msd, averaged over an equilibrium run at the
+ * size and temperature of the switching runs).  msd[n_rep] is a host array in
+ * A^2.  Synchronises. */
+int eamfe_msd(eamfe_ctx* ctx, const double* x_dev, double* msd);
+
 /* Copy the current Verlet rows (for inspection): nnb_dev[N_tot] row lengths,
  * nbr_dev[N_tot][cap] global atom ids in row order, -1 past each row's end
  * (may be NULL; cap >= the row capacity reported by eamfe_list_stats).

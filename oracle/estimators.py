@@ -25,6 +25,20 @@ def fixed_cm_correction(N, V, T, k):
     return KB * T * np.log((N / V) * (2.0 * np.pi * KB * T / (N * k)) ** 1.5)
 
 
+def msd_com_removed(x, x0):
+    """<(dr)^2> over the atoms of one replica, dr = x - x0 minus the mean
+    displacement (the centre of mass removed), as in the spring-constant
+    choice of Eq. msd.  x, x0: [n, 3]."""
+    d = np.asarray(x, dtype=np.float64) - np.asarray(x0, dtype=np.float64)
+    d = d - d.mean(axis=0)
+    return float((d * d).sum(axis=1).mean())
+
+
+def spring_constant(msd, T):
+    """k = 3 kB T / <(dr)^2>  (Eq. msd)."""
+    return 3.0 * KB * T / msd
+
+
 def forward_backward(W_fwd, W_bwd):
     """Eq. W12 and Eq. Ediss: dF = (W12 - W21)/2 and E_diss = (W12 + W21)/2 over
     the replica means; returns (dF, E_diss, standard error of dF)."""

@@ -54,7 +54,7 @@ struct eamfe_ctx {
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d;
 
     // neighbour lists
     bool have_list = false;
@@ -858,7 +858,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -1511,6 +1511,19 @@ int eamfe_row_history(eamfe_ctx* c, double* mean_len, int64_t* passes, int reset
     if (mean_len) *mean_len = n > 0.0 ? sum / (n * c->N) : 0.0;
     if (passes) *passes = (int64_t)n;
     if (reset) HIPCHK(c, hipMemsetAsync(c->row_acc_d.p, 0, h.size() * sizeof(double), c->stream));
+    return EAMFE_OK;
+}
+
+int eamfe_msd(eamfe_ctx* c, const double* x, double* msd)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!x || !msd) return fail(c, EAMFE_EINVAL, "msd: null argument");
+    (void)hipSetDevice(c->device);
+    OK(ensure(c, c->msd_d, (size_t)c->n_rep * sizeof(double)));
+    LCHK(c, launch_msd(x, (const double*)c->x0_d.p, (const RepDesc*)c->reps_d.p, c->n_rep, c->N, (double*)c->msd_d.p,
+                       c->stream));
+    HIPCHK(c, hipMemcpyAsync(msd, c->msd_d.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return EAMFE_OK;
 }
 

@@ -181,6 +181,8 @@ int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStre
 // pass that no list pass follows
 int launch_finish(const StepArgs& a, hipStream_t s);
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);
+// per-replica mean-squared displacement from x0 with the centre of mass removed -> out[n_rep] (device)
+int launch_msd(const double* x, const double* x0, const RepDesc* reps, int n_rep, int N, double* out, hipStream_t s);
 int launch_adjoint(const AdjointArgs& a, int precision, int grid, hipStream_t s);
 // Coefficient-bin sums -> knot gradients.  out[r][f][k] += w[r] dU_r/dtheta_{f,k}
 // (per replica), or out[f][k] += sum_r w[r] dU_r/dtheta_{f,k} when reduce;

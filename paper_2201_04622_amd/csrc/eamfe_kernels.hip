@@ -1397,6 +1397,50 @@ static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s
     return (int)hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// Mean-squared displacement from the lattice sites with the centre-of-mass
+// displacement removed (Eq. msd): one block per replica, per-thread sums in a
+// fixed stride, then a fixed tree.  msd = sum |d|^2 / n - |sum d / n|^2.
+// --------------------------------------------------------------------------
+constexpr int kMsdBlock = 256;
+
+__global__ __launch_bounds__(kMsdBlock) void k_msd(const double* x, const double* x0, const RepDesc* reps, int N,
+                                                   double* out)
+{
+    __shared__ double sh[4][kMsdBlock];
+    const RepDesc& R = reps[blockIdx.x];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < R.n; k += blockDim.x) {
+        const int i = R.off + k;
+        const double d0 = x[i] - x0[i], d1 = x[N + i] - x0[N + i], d2 = x[2 * N + i] - x0[2 * N + i];
+        s[0] += d0;
+        s[1] += d1;
+        s[2] += d2;
+        s[3] += d0 * d0 + d1 * d1 + d2 * d2;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int h = kMsdBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = (double)R.n;
+        const double m0 = sh[0][0] / n, m1 = sh[1][0] / n, m2 = sh[2][0] / n;
+        out[blockIdx.x] = sh[3][0] / n - (m0 * m0 + m1 * m1 + m2 * m2);
+    }
+}
+
+int launch_msd(const double* x, const double* x0, const RepDesc* reps, int n_rep, int N, double* out, hipStream_t s)
+{
+    if (n_rep <= 0) return 0;
+    hipLaunchKernelGGL(k_msd, dim3(n_rep), dim3(kMsdBlock), 0, s, x, x0, reps, N, out);
+    return (int)hipGetLastError();
+}
+
 int launch_finish(const StepArgs& a, hipStream_t s)
 {
     if (a.n_rep <= 0) return 0;

@@ -72,6 +72,7 @@ def lib():
         "eamfe_kernel_timing": (i32, [vp, _dp, C.POINTER(i64)]),
         "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
         "eamfe_row_history": (i32, [vp, _dp, C.POINTER(i64), i32]),
+        "eamfe_msd": (i32, [vp, vp, _dp]),
         "eamfe_copy_lists": (i32, [vp, vp, vp, i32]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
@@ -276,6 +277,13 @@ class Context:
         nbr = torch.zeros(self.N, cap, dtype=torch.int32, device="cuda")
         self._c(self._lib.eamfe_copy_lists(self._h, C.c_void_p(nnb.data_ptr()), C.c_void_p(nbr.data_ptr()), cap))
         return nnb, nbr
+
+    def msd(self, x):
+        """Per-replica mean-squared displacement (A^2) of x from the lattice
+        sites, centre of mass removed (Eq. msd)."""
+        out = np.zeros(self.n_rep)
+        self._c(self._lib.eamfe_msd(self._h, _ptr(x), out.ctypes.data_as(_dp)))
+        return out
 
     def row_history(self, reset=False):
         """(mean row length over the step force passes since the last reset, passes)."""

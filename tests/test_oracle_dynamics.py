@@ -197,3 +197,16 @@ def test_jarzynski_gaussian_work():
     mu, sd = 0.3, 0.6 * kT
     W = rng.normal(mu, sd, 400000)
     assert E.jarzynski(W, T) == pytest.approx(mu - sd ** 2 / (2 * kT), abs=3e-4)
+
+
+def test_msd_removes_the_centre_of_mass():
+    """The oracle's MSD with the centre of mass removed against the pair
+    identity mean_i |d_i - <d>|^2 = (1 / 2n^2) sum_ij |d_i - d_j|^2 (brute
+    force over pairs), and a rigid translation, which has none."""
+    rng = np.random.default_rng(5)
+    x0 = rng.uniform(0.0, 10.0, (17, 3))
+    d = 0.2 * rng.standard_normal((17, 3))
+    pair = sum(float(((d[i] - d[j]) ** 2).sum()) for i in range(17) for j in range(17)) / (2 * 17 ** 2)
+    assert E.msd_com_removed(x0 + d, x0) == pytest.approx(pair, rel=1e-13)
+    assert E.msd_com_removed(x0 + np.array([0.3, -1.2, 2.0]), x0) == pytest.approx(0.0, abs=1e-24)
+    assert E.spring_constant(E.msd_com_removed(x0 + d, x0), 300.0) == pytest.approx(3 * E.KB * 300.0 / pair)
