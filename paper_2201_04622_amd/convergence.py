@@ -52,7 +52,7 @@ def fl_sweep(ctx, replicas, x0, t_s_list, n_eq, n_hold, dt=0.001, damp=0.1, skin
 
     r0 = replicas[0]
     for r in replicas[1:]:
-        if (r.kind, r.n, r.a, r.T, r.k) != (r0.kind, r0.n, r0.a, r0.T, r0.k):
+        if (r.kind, r.dims, r.a, r.T, r.k, r.mass) != (r0.kind, r0.dims, r0.a, r0.T, r0.k, r0.mass):
             raise ValueError("fl_sweep: the replicas must be realizations of one system")
     N = int(x0.shape[1]) // len(replicas)
     L = np.asarray(r0.box, dtype=np.float64)

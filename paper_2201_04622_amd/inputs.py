@@ -85,18 +85,37 @@ def synthetic_eam_knots(n: int = N_KNOTS, r_cut: float = R_CUT, rho_max: float =
 # ---------------------------------------------------------------------------
 # Lattices
 # ---------------------------------------------------------------------------
+# Basis of each lattice's conventional cell in fractional coordinates, and
+# the cell's edges in units of the lattice parameter a.  hcp uses the
+# orthorhombic cell (a, sqrt(3) a, c) of two close-packed layers with the
+# ideal c = sqrt(8/3) a, so every site has 12 neighbours at distance a.
 BASIS = {
     "bcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]),
     "fcc": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]]),
+    "hcp": np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 5.0 / 6.0, 0.5], [0.0, 1.0 / 3.0, 0.5]]),
+}
+CELL = {
+    "bcc": np.array([1.0, 1.0, 1.0]),
+    "fcc": np.array([1.0, 1.0, 1.0]),
+    "hcp": np.array([1.0, np.sqrt(3.0), np.sqrt(8.0 / 3.0)]),
 }
 
 
-def lattice_sites(kind: str, n: int, a: float) -> np.ndarray:
-    """Sites of an n x n x n cubic supercell, shape [N, 3], id = ((ix*n+iy)*n+iz)*nb + b."""
+def cell_counts(n) -> tuple:
+    """Cells per axis: n for a cube of n^3 cells, or (nx, ny, nz)."""
+    if np.isscalar(n):
+        return (int(n),) * 3
+    nx, ny, nz = (int(v) for v in n)
+    return nx, ny, nz
+
+
+def lattice_sites(kind: str, n, a: float) -> np.ndarray:
+    """Sites of a supercell of nx x ny x nz conventional cells (n an int for a
+    cube), shape [N, 3], id = ((ix*ny+iy)*nz+iz)*nb + b."""
+    nx, ny, nz = cell_counts(n)
     basis = BASIS[kind]
-    idx = np.arange(n)
-    cells = np.stack(np.meshgrid(idx, idx, idx, indexing="ij"), axis=-1).reshape(-1, 3)
-    pos = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    cells = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), axis=-1).reshape(-1, 3)
+    pos = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * (CELL[kind] * a)
     return np.ascontiguousarray(pos, dtype=np.float64)
 
 
@@ -105,25 +124,30 @@ def lattice_sites(kind: str, n: int, a: float) -> np.ndarray:
 # ---------------------------------------------------------------------------
 @dataclass(frozen=True)
 class Replica:
-    kind: str            # "bcc" | "fcc"
-    n: int               # unit cells per edge
+    kind: str            # "bcc" | "fcc" | "hcp"
+    n: int               # conventional cells per edge (a cube); see cells
     a: float             # lattice constant (Angstrom)
     T: float             # thermostat temperature (K)
     k: float             # Einstein spring constant (eV/A^2); k1 for the harmonic test mode
     seed: int            # Philox key
     mass: float = MASS_FE
     k2: float = 0.0      # second spring constant (harmonic -> harmonic test mode only)
+    cells: tuple = None  # (nx, ny, nz) conventional cells of an orthorhombic supercell; None: n per edge
+
+    @property
+    def dims(self) -> tuple:
+        return cell_counts(self.n if self.cells is None else self.cells)
 
     @property
     def natoms(self) -> int:
-        return len(BASIS[self.kind]) * self.n ** 3
+        return len(BASIS[self.kind]) * int(np.prod(self.dims))
 
     @property
     def box(self) -> np.ndarray:
-        return np.full(3, self.n * self.a, dtype=np.float64)
+        return np.asarray(self.dims, dtype=np.float64) * CELL[self.kind] * self.a
 
     def sites(self) -> np.ndarray:
-        return lattice_sites(self.kind, self.n, self.a)
+        return lattice_sites(self.kind, self.dims, self.a)
 
 
 @dataclass(frozen=True)
