@@ -60,7 +60,7 @@ struct eamfe_ctx {
     bool have_list = false;
     double skin = 0.3;
     int cap = 0, ccap = 0, n_cells = 0;
-    DevBuf nbr_d, nnb_d, cell_cnt_d, cell_n_d, cell_atoms_d, cell_rep_d;
+    DevBuf nbr_d, nnb_d, cell_cnt_d, cell_atoms_d, cell_rep_d;
 
     // graph replay of the middle iterations (0 = eager launches)
     int graph_iters = 0;
@@ -366,7 +366,6 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
     a.n_rep = c->n_rep;
     a.xref = (double*)c->xref_d.p;
     a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
-    a.cell_n = (int32_t*)c->cell_n_d.p;
     a.cell_atoms = (int32_t*)c->cell_atoms_d.p;
     a.nbr = (int32_t*)c->nbr_d.p;
     a.nnb = (int32_t*)c->nnb_d.p;
@@ -377,6 +376,7 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
     a.n_cells = c->n_cells;
     a.ccap = c->ccap;
     a.cap = c->cap;
+    a.chunk = std::max(512, c->ccap);
     a.rl2 = (c->r_cut + c->skin) * (c->r_cut + c->skin);
     {
         // candidate test in single precision on folded coordinates: widen the
@@ -406,6 +406,7 @@ StepArgs step_args(eamfe_ctx* c)
     a.energy_part = (double*)c->energy_part_d.p;
     a.U_rep = (double*)c->U_rep_d.p;
     a.rebuild = (int32_t*)c->rebuild_d.p;
+    a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
     a.flag_pre = (int32_t*)c->flag_pre_d.p;
     a.pending = (int32_t*)c->pending_d.p;
     a.row_acc = (double*)c->row_acc_d.p;
@@ -479,7 +480,6 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
     OK(ensure(c, c->nbr_d, (size_t)c->N * c->cap * sizeof(int32_t)));
     OK(ensure(c, c->nnb_d, (size_t)c->N * sizeof(int32_t)));
     OK(ensure(c, c->cell_cnt_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
-    OK(ensure(c, c->cell_n_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
     OK(ensure(c, c->cell_atoms_d, (size_t)std::max(1, n_cells) * c->ccap * sizeof(int32_t)));
     OK(ensure(c, c->cell_rep_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
     HIPCHK(c, hipMemsetAsync(c->cell_cnt_d.p, 0, (size_t)std::max(1, n_cells) * sizeof(int32_t), c->stream));
@@ -859,7 +859,7 @@ int eamfe_destroy(eamfe_ctx* c)
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
                       &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->nbr_d,
-                      &c->nnb_d, &c->cell_cnt_d, &c->cell_n_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
+                      &c->nnb_d, &c->cell_cnt_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
     release(c->rho_d);
@@ -1079,10 +1079,15 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
         OK(set_rebuild_all(c));
         NeighArgs na = neigh_args(c, PA(c));
         LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
-        // the flags are cleared by the next density pass; clear them here too
+        // the flags and bin counters are cleared by the next density pass; clear them here too
         hipLaunchKernelGGL(k_fill_i32, dim3((c->n_rep + 255) / 256), dim3(256), 0, c->stream,
                            (int32_t*)c->rebuild_d.p, c->n_rep, 0);
         HIPCHK(c, hipGetLastError());
+        if (c->n_cells > 0) {
+            hipLaunchKernelGGL(k_fill_i32, dim3((c->n_cells + 255) / 256), dim3(256), 0, c->stream,
+                               (int32_t*)c->cell_cnt_d.p, c->n_cells, 0);
+            HIPCHK(c, hipGetLastError());
+        }
         if (max_neighbors > 0 || attempt >= 6) break;
         // automatic capacity: enlarge rows or bins until this configuration fits
         HIPCHK(c, hipStreamSynchronize(c->stream));

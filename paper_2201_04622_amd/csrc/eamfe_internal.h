@@ -76,7 +76,6 @@ struct NeighArgs {
     const uint4* Q;             // [N] box coordinates frac(x/L) 2^32
     double* xref;               // SoA [3][N]
     int32_t* cell_cnt;          // [n_cells]
-    int32_t* cell_n;            // [n_cells] sorted occupancy
     int32_t* cell_atoms;        // [n_cells][ccap] local atom ids
     int32_t* nbr;               // [N][cap] global atom ids
     int32_t* nnb;               // [N]
@@ -84,6 +83,7 @@ struct NeighArgs {
     int32_t* flag_pre;          // [2 (n_rep + 1)] prefix of flagged atoms, then of flagged cells
     int32_t* status;
     int N, n_cells, ccap, cap;
+    int chunk;                  // candidates staged per wavefront in the row builder (>= ccap)
     int n_rep;
     double rl2;                 // (r_cut + skin)^2
     float rl2_f;                // (r_cut + skin + margin)^2 for the single-precision candidate test
@@ -110,6 +110,7 @@ struct StepArgs {
     double* energy_part;    // [units][3] U_EAM, |x - x0|^2 and row lengths summed per unit
     double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
     int32_t* rebuild;       // [n_rep]
+    int32_t* cell_cnt;      // [n_cells] bin counters (cleared by the density pass after a rebuild)
     int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix (formed by the list pass's first kernel)
     int32_t* pending;       // [1] 1 while a force pass of a step awaits its finish
     double* row_acc;        // [n_rep + 1] row lengths summed over the step force passes, then their count

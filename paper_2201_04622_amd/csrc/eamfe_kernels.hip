@@ -4,12 +4,14 @@
 //
 //   k_bin      : finish of the previous force pass (replica energies, dH/dl,
 //                the work increment of Eq. w_irr, iteration counter) and the
-//                prefix of the replicas whose lists are due, in block 0;
-//                binning of those replicas' atoms into cells in the others;
-//   k_cellsort : each due cell's atom ids sorted, so rows have a fixed order;
-//   k_list     : Verlet rows within r_cut + skin, one wavefront per atom;
+//                prefix of the replicas whose lists are due, in blocks 0
+//                and 1; binning of those replicas' atoms into cells in the
+//                others;
+//   k_list     : Verlet rows within r_cut + skin, one wavefront per atom,
+//                each cell's members taken in id order;
 //   k_density  : rho_i = sum_j rho(r_ij) over the row, F(rho_i), F'(rho_i),
-//                and the thermostat noise of the step with its replica sum;
+//                the thermostat noise of the step with its replica sum, and
+//                the bin counters of the rebuilt replicas cleared;
 //   k_force    : pair + embedding forces, the Einstein spring, the lambda
 //                blend (Eq. interp) or scale (Eq. H_rs), the closing B
 //                half-kick of the previous step and B-A-O-A of the next one
@@ -447,10 +449,10 @@ __device__ __forceinline__ double3 sep(const RepDesc& R, const double4& a, const
 // --------------------------------------------------------------------------
 // Neighbour lists.  Rebuilds run only for replicas whose flag is set (an
 // atom moved more than skin/2 since the last build).  Atoms are binned into
-// cells of edge >= (r_cut + skin) / 2, each cell's atoms are sorted by id,
-// and every row is the in-order concatenation of the members within
-// r_cut + skin of the 5 x 5 x 5 cells around the atom's own, so rows have a
-// fixed order.
+// cells of edge >= (r_cut + skin) / 2 (in arrival order), and every row is
+// the concatenation, cell by cell in stencil order with each cell's members
+// in id order, of the members within r_cut + skin of the 5 x 5 x 5 cells
+// around the atom's own, so rows have a fixed order.
 // --------------------------------------------------------------------------
 // Prefix sums over the replicas of the atoms and of the cells to rebuild:
 // pre[r] (atoms of flagged replicas before r), pre[n_rep + 1 + r] (cells of
@@ -578,69 +580,31 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
     }
 }
 
-// Sorting of the flagged replicas' cells: 64-thread blocks take the cells
-// (work items from the prefix) in a stride; a cell's atom ids are sorted in
-// LDS (bitonic), the occupancy copied to cell_n and the bin counter reset.
-__global__ __launch_bounds__(64) void k_cellsort(NeighArgs a)
-{
-    extern __shared__ int32_t sv[];
-    const int32_t* pre = a.flag_pre + a.n_rep + 1;
-    const int total = pre[a.n_rep];
-    for (int f = blockIdx.x; f < total; f += gridDim.x) {
-        const int r = item_replica(pre, a.n_rep, f);
-        const int c = a.reps[r].cell_base + (f - pre[r]);
-        int n = a.cell_cnt[c];
-        n = n > a.ccap ? a.ccap : n;
-        int32_t* p = a.cell_atoms + (size_t)c * a.ccap;
-        int P2 = 1;
-        while (P2 < n) P2 <<= 1;
-        for (int k = threadIdx.x; k < P2; k += blockDim.x) sv[k] = k < n ? p[k] : 0x7fffffff;
-        __syncthreads();
-        for (int size = 2; size <= P2; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int k = threadIdx.x; k < P2; k += blockDim.x) {
-                    const int q = k ^ stride;
-                    if (q > k) {
-                        const int x = sv[k], y = sv[q];
-                        if ((x > y) == ((k & size) == 0)) {
-                            sv[k] = y;
-                            sv[q] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = sv[k];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            a.cell_n[c] = n;
-            a.cell_cnt[c] = 0;
-        }
-    }
-}
-
 // Rows: one wavefront per atom of a flagged replica (waves of the whole grid
 // stride over the flagged atoms, work items from the prefix).  The 125
 // stencil cells' members form one candidate stream in a fixed order (cells
-// by offset, atoms by id); each pass
-// tests 64 candidates with exact minimum-image box coordinates and appends
-// the accepted ones in stream order (ballot + prefix count) to a row buffer
-// in LDS, which is written out as whole 16-byte slabs at the end (row stores
-// inside the loop would make every pass's loads wait for them).
+// by offset, atoms by id).  The stream is staged in LDS a chunk at a time:
+// each lane copies one cell's members (their loads in flight together) and
+// sorts them (a sorting network of eight, an insertion sort beyond), so the
+// cells need no sorting pass of their own and a candidate costs one LDS read.
+// Each pass tests 64 candidates with exact minimum-image box coordinates and
+// appends the accepted ones in stream order (ballot + prefix count) to a row
+// buffer in LDS, which is written out as whole 16-byte slabs at the end (row
+// stores inside the loop would make every pass's loads wait for them).
 constexpr int kListBlock = 256;
 constexpr int kListGrid = 2048;
 constexpr int kStencil = 125;   // 5 x 5 x 5 cells
 
 __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 {
-    extern __shared__ int rowbuf[];             // [waves][cap] accepted ids of each wavefront's atom
+    extern __shared__ int rowbuf[];             // [waves][cap] accepted ids, then [waves][chunk] candidates
     __shared__ int cend[kListBlock / 64][kStencil];   // per wave: inclusive prefix of stencil cell sizes
     __shared__ int cid[kListBlock / 64][kStencil];    // per wave: global stencil cell ids
     const int lw = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int cap = a.cap, N = a.N;
     const float rl2 = a.rl2_f;
     int* row = rowbuf + (size_t)w * cap;
+    int* cb = rowbuf + (size_t)(kListBlock / 64) * cap + (size_t)w * a.chunk;   // this wave's candidate chunk
     const int32_t* pre = a.flag_pre;
     const int total = pre[n_rep];
     const uint64_t below = (1ull << lw) - 1ull;
@@ -683,7 +647,7 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
                     const int uy = (cy + (q / 5) % 5 - 2 + R.nc[1]) % R.nc[1];
                     const int uz = (cz + q % 5 - 2 + R.nc[2]) % R.nc[2];
                     c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
-                    n_c = a.cell_n[c];
+                    n_c = min(a.cell_cnt[c], a.ccap);
                 }
                 int incl = n_c;
 #pragma unroll
@@ -699,33 +663,116 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
                 tot_c = __builtin_amdgcn_readlane(incl, 63);
             }
             __builtin_amdgcn_wave_barrier();
-            // four passes per iteration: their independent loads are in flight together
-            constexpr int U = 4;
-            for (int k0 = 0; k0 < tot_c; k0 += 64 * U) {
-                int jl[U];
-                uint4 qj[U];
+            constexpr int U = 4;   // passes per iteration: their independent loads are in flight together
+            int q0 = 0, base = 0;  // first stencil cell of the chunk, candidates before it
+            while (q0 < kStencil) {
+                // the cells (up to 128, two per lane) whose members fit the chunk
+                // (a cell always does: chunk >= ccap)
+                int q1 = q0;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int k = k0 + 64 * u + lw;
-                    jl[u] = -1;
-                    if (k < tot_c) {
-                        int q = 0;   // first stencil cell whose inclusive end exceeds k
+                for (int h = 0; h < 2; ++h) {
+                    const int qq = q0 + 64 * h + lw;
+                    const int c = __popcll(__ballot(qq < kStencil && cend[w][qq] - base <= a.chunk));
+                    if (q1 == q0 + 64 * h) q1 += c;   // uniform
+                }
+                q1 = q1 > q0 ? q1 : q0 + 1;
+                const int end = cend[w][q1 - 1] - base;
+                // lane l stages cells q0 + l and q0 + 64 + l in id order with a
+                // sorting network (Batcher's odd-even merge): eight inputs, or
+                // sixteen when some cell of the wavefront holds more than eight
+                // (a uniform branch), an insertion sort beyond
+                int s0[2], n[2];
+                const int32_t* src[2];
 #pragma unroll
-                        for (int step = 64; step > 0; step >>= 1)
-                            if (q + step <= kStencil - 1 && cend[w][q + step - 1] <= k) q += step;
-                        const int slot = k - (q ? cend[w][q - 1] : 0);
-                        jl[u] = a.cell_atoms[(size_t)cid[w][q] * a.ccap + slot];
+                for (int h = 0; h < 2; ++h) {
+                    const int qq = q0 + 64 * h + lw;
+                    const bool mine = qq < q1;
+                    s0[h] = mine ? (qq ? cend[w][qq - 1] : 0) - base : 0;
+                    n[h] = mine ? cend[w][qq] - base - s0[h] : 0;
+                    src[h] = a.cell_atoms + (size_t)(mine ? cid[w][qq] : 0) * a.ccap;
+                }
+                auto cmpx = [](int* v, int p, int r) {
+                    const int lo = min(v[p], v[r]), hi = max(v[p], v[r]);
+                    v[p] = lo;
+                    v[r] = hi;
+                };
+                if (__ballot(n[0] > 8 || n[1] > 8) == 0) {
+                    int m[2][8];   // both cells' loads in flight together
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) m[h][t] = t < n[h] ? src[h][t] : 0x7fffffff;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        int* v = m[h];
+                        cmpx(v, 0, 1); cmpx(v, 2, 3); cmpx(v, 4, 5); cmpx(v, 6, 7);
+                        cmpx(v, 0, 2); cmpx(v, 1, 3); cmpx(v, 4, 6); cmpx(v, 5, 7);
+                        cmpx(v, 1, 2); cmpx(v, 5, 6);
+                        cmpx(v, 0, 4); cmpx(v, 1, 5); cmpx(v, 2, 6); cmpx(v, 3, 7);
+                        cmpx(v, 2, 4); cmpx(v, 3, 5);
+                        cmpx(v, 1, 2); cmpx(v, 3, 4); cmpx(v, 5, 6);
+#pragma unroll
+                        for (int t = 0; t < 8; ++t)
+                            if (t < n[h]) cb[s0[h] + t] = v[t];
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        int v[16];
+#pragma unroll
+                        for (int t = 0; t < 16; ++t) v[t] = t < n[h] ? src[h][t] : 0x7fffffff;
+                        cmpx(v, 0, 1); cmpx(v, 2, 3); cmpx(v, 0, 2); cmpx(v, 1, 3); cmpx(v, 1, 2);
+                        cmpx(v, 4, 5); cmpx(v, 6, 7); cmpx(v, 4, 6); cmpx(v, 5, 7); cmpx(v, 5, 6);
+                        cmpx(v, 0, 4); cmpx(v, 2, 6); cmpx(v, 2, 4); cmpx(v, 1, 5); cmpx(v, 3, 7);
+                        cmpx(v, 3, 5); cmpx(v, 1, 2); cmpx(v, 3, 4); cmpx(v, 5, 6); cmpx(v, 8, 9);
+                        cmpx(v, 10, 11); cmpx(v, 8, 10); cmpx(v, 9, 11); cmpx(v, 9, 10); cmpx(v, 12, 13);
+                        cmpx(v, 14, 15); cmpx(v, 12, 14); cmpx(v, 13, 15); cmpx(v, 13, 14); cmpx(v, 8, 12);
+                        cmpx(v, 10, 14); cmpx(v, 10, 12); cmpx(v, 9, 13); cmpx(v, 11, 15); cmpx(v, 11, 13);
+                        cmpx(v, 9, 10); cmpx(v, 11, 12); cmpx(v, 13, 14); cmpx(v, 0, 8); cmpx(v, 4, 12);
+                        cmpx(v, 4, 8); cmpx(v, 2, 10); cmpx(v, 6, 14); cmpx(v, 6, 10); cmpx(v, 2, 4);
+                        cmpx(v, 6, 8); cmpx(v, 10, 12); cmpx(v, 1, 9); cmpx(v, 5, 13); cmpx(v, 5, 9);
+                        cmpx(v, 3, 11); cmpx(v, 7, 15); cmpx(v, 7, 11); cmpx(v, 3, 5); cmpx(v, 7, 9);
+                        cmpx(v, 11, 13); cmpx(v, 1, 2); cmpx(v, 3, 4); cmpx(v, 5, 6); cmpx(v, 7, 8);
+                        cmpx(v, 9, 10); cmpx(v, 11, 12); cmpx(v, 13, 14);
+#pragma unroll
+                        for (int t = 0; t < 16; ++t)
+                            if (t < n[h]) cb[s0[h] + t] = v[t];
+                        if (n[h] > 16) {   // the rest in, then an insertion sort of the whole cell
+                            for (int t = 16; t < n[h]; ++t) cb[s0[h] + t] = src[h][t];
+                            for (int t = 1; t < n[h]; ++t) {
+                                const int x = cb[s0[h] + t];
+                                int u = t;
+                                while (u > 0 && cb[s0[h] + u - 1] > x) {
+                                    cb[s0[h] + u] = cb[s0[h] + u - 1];
+                                    --u;
+                                }
+                                cb[s0[h] + u] = x;
+                            }
+                        }
                     }
                 }
+                __builtin_amdgcn_wave_barrier();
+                for (int k0 = 0; k0 < end; k0 += 64 * U) {
+                    int jl[U];
+                    uint4 qj[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) qj[u] = a.Q[roff + (jl[u] < 0 ? il : jl[u])];
+                    for (int u = 0; u < U; ++u) {
+                        const int k = k0 + 64 * u + lw;
+                        jl[u] = k < end ? cb[k] : -1;
+                    }
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const float dx = (float)(int)(qi.x - qj[u].x) * sx, dy = (float)(int)(qi.y - qj[u].y) * sy,
-                                dz = (float)(int)(qi.z - qj[u].z) * sz;
-                    const bool acc = jl[u] >= 0 && jl[u] != il && dx * dx + dy * dy + dz * dz < rl2;
-                    append(acc, roff + jl[u]);
+                    for (int u = 0; u < U; ++u) qj[u] = a.Q[roff + (jl[u] < 0 ? il : jl[u])];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const float dx = (float)(int)(qi.x - qj[u].x) * sx, dy = (float)(int)(qi.y - qj[u].y) * sy,
+                                    dz = (float)(int)(qi.z - qj[u].z) * sz;
+                        const bool acc = jl[u] >= 0 && jl[u] != il && dx * dx + dy * dy + dz * dz < rl2;
+                        append(acc, roff + jl[u]);
+                    }
                 }
+                __builtin_amdgcn_wave_barrier();   // the chunk is refilled next
+                base = cend[w][q1 - 1];
+                q0 = q1;
             }
         }
         // pad the last slab with the atom itself (cap is a multiple of 32), then
@@ -883,6 +930,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
             }
         }
         if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
+    }
+    // a replica rebuilt in this step: the list pass has read its cell counters,
+    // which are cleared here for its next binning
+    if (a.cell_cnt && R.nc[0] > 0 && a.flag_pre[tl.rep + 1] > a.flag_pre[tl.rep]) {
+        const int ncell = R.nc[0] * R.nc[1] * R.nc[2];
+        for (int c = tl.idx * 64 + wave_lane(); c < ncell; c += R.n_tiles * 64) a.cell_cnt[R.cell_base + c] = 0;
     }
     };   // unit
     run_units<kStage>(a, st, stage_table, unit);
@@ -1239,15 +1292,10 @@ int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int 
     if (a.N <= 0) return 0;
     const int bin_blocks = 2 + std::min(1024, (a.N + kBinBlock - 1) / kBinBlock);
     hipLaunchKernelGGL(k_bin, dim3(bin_blocks), dim3(kBinBlock), 0, s, a, st);
-    if (a.n_cells > 0) {
-        int p2 = 1;
-        while (p2 < a.ccap) p2 <<= 1;
-        hipLaunchKernelGGL(k_cellsort, dim3(4096), dim3(64), p2 * sizeof(int32_t), s, a);
-    }
     (void)lanes;
     (void)block;
-    // one row buffer per wavefront
-    const size_t lds = (size_t)((kListBlock / 64) * a.cap) * sizeof(int);
+    // one row buffer and one candidate chunk per wavefront
+    const size_t lds = (size_t)((kListBlock / 64) * (a.cap + a.chunk)) * sizeof(int);
     if (lds > 64 * 1024) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_list, dim3(kListGrid), dim3(kListBlock), lds, s, a, a.n_rep);
     return (int)hipGetLastError();
