@@ -66,15 +66,23 @@ def test_forces_and_energies_batched(opot, prec, lanes, block):
 
 
 def test_fp32_bitwise_identical_across_launch_shapes():
+    """FP32 forces and energies are bitwise the same for every lanes x block
+    shape, in both forms of the pair kernels: replica slices staged in LDS
+    (the default) and the persistent grid gathering from global memory (a
+    caller-fixed grid), with or without XCD grouping."""
     import torch
 
     import paper_2201_04622_amd.eamfe as E
     reps = _mixed_batch()
     x = None
     outs = []
-    for lanes, block in ((1, 64), (2, 256), (4, 512), (8, 1024), (16, 256)):
-        say(f"fp32 shape {lanes}x{block}")
+    for lanes, block, grid, xcd in ((1, 64, 0, 1), (2, 256, 0, 1), (4, 512, 0, 1), (8, 1024, 0, 1), (16, 256, 0, 1),
+                                    (2, 1024, 256, 1), (4, 256, 512, 0), (2, 1024, 0, 0)):
+        say(f"fp32 shape {lanes}x{block} grid {grid} xcd {xcd}")
         ctx, x0, arrs = make_ctx(reps, FP32, lanes, block)
+        ctx.set_xcd_affinity(xcd)
+        if grid:
+            ctx.set_grid(grid)
         if x is None:
             x = I.displaced(arrs["x0"], 0.06, seed=3)
         xd = E.to_soa(x)
@@ -256,7 +264,8 @@ def test_harmonic_switching_on_gpu_reaches_closed_form(oracle_lib):
 def test_overflow_replay_is_the_same_trajectory(prec):
     """Rows far too short for a dense crystal: run_switching detects the
     overflow, enlarges the lists, replays the chunk, and ends bit-identical
-    to a run that had room from the start."""
+    to a run that had room from the start, with the replayed chunk's list
+    work counted once."""
     import torch
 
     import paper_2201_04622_amd.eamfe as E
@@ -275,11 +284,15 @@ def test_overflow_replay_is_the_same_trajectory(prec):
         else:
             ctx.neigh_build(x, 0.3, 0)
         W = torch.zeros(len(reps), 160, dtype=torch.float64, device="cuda")
+        ctx.row_history(reset=True)
         ctx.run_switching(p, x, v, 0, 160, None, None, W)
-        out.append((x.cpu().numpy(), v.cpu().numpy(), W.cpu().numpy(), ctx.replays(), ctx.list_stats()))
+        out.append((x.cpu().numpy(), v.cpu().numpy(), W.cpu().numpy(), ctx.replays(), ctx.list_stats(),
+                    ctx.row_history()))
         ctx.close()
     assert out[0][3] > 0 and out[1][3] == 0
     assert out[0][4][2] >= out[0][4][1]
+    assert out[0][5][1] == out[1][5][1] == 160 + 4   # one force pass per step plus one per chunk of 40
+    assert out[0][5][0] == out[1][5][0]
     for a, b in zip(out[0][:3], out[1][:3]):
         assert np.array_equal(a, b)
 
