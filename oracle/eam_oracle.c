@@ -447,11 +447,14 @@ typedef struct orc_params {
 } orc_params;
 
 /* Potential-energy components at x: U_EAM (with forces fE), and the spring sum
- * S2 = sum |x - x0|^2 (spring force is -k (x - x0)). */
+ * S2 = sum_i s_i |x_i - x0_i|^2 with per-atom spring scales s_i (1 when ks is
+ * NULL): atom i's spring is k s_i, its force -k s_i (x_i - x0_i) (Sec. on
+ * multi-species springs: one spring constant per group of atoms). */
 typedef struct orc_comp {
     double U_eam;
     double S2;
     double* f_eam;       /* [N][3] */
+    const double* ks;    /* [N] spring scales or NULL */
 } orc_comp;
 
 static int orc_components(const orc_pot* p, const orc_params* P, int N, const double* x,
@@ -465,7 +468,11 @@ static int orc_components(const orc_pot* p, const orc_params* P, int N, const do
         memset(c->f_eam, 0, sizeof(double) * 3 * (size_t)N);
     }
     double s2 = 0.0;
-    for (int i = 0; i < 3 * N; ++i) s2 += (x[i] - x0[i]) * (x[i] - x0[i]);
+    for (int i = 0; i < N; ++i) {
+        double d2 = 0.0;
+        for (int q = 0; q < 3; ++q) d2 += (x[3 * i + q] - x0[3 * i + q]) * (x[3 * i + q] - x0[3 * i + q]);
+        s2 += (c->ks ? c->ks[i] : 1.0) * d2;
+    }
     c->S2 = s2;
     return st;
 }
@@ -490,7 +497,7 @@ static double orc_dHdl(const orc_params* P, const orc_comp* c)
 static double orc_force(const orc_params* P, const orc_comp* c, const double* x, const double* x0,
                         int idx, double lam)
 {
-    double dx = x[idx] - x0[idx];
+    double dx = (x[idx] - x0[idx]) * (c->ks ? c->ks[idx / 3] : 1.0);   /* s_i (x - x0) */
     switch (P->mode) {
     case ORC_FL: return (1.0 - lam) * c->f_eam[idx] + lam * (-P->k * dx);
     case ORC_RS: return lam * c->f_eam[idx];
@@ -541,7 +548,7 @@ void orc_init_velocities(const orc_params* P, int N, double* v)
  * after the step.  Returns a status bit set (ORC_ETABLE possible). */
 int orc_run(const orc_pot* p, const orc_params* P, int N, const double* x0, const double* L,
             double* x, double* v, int S, const double* lam, int64_t step0, double W0,
-            double* dHdl_out, double* W_out, double* e_out)
+            double* dHdl_out, double* W_out, double* e_out, const double* ks)
 {
     if (N < 1 || S < 0) return ORC_EINVAL;
     if (P->mode == ORC_FL || P->mode == ORC_RS) {
@@ -551,6 +558,7 @@ int orc_run(const orc_pot* p, const orc_params* P, int N, const double* x0, cons
     }
     int status = ORC_OK;
     orc_comp comp;
+    comp.ks = ks;
     comp.f_eam = (double*)calloc(3 * (size_t)N, sizeof(double));
     double* xi = (double*)calloc(3 * (size_t)N, sizeof(double));
     orc_nlist nl;

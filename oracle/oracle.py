@@ -70,7 +70,7 @@ def lib():
         L.orc_schedule.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _dp]
         L.orc_init_velocities.argtypes = [C.POINTER(_Params), C.c_int, _dp]
         L.orc_run.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp,
-                              C.c_int64, C.c_double, _dp, _dp, _dp]
+                              C.c_int64, C.c_double, _dp, _dp, _dp, _dp]
         L.orc_adjoint_theta.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -217,8 +217,9 @@ def init_velocities(params: RunParams, N: int):
     return v
 
 
-def run(pot, params: RunParams, x0, L, x, v, lam, step0=0, W0=0.0, energies=False):
-    """Advance (x, v) in place over len(lam)-1 steps.  Returns dHdl[S], W[S], e[S] or None, status."""
+def run(pot, params: RunParams, x0, L, x, v, lam, step0=0, W0=0.0, energies=False, spring_scale=None):
+    """Advance (x, v) in place over len(lam)-1 steps.  Returns dHdl[S], W[S], e[S] or None, status.
+    spring_scale: per-atom factors s_i of the spring constant (atom i's spring is k s_i), or None."""
     x0 = _f64(x0, (-1, 3)); L = _f64(L, (3,)); lam = _f64(lam)
     assert x.dtype == np.float64 and x.flags.c_contiguous and v.dtype == np.float64 and v.flags.c_contiguous
     N = x0.shape[0]
@@ -228,8 +229,9 @@ def run(pot, params: RunParams, x0, L, x, v, lam, step0=0, W0=0.0, energies=Fals
     hp = pot._h if pot is not None else None
     if hp is None and params.mode in ("fl", "rs"):
         raise ValueError("EAM modes need a potential")
+    ks = None if spring_scale is None else _f64(spring_scale, (N,))
     st = lib().orc_run(hp, C.byref(P), N, _p(x0), _p(L), _p(x), _p(v), S, _p(lam), int(step0), float(W0),
-                       _p(dH), _p(W), _p(e))
+                       _p(dH), _p(W), _p(e), _p(ks))
     if st & EBOX:
         raise ValueError("box too small")
     if st & ~ETABLE:

@@ -71,7 +71,7 @@ def test_nve_energy_conservation_second_order(oracle_lib, opot):
     assert drift < 5e-5
 
 
-def _hh(O, N, k1, k2, T, n_sw, reps, fix_com, n_eq=1500):
+def _hh(O, N, k1, k2, T, n_sw, reps, fix_com, n_eq=1500, scale=None):
     p = O.RunParams(mode="hh", T=T, k=k1, k2=k2, fix_com=fix_com)
     lam = O.schedule("hh", n_eq, n_sw, n_eq, 0, function=2)
     Wf, Wb = [], []
@@ -80,7 +80,7 @@ def _hh(O, N, k1, k2, T, n_sw, reps, fix_com, n_eq=1500):
         x0 = np.arange(N)[:, None] * np.array([2.0, 0.0, 0.0])
         x = x0.copy()
         v = O.init_velocities(p, N)
-        _, W, _, _ = O.run(None, p, x0, np.full(3, 1000.0), x, v, lam)
+        _, W, _, _ = O.run(None, p, x0, np.full(3, 1000.0), x, v, lam, spring_scale=scale)
         wf = W[n_eq + n_sw - 1]
         Wf.append(wf)
         Wb.append(W[-1] - wf)
@@ -210,3 +210,33 @@ def test_msd_removes_the_centre_of_mass():
     assert E.msd_com_removed(x0 + d, x0) == pytest.approx(pair, rel=1e-13)
     assert E.msd_com_removed(x0 + np.array([0.3, -1.2, 2.0]), x0) == pytest.approx(0.0, abs=1e-24)
     assert E.spring_constant(E.msd_com_removed(x0 + d, x0), 300.0) == pytest.approx(3 * E.KB * 300.0 / pair)
+
+
+def test_harmonic_to_harmonic_exact_with_per_atom_springs(oracle_lib):
+    """Two species of springs (atom i's spring k s_i, s_i = 1 or 3): between
+    Einstein crystals k1 s_i and k2 s_i the exact free-energy difference is
+    (3/2) N kB T ln(k2/k1) whatever the s_i.  An s_i missing from either the
+    spring force or the spring energy shifts <dH/dl> by the mean of 1/s_i
+    (a third here) and fails this."""
+    N, k1, k2, T = 24, 2.0, 8.0, 300.0
+    scale = np.where(np.arange(N) % 2 == 0, 1.0, 3.0)
+    Wf, Wb = _hh(oracle_lib, N, k1, k2, T, n_sw=6000, reps=32, fix_com=False, scale=scale)
+    dF, ediss, err = E.forward_backward(Wf, Wb)
+    exact = 1.5 * N * KB * T * np.log(k2 / k1)
+    assert abs(dF - exact) < 4 * err, (dF, exact, err)
+    assert exact * (1.0 - np.mean(1.0 / scale)) > 10 * err   # the test can see a missing s_i
+
+
+def test_energy_conserved_with_per_atom_springs(oracle_lib):
+    """Without friction the total energy KE + sum_i k s_i |x_i - x0_i|^2 / 2
+    of an Einstein crystal with per-atom springs is conserved by velocity
+    Verlet (to O(dt^2)): the spring force and energy use the same s_i."""
+    O = oracle_lib
+    N = 16
+    p = O.RunParams(mode="ein_rs", T=600.0, gamma=0.0, dt=0.0005, k=4.0, seed=9, fix_com=False)
+    x0 = np.zeros((N, 3)) + np.arange(N)[:, None] * 3.0
+    x = x0.copy()
+    v = O.init_velocities(p, N)
+    scale = 1.0 + 2.0 * (np.arange(N) % 3)
+    _, _, e, _ = O.run(None, p, x0, np.full(3, 1000.0), x, v, np.ones(4001), energies=True, spring_scale=scale)
+    assert np.ptp(e) < 2e-3 * np.abs(e).mean(), (np.ptp(e), e.mean())
