@@ -180,6 +180,17 @@ int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capaci
  * overflow is counted once. */
 int eamfe_row_history(eamfe_ctx* ctx, double* mean_len, int64_t* passes, int reset);
 
+/* Per-atom spring constants for systems of several species (the paper's
+ * remark on one spring constant per group of atoms, chosen from each
+ * group's mean-squared displacement, Eq. msd): s_dev[N_tot] (device FP64,
+ * copied) scales each atom's spring to k s_i, k its replica's spring
+ * constant; this enters the spring force, U_E and so dH/dl of the FL,
+ * harmonic and Einstein-RS paths.  NULL restores s_i = 1.  The Einstein
+ * reference free energy is then the sum of eamfe_einstein_free_energy over
+ * the groups, each with its own k s and atom count.  Reset by
+ * eamfe_system_setup. */
+int eamfe_set_spring_scale(eamfe_ctx* ctx, const double* s_dev);
+
 /* Mean-squared displacement of each replica's atoms at x_dev (device SoA
  * [3][N_tot] FP64) from its lattice sites x0, with the replica's
  * centre-of-mass displacement removed (Eq. msd and the spring-constant

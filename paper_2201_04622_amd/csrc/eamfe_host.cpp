@@ -54,7 +54,8 @@ struct eamfe_ctx {
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d, kscale_d;
+    bool has_kscale = false;   // per-atom spring scales set
 
     // neighbour lists
     bool have_list = false;
@@ -396,6 +397,7 @@ StepArgs step_args(eamfe_ctx* c)
     a.tiles = (const Tile*)c->tiles_d.p;
     a.reps = (const RepDesc*)c->reps_d.p;
     a.x0 = (const double*)c->x0_d.p;
+    a.kscale = c->has_kscale ? (const double*)c->kscale_d.p : nullptr;
     a.xref = (const double*)c->xref_d.p;
     a.nbr = (const int32_t*)c->nbr_d.p;
     a.nnb = (const int32_t*)c->nnb_d.p;
@@ -858,7 +860,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->kscale_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -1063,6 +1065,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->pending_d.p, 0, sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->row_acc_d.p, 0, (size_t)(n_rep + 1) * sizeof(double)));
     c->have_list = false;
+    c->has_kscale = false;
     return build_tiles(c);
 }
 
@@ -1516,6 +1519,21 @@ int eamfe_row_history(eamfe_ctx* c, double* mean_len, int64_t* passes, int reset
     if (mean_len) *mean_len = n > 0.0 ? sum / (n * c->N) : 0.0;
     if (passes) *passes = (int64_t)n;
     if (reset) HIPCHK(c, hipMemsetAsync(c->row_acc_d.p, 0, h.size() * sizeof(double), c->stream));
+    return EAMFE_OK;
+}
+
+int eamfe_set_spring_scale(eamfe_ctx* c, const double* s)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    drop_graphs(c);   // captured launches hold the old argument
+    if (!s) {
+        c->has_kscale = false;
+        return EAMFE_OK;
+    }
+    OK(ensure(c, c->kscale_d, (size_t)c->N * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(c->kscale_d.p, s, (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    c->has_kscale = true;
     return EAMFE_OK;
 }
 

@@ -100,6 +100,7 @@ struct StepArgs {
     uint4* Qn;              // [N] box coordinates after the step
     double* v;              // SoA, in place
     const double* x0;       // SoA
+    const double* kscale;   // [N] per-atom spring scales s_i (atom i's spring k s_i) or null (all 1)
     const double* xref;     // SoA, list reference positions
     const int32_t* nbr;
     const int32_t* nnb;

@@ -1090,6 +1090,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     // noise total so that the two latencies overlap (i is in range on every lane)
     const bool stepping = a.step_kernel != 0, opening = stepping && it < a.it_last;
     const double x0i[3] = {a.x0[i], a.x0[N + i], a.x0[2 * N + i]};
+    const double ks = a.kscale ? a.kscale[i] : 1.0;   // this atom's spring is k ks
     const double eemb = a.has_eam ? a.e_emb[i] : 0.0;
     const int nrow = a.has_eam ? a.nnb[i] : 0;
     double vi[3] = {0.0, 0.0, 0.0}, xii[3] = {0.0, 0.0, 0.0}, xr[3] = {0.0, 0.0, 0.0};
@@ -1115,9 +1116,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     if (valid && lane == 0) {
         const double fe[3] = {Acc<real>::fin(f0), Acc<real>::fin(f1), Acc<real>::fin(f2)};
         double x[3] = {pi.x, pi.y, pi.z};
-        const double d[3] = {x[0] - x0i[0], x[1] - x0i[1], x[2] - x0i[2]};
+        // the spring displacement weighted by the atom's spring scale: the
+        // spring force is -k ks (x - x0) and its energy k ks |x - x0|^2 / 2
+        const double d[3] = {ks * (x[0] - x0i[0]), ks * (x[1] - x0i[1]), ks * (x[2] - x0i[2])};
         e[0] = a.has_eam ? eemb + 0.5 * Acc<real>::fin(ep) : 0.0;
-        e[1] = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        e[1] = (d[0] * (x[0] - x0i[0]) + d[1] * (x[1] - x0i[1]) + d[2] * (x[2] - x0i[2]));
         e[2] = (double)nrow;
         if (!isfinite(fe[0] + fe[1] + fe[2] + e[0] + e[1])) atomicOr(a.status, ST_NONFINITE);
         if (a.f_out) {

@@ -73,6 +73,7 @@ def lib():
         "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
         "eamfe_row_history": (i32, [vp, _dp, C.POINTER(i64), i32]),
         "eamfe_msd": (i32, [vp, vp, _dp]),
+        "eamfe_set_spring_scale": (i32, [vp, vp]),
         "eamfe_copy_lists": (i32, [vp, vp, vp, i32]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
@@ -277,6 +278,11 @@ class Context:
         nbr = torch.zeros(self.N, cap, dtype=torch.int32, device="cuda")
         self._c(self._lib.eamfe_copy_lists(self._h, C.c_void_p(nnb.data_ptr()), C.c_void_p(nbr.data_ptr()), cap))
         return nnb, nbr
+
+    def set_spring_scale(self, s=None):
+        """Per-atom spring scales s_i (device float64 [N_tot]; atom i's spring
+        is k s_i) or None for uniform springs."""
+        self._c(self._lib.eamfe_set_spring_scale(self._h, _ptr(s)))
 
     def msd(self, x):
         """Per-replica mean-squared displacement (A^2) of x from the lattice
