@@ -9,7 +9,8 @@
  *   work                 W = sum_k (l_{k+1} - l_k) dH/dl(G_k)   (Eq. w_irr, discrete form)
  *   schedules            ti/spring phases and lambda(tau) forms (Sec. fl_lammps),
  *                        RS lambda(tau) = 1/(1 + tau (1/l_f - 1)) (Sec. RS in LAMMPS)
- *   estimators           Eq. W12, Eq. Ediss, Eq. fl (+ Eq. cm), Eq. rs
+ *   estimators           Eq. W12, Eq. Ediss, Eq. fl (+ Eq. cm), Eq. rs, Eq. jarz
+ *   spring constants     Eq. msd (mean-squared displacement), per-atom springs
  *
  * Conventions for every entry point:
  *   - Units are LAMMPS "metal": eV, Angstrom, ps, amu, K.
@@ -130,12 +131,17 @@ int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threa
 int eamfe_autotune(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step, const double* x_dev,
                    const double* v_dev, int trial_steps, int* lanes_out, int* block_out, double* ms_per_step);
 
-/* Persistent blocks launched for the density and force passes (rounded up
- * to a multiple of 8).  Each block stages the spline table once; each of its
- * wavefronts then takes a fixed stride of work units (the atoms of one
- * wavefront, 64/lanes atoms of one replica).  0 = as many blocks as the chip
- * holds resident at this launch shape, or fewer when every unit has its own
- * wavefront (default). */
+/* Blocks of the density and force passes.  0 (default): in EAMFE_FP32,
+ * when the pair table and the largest replica's gather records fit one
+ * block's LDS, one block per replica slice (a run of work units of one
+ * replica, about n_CU blocks in all), which copies its replica's records
+ * into LDS and gathers neighbours from there; otherwise (FP64, larger
+ * replicas) a persistent grid of as many blocks as the chip holds resident,
+ * or fewer when every unit has its own wavefront.  blocks > 0 (rounded up
+ * to a multiple of 8) asks for that persistent grid.  A work unit is the
+ * atoms of one wavefront, 64/lanes atoms of one replica; in the persistent
+ * form each wavefront takes a fixed stride of units.  Results are the same
+ * bit for bit in every form. */
 int eamfe_set_grid(eamfe_ctx* ctx, int blocks);
 int eamfe_get_grid(const eamfe_ctx* ctx, int* blocks);
 
