@@ -186,6 +186,17 @@ int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capaci
  * overflow is counted once. */
 int eamfe_row_history(eamfe_ctx* ctx, double* mean_len, int64_t* passes, int reset);
 
+/* Diagonal of each replica's pressure tensor at positions x_dev (device SoA)
+ * and velocities v_dev (device SoA, or NULL for the configurational part):
+ * P_aa = (sum_i m v_ia^2 + W_aa) / V with the pair virial W_aa = sum_{i<j}
+ * (x_i - x_j)_a f_ij,a of the EAM forces (H0).  The paper holds the
+ * hydrostatic pressure at zero with a barostat to fix the lattice parameter
+ * of its Frenkel--Ladd runs (Sec. p_fl); averaged over fixed-volume runs at
+ * trial lattice parameters this gives that lattice parameter.  P[n_rep][3]
+ * is a host array in eV/A^3 (1 eV/A^3 = 160.2177 GPa).  Synchronises;
+ * a list or bin overflow enlarges the lists and evaluates again. */
+int eamfe_pressure(eamfe_ctx* ctx, const double* x_dev, const double* v_dev, double* P);
+
 /* Per-atom spring constants for systems of several species (the paper's
  * remark on one spring constant per group of atoms, chosen from each
  * group's mean-squared displacement, Eq. msd): s_dev[N_tot] (device FP64,

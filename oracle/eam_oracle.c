@@ -217,7 +217,7 @@ static int orc_nlist_stale(const orc_nlist* nl, int N, const double* x)
  * 1/2 sum_j phi, rho[N], Fp[N].  Returns ORC_ETABLE if some rho_i > rho_max
  * (the values are still computed by continuing the last cubic). */
 static int orc_eam_impl(const orc_pot* p, int N, const double* x, const double* L, const orc_nlist* nl,
-                        double* f, double* U, double* e_atom, double* rho_out, double* Fp_out)
+                        double* f, double* U, double* e_atom, double* rho_out, double* Fp_out, double* vir)
 {
     int status = ORC_OK;
     double rc2 = p->r_cut * p->r_cut;
@@ -246,7 +246,9 @@ static int orc_eam_impl(const orc_pot* p, int N, const double* x, const double* 
         if (e_atom) e_atom[i] = Fi;
         Usum += Fi;
     }
-    /* pair energy and forces */
+    /* pair energy and forces; virial sum_{i<j} d_a f_a = (1/2) sum_i sum_j d_a f_a with
+     * d = x_i - x_j and f the force on i due to j */
+    double w[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < N; ++i) {
         int cnt = nl ? nl->cnt[i] : N;
         double fi[3] = {0.0, 0.0, 0.0};
@@ -263,7 +265,10 @@ static int orc_eam_impl(const orc_pot* p, int N, const double* x, const double* 
             double ph = orc_spline_eval(p->n_r, p->h_r, p->phi, r, &dphi);
             (void)orc_spline_eval(p->n_r, p->h_r, p->rho, r, &drho);
             double g = dphi + (Fp[i] + Fp[j]) * drho;   /* dU/dr_ij */
-            for (int c = 0; c < 3; ++c) fi[c] -= g * d[c] / r;
+            for (int c = 0; c < 3; ++c) {
+                fi[c] -= g * d[c] / r;
+                w[c] -= 0.5 * g * d[c] * d[c] / r;
+            }
             ei += 0.5 * ph;
         }
         if (f) for (int c = 0; c < 3; ++c) f[3 * i + c] = fi[c];
@@ -271,6 +276,7 @@ static int orc_eam_impl(const orc_pot* p, int N, const double* x, const double* 
         Usum += ei;
     }
     if (U) *U = Usum;
+    if (vir) for (int c = 0; c < 3; ++c) vir[c] = w[c];
     if (rho_out) memcpy(rho_out, rho, sizeof(double) * (size_t)N);
     if (Fp_out) memcpy(Fp_out, Fp, sizeof(double) * (size_t)N);
     free(rho); free(Fp);
@@ -282,7 +288,28 @@ int orc_eam(const orc_pot* p, int N, const double* x, const double* L,
 {
     for (int c = 0; c < 3; ++c)
         if (!(L[c] > 2.0 * p->r_cut)) return ORC_EBOX;   /* one image at most */
-    return orc_eam_impl(p, N, x, L, NULL, f, U, e_atom, rho, Fp);
+    return orc_eam_impl(p, N, x, L, NULL, f, U, e_atom, rho, Fp, NULL);
+}
+
+/* Diagonal of the pressure tensor of an EAM configuration (the quantity the
+ * paper holds at zero with its barostat before the Frenkel--Ladd runs):
+ * P_aa = (sum_i m v_ia^2 + W_aa) / V with the pair virial W_aa = sum_{i<j}
+ * (x_i - x_j)_a f_ij,a of the central EAM pair forces.  v may be NULL (the
+ * configurational part only).  Output P[3] in eV/A^3. */
+int orc_pressure(const orc_pot* p, int N, const double* x, const double* v, double mass, const double* L,
+                 double* P)
+{
+    for (int c = 0; c < 3; ++c)
+        if (!(L[c] > 2.0 * p->r_cut)) return ORC_EBOX;
+    double w[3];
+    int st = orc_eam_impl(p, N, x, L, NULL, NULL, NULL, NULL, NULL, NULL, w);
+    const double V = L[0] * L[1] * L[2];
+    for (int c = 0; c < 3; ++c) {
+        double k2 = 0.0;
+        if (v) for (int i = 0; i < N; ++i) k2 += v[3 * i + c] * v[3 * i + c];
+        P[c] = (mass * ORC_MVV2E * k2 + w[c]) / V;
+    }
+    return st;
 }
 
 /* Force on, energy of, and density of one atom i (for sampled checks of very
@@ -462,7 +489,7 @@ static int orc_components(const orc_pot* p, const orc_params* P, int N, const do
 {
     int st = ORC_OK;
     if (P->mode == ORC_FL || P->mode == ORC_RS) {
-        st = orc_eam_impl(p, N, x, L, nl, c->f_eam, &c->U_eam, NULL, NULL, NULL);
+        st = orc_eam_impl(p, N, x, L, nl, c->f_eam, &c->U_eam, NULL, NULL, NULL, NULL);
     } else {
         c->U_eam = 0.0;
         memset(c->f_eam, 0, sizeof(double) * 3 * (size_t)N);
@@ -641,7 +668,7 @@ int orc_adjoint_theta(const orc_pot* p, int N, const double* x, const double* L,
     double* ce = (double*)calloc(4 * (size_t)(nmax - 1), sizeof(double));
     int status = ORC_OK;
     if (!gphi || !grho || !gF || !rho || !Fp || !e || !ce) { status = ORC_ENOMEM; goto out; }
-    status = orc_eam_impl(p, N, x, L, NULL, NULL, NULL, NULL, rho, Fp);
+    status = orc_eam_impl(p, N, x, L, NULL, NULL, NULL, NULL, rho, Fp, NULL);
     for (int i = 0; i < N; ++i) {
         double t;
         int m = orc_interval(nf, p->h_rho, rho[i], &t);

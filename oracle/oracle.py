@@ -60,6 +60,7 @@ def lib():
         L.orc_pot_free.argtypes = [C.c_void_p]
         L.orc_pot_coefficients.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_eam.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_pressure.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_eam_atom.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int, _dp, _dp, _dp]
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, _dp]
@@ -141,6 +142,16 @@ class Potential:
         if st & EBOX:
             raise ValueError("box too small for a single periodic image")
         return {"U": float(U[0]), "f": f, "e_atom": e, "rho": rho, "Fp": Fp, "status": st}
+
+    def pressure(self, x, L, v=None, mass=55.845):
+        """Diagonal pressure tensor P_aa = (sum m v_a^2 + W_aa) / V, eV/A^3."""
+        x = _f64(x, (-1, 3)); L = _f64(L, (3,))
+        vv = None if v is None else _f64(v, (-1, 3))
+        P = np.zeros(3)
+        st = lib().orc_pressure(self._h, x.shape[0], _p(x), _p(vv), float(mass), _p(L), _p(P))
+        if st & EBOX:
+            raise ValueError("box too small for a single periodic image")
+        return P
 
     def eam_atom(self, x, L, i):
         x = _f64(x, (-1, 3)); L = _f64(L, (3,))

@@ -54,7 +54,7 @@ struct eamfe_ctx {
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d, kscale_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d, kscale_d, vir_d;
     bool has_kscale = false;   // per-atom spring scales set
 
     // neighbour lists
@@ -860,7 +860,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->kscale_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->kscale_d, &c->vir_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -1520,6 +1520,55 @@ int eamfe_row_history(eamfe_ctx* c, double* mean_len, int64_t* passes, int reset
     if (passes) *passes = (int64_t)n;
     if (reset) HIPCHK(c, hipMemsetAsync(c->row_acc_d.p, 0, h.size() * sizeof(double), c->stream));
     return EAMFE_OK;
+}
+
+int eamfe_pressure(eamfe_ctx* c, const double* x, const double* v, double* P)
+{
+    if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!x || !P) return fail(c, EAMFE_EINVAL, "pressure: null argument");
+    (void)hipSetDevice(c->device);
+    OK(pack(c, x));
+    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
+    OK(ensure(c, c->vir_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
+    for (int attempt = 0;; ++attempt) {
+        NeighArgs na = neigh_args(c, PA(c));
+        LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
+        StepArgs a = step_args(c);
+        a.P = PA(c);
+        a.Pn = nullptr;
+        a.Q = QA(c);
+        a.Qn = nullptr;
+        a.v = const_cast<double*>(v);
+        a.has_eam = 1;
+        a.step_kernel = 0;
+        a.mode = EAMFE_MODE_FL;
+        a.vir_part = (double*)c->vir_d.p;
+        LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+        LCHK(c, launch_force(a, c->precision, c->lanes, c->block, c->stream));
+        LCHK(c, launch_finish(a, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int st = 0;
+        HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW)) || attempt >= 6) break;
+        HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
+        const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
+        if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
+        OK(plan_lists(c, c->skin, new_cap));
+        OK(set_rebuild_all(c));
+        ++c->replays;
+    }
+    std::vector<double> part((size_t)c->n_tiles * 3);
+    HIPCHK(c, hipMemcpy(part.data(), c->vir_d.p, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int r = 0; r < c->n_rep; ++r) {   // each replica's units in order
+        const RepDesc& R = c->reps[r];
+        const double V = R.L[0] * R.L[1] * R.L[2];
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int t = 0; t < R.n_tiles; ++t) s += part[(size_t)(R.tile_base + t) * 3 + k];
+            P[3 * r + k] = s / V;
+        }
+    }
+    return read_status(c);
 }
 
 int eamfe_set_spring_scale(eamfe_ctx* c, const double* s)

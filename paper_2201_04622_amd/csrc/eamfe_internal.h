@@ -109,6 +109,7 @@ struct StepArgs {
     double* xi;             // [3][N] thermostat noise of this step
     double* noise_part;     // [units][3] thermostat noise summed per unit
     double* energy_part;    // [units][3] U_EAM, |x - x0|^2 and row lengths summed per unit
+    double* vir_part;       // [units][3] pressure evaluation: virial/2 + m v^2 per axis per unit, or null
     double* U_rep;          // [n_rep][2]: U_EAM, sum |x-x0|^2 at x
     int32_t* rebuild;       // [n_rep]
     int32_t* cell_cnt;      // [n_cells] bin counters (cleared by the density pass after a rebuild)

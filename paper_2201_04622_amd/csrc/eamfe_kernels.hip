@@ -958,7 +958,7 @@ __device__ __forceinline__ void total_force(int mode, const double (&fe)[3], con
     }
 }
 
-template <typename real, int T, bool kStage = false>
+template <typename real, int T, bool kStage = false, bool kVir = false>
 __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
@@ -996,6 +996,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     const float qsx = (float)(R.L[0] * 2.3283064365386963e-10), qsy = (float)(R.L[1] * 2.3283064365386963e-10),
                 qsz = (float)(R.L[2] * 2.3283064365386963e-10);
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, ep = 0.0;
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;   // virial (kVir): sum_j (x_i - x_j)_a f_ij,a per axis
     if (valid && a.has_eam) {
         const int n = a.nnb[i];
         const real Fpi = kQ ? (real)__uint_as_float(qi.w) : (real)pi.w;
@@ -1033,6 +1034,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 }
             }
             real p0 = (real)0, p1 = (real)0, p2 = (real)0, pe = (real)0;
+            real q0 = (real)0, q1 = (real)0, q2 = (real)0;
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
                 real ua, ub, uc, ud, wb, wc, wd;
@@ -1060,6 +1062,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                     p1 += sc * ry[s];
                     p2 += sc * rz[s];
                     pe += phi * fm;
+                    if constexpr (kVir) {
+                        q0 += sc * rx[s] * rx[s];
+                        q1 += sc * ry[s] * ry[s];
+                        q2 += sc * rz[s] * rz[s];
+                    }
                 } else {
                     const real phi = ua + ts * (ub + ts * (uc + ts * ud));
                     const real dphi = (ub + ts * ((real)2 * uc + (real)3 * ts * ud)) * inv_h;
@@ -1070,12 +1077,22 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                     p1 += sc * ry[s];
                     p2 += sc * rz[s];
                     pe += in[s] ? phi : (real)0;
+                    if constexpr (kVir) {
+                        q0 += sc * rx[s] * rx[s];
+                        q1 += sc * ry[s] * ry[s];
+                        q2 += sc * rz[s] * rz[s];
+                    }
                 }
             }
             f0 += Acc<real>::q(p0);
             f1 += Acc<real>::q(p1);
             f2 += Acc<real>::q(p2);
             ep += Acc<real>::q(pe);
+            if constexpr (kVir) {
+                w0 += Acc<real>::q(q0);
+                w1 += Acc<real>::q(q1);
+                w2 += Acc<real>::q(q2);
+            }
         });
     }
 #pragma unroll
@@ -1084,6 +1101,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         f1 += __shfl_xor(f1, o, T);
         f2 += __shfl_xor(f2, o, T);
         ep += __shfl_xor(ep, o, T);
+        if constexpr (kVir) {
+            w0 += __shfl_xor(w0, o, T);
+            w1 += __shfl_xor(w1, o, T);
+            w2 += __shfl_xor(w2, o, T);
+        }
     }
 
     // the atom's operands of the integration, issued before the replica's
@@ -1161,6 +1183,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     }
 
     unit_partial<3>(e, a.energy_part, R, tl.idx);
+    if constexpr (kVir) {   // pressure evaluation: (1/2) pair virial plus m v_a^2 of the atom, per unit
+        double pv[3] = {0.0, 0.0, 0.0};
+        if (valid && lane == 0) {
+            const double wv[3] = {Acc<real>::fin(w0), Acc<real>::fin(w1), Acc<real>::fin(w2)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double vc = a.v ? a.v[c * N + i] : 0.0;
+                pv[c] = 0.5 * wv[c] + vc * vc / R.inv_m;
+            }
+        }
+        unit_partial<3>(pv, a.vir_part, R, tl.idx);
+    }
     };   // unit
     run_units<kStage>(a, st, stage_table, unit);
 }
@@ -1402,6 +1436,12 @@ static void density_one(const StepArgs& a, int block, hipStream_t s)
 template <typename real, int T>
 static void force_one(const StepArgs& a, int block, hipStream_t s)
 {
+    if (a.vir_part) {   // pressure evaluation (not a step): the persistent form with the virial
+        const size_t sh = lds_bytes<real>(a, 2);
+        const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, true>);
+        hipLaunchKernelGGL((k_force<real, T, false, true>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
+        return;
+    }
     if constexpr (sizeof(real) == 4) {
         if (staged<real>(a)) {
             const size_t sh = lds_bytes<real>(a, 2) + (size_t)a.stage_atoms * sizeof(uint4);

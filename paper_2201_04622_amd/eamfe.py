@@ -74,6 +74,7 @@ def lib():
         "eamfe_row_history": (i32, [vp, _dp, C.POINTER(i64), i32]),
         "eamfe_msd": (i32, [vp, vp, _dp]),
         "eamfe_set_spring_scale": (i32, [vp, vp]),
+        "eamfe_pressure": (i32, [vp, vp, vp, _dp]),
         "eamfe_copy_lists": (i32, [vp, vp, vp, i32]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
@@ -278,6 +279,13 @@ class Context:
         nbr = torch.zeros(self.N, cap, dtype=torch.int32, device="cuda")
         self._c(self._lib.eamfe_copy_lists(self._h, C.c_void_p(nnb.data_ptr()), C.c_void_p(nbr.data_ptr()), cap))
         return nnb, nbr
+
+    def pressure(self, x, v=None):
+        """Per-replica diagonal pressure tensor [n_rep, 3] (eV/A^3) at x (and
+        velocities v, or the configurational part only)."""
+        out = np.zeros((self.n_rep, 3))
+        self._c(self._lib.eamfe_pressure(self._h, _ptr(x), _ptr(v), out.ctypes.data_as(_dp)))
+        return out
 
     def set_spring_scale(self, s=None):
         """Per-atom spring scales s_i (device float64 [N_tot]; atom i's spring

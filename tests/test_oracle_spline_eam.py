@@ -165,3 +165,33 @@ def test_small_box_rejected(opot):
     x = I.lattice_sites("bcc", 3, 2.855)   # L = 8.57 < 2 r_cut
     with pytest.raises(ValueError):
         opot.eam(x, np.full(3, 3 * 2.855))
+
+
+@pytest.mark.parametrize("kind,n,a", [("bcc", 6, None), ("fcc", 5, None)])
+def test_virial_is_minus_the_strain_derivative_of_the_energy(opot, kind, n, a):
+    """The oracle's pair virial against finite differences of its energy
+    under a homogeneous strain of one axis (positions and box edge scaled by
+    1 + e): W_aa = -dU/de at e = 0, for displaced crystals, each axis."""
+    a = a or (I.A_BCC_STABLE if kind == "bcc" else I.A_FCC_VERBATIM)
+    x0 = I.lattice_sites(kind, n, a)
+    L = np.full(3, n * a)
+    rng = np.random.default_rng(2)
+    x = x0 + 0.08 * rng.standard_normal(x0.shape)
+    W = opot.pressure(x, L) * np.prod(L)   # no velocities: V P = W
+    eps = 1e-5
+    for c in range(3):
+        s = np.ones(3)
+        s[c] = 1 + eps
+        up = opot.eam(x * s, L * s)["U"]
+        s[c] = 1 - eps
+        dn = opot.eam(x * s, L * s)["U"]
+        assert W[c] == pytest.approx(-(up - dn) / (2 * eps), rel=1e-7, abs=1e-9)
+
+
+def test_kinetic_pressure_term(opot):
+    """The kinetic part of P_aa is sum m v_a^2 / V (metal units)."""
+    x0 = I.lattice_sites("bcc", 6, I.A_BCC_STABLE)
+    L = np.full(3, 6 * I.A_BCC_STABLE)
+    v = np.random.default_rng(3).standard_normal(x0.shape)
+    dP = opot.pressure(x0, L, v=v) - opot.pressure(x0, L)
+    assert np.allclose(dP, 55.845 * 1.0364269e-4 * (v ** 2).sum(0) / np.prod(L), rtol=1e-12)
