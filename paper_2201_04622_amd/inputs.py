@@ -133,6 +133,7 @@ class Replica:
     mass: float = MASS_FE
     k2: float = 0.0      # second spring constant (harmonic -> harmonic test mode only)
     cells: tuple = None  # (nx, ny, nz) conventional cells of an orthorhombic supercell; None: n per edge
+    vacuum: float = 0.0  # empty space added to the box along z (A): a slab with two free z faces
 
     @property
     def dims(self) -> tuple:
@@ -144,7 +145,9 @@ class Replica:
 
     @property
     def box(self) -> np.ndarray:
-        return np.asarray(self.dims, dtype=np.float64) * CELL[self.kind] * self.a
+        L = np.asarray(self.dims, dtype=np.float64) * CELL[self.kind] * self.a
+        L[2] += self.vacuum
+        return L
 
     def sites(self) -> np.ndarray:
         return lattice_sites(self.kind, self.dims, self.a)
