@@ -197,6 +197,42 @@ int eamfe_row_history(eamfe_ctx* ctx, double* mean_len, int64_t* passes, int res
  * a list or bin overflow enlarges the lists and evaluates again. */
 int eamfe_pressure(eamfe_ctx* ctx, const double* x_dev, const double* v_dev, double* P);
 
+/* Isotropic stochastic cell rescaling (Bernetti and Bussi, J. Chem. Phys.
+ * 153, 114107, 2020), one coupling move per call, made between
+ * fixed-volume runs of run_switching.  It holds the pressure the paper holds
+ * with a barostat: at zero in its reversible-scaling runs (Sec. p_rs) and
+ * while the lattice parameter of its Frenkel--Ladd runs is fixed (Sec. p_fl).
+ * At positions x_dev and velocities v_dev (device SoA [3][N_tot] FP64, both
+ * updated in place) each replica's internal pressure of H = w_eam U_EAM,
+ *   P = (sum_i m v_i^2 + w_eam W) / (3 V),  W the trace of the pair virial,
+ * moves eps = ln V by
+ *   d eps = -(beta_T / tau_p) (p0 - P - kB T / V) dt
+ *           + sqrt(2 kB T beta_T dt / (V tau_p)) z,
+ * T the replica's temperature and z the first Box--Muller deviate of Philox
+ * stream 3 under the replica's seed at counter (atom 0, step).  Positions and
+ * box edges are then scaled by mu = exp(d eps / 3) and velocities by 1 / mu.
+ * w_eam is the weight of U_EAM in the Hamiltonian at the step boundary
+ * `step`: lambda_step of the schedule in reversible scaling (where, with
+ * p0 = 0, this keeps the scaled system at the zero pressure of the real one
+ * at T0 / lambda), 1 for plain dynamics of U_EAM.  The spring anchors x0 are not moved, so the
+ * move suits runs without springs.  The lists are
+ * planned again for the new boxes by the next pass.  mu_host[n_rep] and
+ * P_host[n_rep] (host, may be NULL) return the factors and the pressures
+ * used.  EAMFE_EBOX leaves everything unchanged if a box edge would fall to
+ * 2 (r_cut + skin) or below.  Synchronises. */
+typedef struct eamfe_barostat {
+    double p0;       /* target pressure, eV/A^3 */
+    double tau_p;    /* coupling time, ps (> 0) */
+    double beta_T;   /* compressibility, A^3/eV: sets the relaxation rate, not the sampled distribution */
+    double dt;       /* time between moves (the coupling interval), ps */
+} eamfe_barostat;
+int eamfe_barostat_step(eamfe_ctx* ctx, const eamfe_barostat* b, int64_t step, double w_eam, double* x_dev,
+                        double* v_dev, double* mu_host, double* P_host);
+
+/* Current box edges, L_host[n_rep][3] (Angstrom): those of eamfe_system_setup
+ * until a barostat move changes them. */
+int eamfe_get_boxes(const eamfe_ctx* ctx, double* L_host);
+
 /* Per-atom spring constants for systems of several species (the paper's
  * remark on one spring constant per group of atoms, chosen from each
  * group's mean-squared displacement, Eq. msd): s_dev[N_tot] (device FP64,

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libeamfe.so")
-SOURCES = [os.path.join(HERE, "csrc", "eamfe_kernels.hip"), os.path.join(HERE, "csrc", "eamfe_host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("eamfe_kernels.hip", "eamfe_barostat.hip", "eamfe_host.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", "eamfe_internal.h"), os.path.join(ROOT, "include", "eamfe.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

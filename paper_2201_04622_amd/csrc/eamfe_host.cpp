@@ -1,7 +1,9 @@
 // Host side of the C ABI declared in include/eamfe.h: context and buffers,
-// spline tables, replica/tile layout, lambda schedules, the stepping loop and
-// the free-energy estimators.  All arithmetic of the MD path runs in the
-// kernels of eamfe_kernels.hip; this file only prepares tables and launches.
+// spline tables, replica/tile layout, lambda schedules, the stepping loop,
+// the free-energy estimators and the barostat's per-replica coupling move.
+// All per-atom arithmetic of the MD path runs in the kernels of
+// eamfe_kernels.hip (and the rescaling kernel of eamfe_barostat.hip); this
+// file only prepares tables, launches, and works on per-replica scalars.
 #include "../../include/eamfe.h"
 #include "eamfe_internal.h"
 
@@ -14,6 +16,12 @@
 #include <vector>
 
 using namespace eamfe;
+
+namespace eamfe {
+// eamfe_barostat.hip
+hipError_t launch_rescale(double* x, double* v, const int32_t* rep_of, const double* mu, int N, hipStream_t s);
+double barostat_gauss(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream);
+}  // namespace eamfe
 
 struct DevBuf {
     void* p = nullptr;
@@ -54,7 +62,7 @@ struct eamfe_ctx {
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d, kscale_d, vir_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d, kscale_d, vir_d, mu_d;
     bool has_kscale = false;   // per-atom spring scales set
 
     // neighbour lists
@@ -860,7 +868,7 @@ int eamfe_destroy(eamfe_ctx* c)
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
                       &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->kscale_d, &c->vir_d, &c->nbr_d,
+                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->kscale_d, &c->vir_d, &c->mu_d, &c->nbr_d,
                       &c->nnb_d, &c->cell_cnt_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
     for (DevBuf* b : bufs) release(*b);
     release(c->stats_d);
@@ -1569,6 +1577,71 @@ int eamfe_pressure(eamfe_ctx* c, const double* x, const double* v, double* P)
         }
     }
     return read_status(c);
+}
+
+int eamfe_barostat_step(eamfe_ctx* c, const eamfe_barostat* b, int64_t step, double w_eam, double* x, double* v,
+                        double* mu_out, double* P_out)
+{
+    if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!b || !x || !v) return fail(c, EAMFE_EINVAL, "barostat_step: null argument");
+    if (!(b->tau_p > 0.0) || !(b->beta_T >= 0.0) || !(b->dt >= 0.0) || !std::isfinite(b->p0) ||
+        !std::isfinite(w_eam))
+        return fail(c, EAMFE_EINVAL, "barostat_step: need tau_p > 0, beta_T >= 0, dt >= 0, finite p0 and w_eam");
+    (void)hipSetDevice(c->device);
+    // configurational pressure of U_EAM at x (virial only), then the kinetic
+    // part from the velocities: P = (sum m v^2 + w_eam W) / (3 V) is the
+    // internal pressure of H = w_eam U_EAM
+    std::vector<double> Pc((size_t)c->n_rep * 3);
+    OK(eamfe_pressure(c, x, nullptr, Pc.data()));
+    std::vector<double> vh((size_t)3 * c->N);
+    HIPCHK(c, hipMemcpy(vh.data(), v, vh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const double rl = c->r_cut + c->skin;
+    std::vector<double> mu(c->n_rep), Pint(c->n_rep);
+    for (int r = 0; r < c->n_rep; ++r) {
+        const RepDesc& R = c->reps[r];
+        const double V = R.L[0] * R.L[1] * R.L[2];
+        double mv2 = 0.0;
+        for (int i = R.off; i < R.off + R.n; ++i)
+            for (int d = 0; d < 3; ++d) mv2 += vh[(size_t)d * c->N + i] * vh[(size_t)d * c->N + i];
+        mv2 *= R.mass * mvv2e;
+        const double W = (Pc[3 * r] + Pc[3 * r + 1] + Pc[3 * r + 2]) * V;   // trace of the virial
+        const double P = (mv2 + w_eam * W) / (3.0 * V);
+        const double kT = kB * R.T;
+        const double z = barostat_gauss(R.seed, 0u, step, 3u);
+        const double deps = -(b->beta_T / b->tau_p) * (b->p0 - P - kT / V) * b->dt +
+                            std::sqrt(2.0 * kT * b->beta_T * b->dt / (V * b->tau_p)) * z;
+        mu[r] = std::exp(deps / 3.0);
+        Pint[r] = P;
+        for (int d = 0; d < 3; ++d)
+            if (!(R.L[d] * mu[r] > 2.0 * rl))
+                return fail(c, EAMFE_EBOX, "barostat_step: box edge of replica " + std::to_string(r) +
+                                               " would fall to 2 (r_cut + skin) or below");
+    }
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepDesc& R = c->reps[r];
+        for (int d = 0; d < 3; ++d) {
+            R.L[d] *= mu[r];
+            R.invL[d] = 1.0 / R.L[d];
+        }
+    }
+    OK(ensure(c, c->mu_d, (size_t)c->n_rep * sizeof(double)));
+    HIPCHK(c, hipMemcpy(c->mu_d.p, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
+    LCHK(c, launch_rescale(x, v, (const int32_t*)c->rep_of_d.p, (const double*)c->mu_d.p, c->N, c->stream));
+    OK(upload_reps(c));
+    drop_graphs(c);
+    c->have_list = false;   // cells and rows are planned again for the new boxes by the next pass
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (mu_out) std::copy(mu.begin(), mu.end(), mu_out);
+    if (P_out) std::copy(Pint.begin(), Pint.end(), P_out);
+    return EAMFE_OK;
+}
+
+int eamfe_get_boxes(const eamfe_ctx* c, double* L)
+{
+    if (!c || !L) return EAMFE_EINVAL;
+    for (int r = 0; r < c->n_rep; ++r)
+        for (int d = 0; d < 3; ++d) L[3 * r + d] = c->reps[r].L[d];
+    return EAMFE_OK;
 }
 
 int eamfe_set_spring_scale(eamfe_ctx* c, const double* s)

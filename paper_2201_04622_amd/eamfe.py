@@ -42,6 +42,10 @@ class Protocol(C.Structure):
                 ("dt", C.c_double), ("damp", C.c_double), ("lambda_f", C.c_double), ("skin", C.c_double)]
 
 
+class Barostat(C.Structure):
+    _fields_ = [("p0", C.c_double), ("tau_p", C.c_double), ("beta_T", C.c_double), ("dt", C.c_double)]
+
+
 _dp = C.POINTER(C.c_double)
 _lib = None
 
@@ -75,6 +79,8 @@ def lib():
         "eamfe_msd": (i32, [vp, vp, _dp]),
         "eamfe_set_spring_scale": (i32, [vp, vp]),
         "eamfe_pressure": (i32, [vp, vp, vp, _dp]),
+        "eamfe_barostat_step": (i32, [vp, C.POINTER(Barostat), i64, dbl, vp, vp, _dp, _dp]),
+        "eamfe_get_boxes": (i32, [vp, _dp]),
         "eamfe_copy_lists": (i32, [vp, vp, vp, i32]),
         "eam_setup": (i32, [vp, i32, dbl, _dp, _dp, i32, dbl, _dp]),
         "eamfe_system_setup": (i32, [vp, i32, C.POINTER(Replica), vp]),
@@ -286,6 +292,22 @@ class Context:
         out = np.zeros((self.n_rep, 3))
         self._c(self._lib.eamfe_pressure(self._h, _ptr(x), _ptr(v), out.ctypes.data_as(_dp)))
         return out
+
+    def barostat_step(self, b: Barostat, step, w_eam, x, v):
+        """One stochastic cell-rescaling move at the step boundary ``step``
+        (``w_eam``: weight of U_EAM in the Hamiltonian there): scales x,
+        v and the boxes in place; returns (mu[n_rep], P[n_rep] internal
+        pressures, eV/A^3)."""
+        mu, P = np.zeros(self.n_rep), np.zeros(self.n_rep)
+        self._c(self._lib.eamfe_barostat_step(self._h, C.byref(b), int(step), float(w_eam), _ptr(x), _ptr(v),
+                                              mu.ctypes.data_as(_dp), P.ctypes.data_as(_dp)))
+        return mu, P
+
+    def boxes(self):
+        """Current box edges [n_rep, 3] (A)."""
+        L = np.zeros((self.n_rep, 3))
+        self._c(self._lib.eamfe_get_boxes(self._h, L.ctypes.data_as(_dp)))
+        return L
 
     def set_spring_scale(self, s=None):
         """Per-atom spring scales s_i (device float64 [N_tot]; atom i's spring
