@@ -125,12 +125,13 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     kt = ctx.kernel_timing()
     ctx.check()
     mean_nl, passes = ctx.row_history()   # time average over the timed force passes
+    rebuilt_reps, rebuilt_atoms = ctx.list_rebuilds()
     end_nl, max_nl, cap = ctx.list_stats()
     launch = ctx.get_launch()
     ctx.close()
     return {
         "natoms": natoms, "n_rep": len(reps), "ms": ms, "wall_s": wall, "kt": kt, "mean_nl": mean_nl,
-        "passes": passes, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch, "tuned": tuned, "desc": wl.description,
+        "passes": passes, "rebuilt_reps": rebuilt_reps, "rebuilt_atoms": rebuilt_atoms, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch, "tuned": tuned, "desc": wl.description,
     }
 
 
@@ -241,6 +242,9 @@ def main():
             "final_neighbour_row": round(main_run["end_nl"], 2),
             "max_neighbour_row": main_run["max_nl"],
             "force_passes": main_run["passes"],
+            # list rebuilds of the timed passes: replica lists per step, atoms per step
+            "list_rebuilds_per_step": round(main_run["rebuilt_reps"] / args.steps, 3),
+            "atoms_rebuilt_per_step": round(main_run["rebuilt_atoms"] / args.steps, 1),
             "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
                        "autotuned": main_run["tuned"] is not None},
             "skin": args.skin,

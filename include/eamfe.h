@@ -186,6 +186,14 @@ int eamfe_list_stats(eamfe_ctx* ctx, double* mean_len, int* max_len, int* capaci
  * overflow is counted once. */
 int eamfe_row_history(eamfe_ctx* ctx, double* mean_len, int64_t* passes, int reset);
 
+/* Neighbour-list rebuilds of the step passes since the last reset of the
+ * row history: replica_rebuilds counts each replica whose lists a pass
+ * rebuilt (an atom had moved more than skin/2, or the run started), and
+ * atoms_rebuilt the atoms of those rebuilds.  Either pointer may be NULL.
+ * Synchronises; a range replayed after a row or bin overflow is counted
+ * once. */
+int eamfe_list_rebuilds(eamfe_ctx* ctx, int64_t* replica_rebuilds, int64_t* atoms_rebuilt);
+
 /* Diagonal of each replica's pressure tensor at positions x_dev (device SoA)
  * and velocities v_dev (device SoA, or NULL for the configurational part):
  * P_aa = (sum_i m v_ia^2 + W_aa) / V with the pair virial W_aa = sum_{i<j}

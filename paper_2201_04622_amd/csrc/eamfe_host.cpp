@@ -1056,7 +1056,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
     OK(ensure(c, c->flag_pre_d, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
     OK(ensure(c, c->pending_d, sizeof(int32_t)));
-    OK(ensure(c, c->row_acc_d, (size_t)(n_rep + 1) * sizeof(double)));
+    OK(ensure(c, c->row_acc_d, (size_t)(n_rep + 3) * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
@@ -1071,7 +1071,7 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->flag_pre_d.p, 0, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->pending_d.p, 0, sizeof(int32_t)));
-    HIPCHK(c, hipMemset(c->row_acc_d.p, 0, (size_t)(n_rep + 1) * sizeof(double)));
+    HIPCHK(c, hipMemset(c->row_acc_d.p, 0, (size_t)(n_rep + 3) * sizeof(double)));
     c->have_list = false;
     c->has_kscale = false;
     return build_tiles(c);
@@ -1212,7 +1212,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
         OK(ensure(c, c->snap_P, p4));
         OK(ensure(c, c->snap_v, v3));
         OK(ensure(c, c->snap_w, wb));
-        OK(ensure(c, c->snap_rows, wb + sizeof(double)));
+        OK(ensure(c, c->snap_rows, wb + 3 * sizeof(double)));
     }
     for (int64_t b = s0; b < s1; b += c->chunk) {
         const int64_t e = std::min(s1, b + c->chunk);
@@ -1221,7 +1221,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             HIPCHK(c, hipMemcpyAsync(c->snap_Q.p, Q_of(c, cur), q4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->snap_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->snap_w.p, c->W_state_d.p, wb, hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(c, hipMemcpyAsync(c->snap_rows.p, c->row_acc_d.p, wb + sizeof(double), hipMemcpyDeviceToDevice,
+            HIPCHK(c, hipMemcpyAsync(c->snap_rows.p, c->row_acc_d.p, wb + 3 * sizeof(double), hipMemcpyDeviceToDevice,
                                      c->stream));
         }
         for (int attempt = 0;; ++attempt) {
@@ -1255,7 +1255,7 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             HIPCHK(c, hipMemcpyAsync(Q_of(c, cur), c->snap_Q.p, q4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(v, c->snap_v.p, v3, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->W_state_d.p, c->snap_w.p, wb, hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(c, hipMemcpyAsync(c->row_acc_d.p, c->snap_rows.p, wb + sizeof(double), hipMemcpyDeviceToDevice,
+            HIPCHK(c, hipMemcpyAsync(c->row_acc_d.p, c->snap_rows.p, wb + 3 * sizeof(double), hipMemcpyDeviceToDevice,
                                      c->stream));
             ++c->replays;
         }
@@ -1526,7 +1526,20 @@ int eamfe_row_history(eamfe_ctx* c, double* mean_len, int64_t* passes, int reset
     const double n = h[c->n_rep];
     if (mean_len) *mean_len = n > 0.0 ? sum / (n * c->N) : 0.0;
     if (passes) *passes = (int64_t)n;
-    if (reset) HIPCHK(c, hipMemsetAsync(c->row_acc_d.p, 0, h.size() * sizeof(double), c->stream));
+    if (reset) HIPCHK(c, hipMemsetAsync(c->row_acc_d.p, 0, (h.size() + 2) * sizeof(double), c->stream));
+    return EAMFE_OK;
+}
+
+int eamfe_list_rebuilds(eamfe_ctx* c, int64_t* replica_rebuilds, int64_t* atoms_rebuilt)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    double h[2];
+    HIPCHK(c, hipMemcpyAsync(h, (const double*)c->row_acc_d.p + c->n_rep + 1, sizeof(h), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (replica_rebuilds) *replica_rebuilds = (int64_t)h[0];
+    if (atoms_rebuilt) *atoms_rebuilt = (int64_t)h[1];
     return EAMFE_OK;
 }
 

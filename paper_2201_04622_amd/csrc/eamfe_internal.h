@@ -115,7 +115,8 @@ struct StepArgs {
     int32_t* cell_cnt;      // [n_cells] bin counters (cleared by the density pass after a rebuild)
     int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix (formed by the list pass's first kernel)
     int32_t* pending;       // [1] 1 while a force pass of a step awaits its finish
-    double* row_acc;        // [n_rep + 1] row lengths summed over the step force passes, then their count
+    double* row_acc;        // [n_rep + 3] row lengths summed over the step force passes, their count, then
+                            // the replicas and the atoms whose lists those passes rebuilt
     int32_t* status;
     const double* lam;      // lambda table [S+1]
     int64_t* iter;          // device iteration counter (global step index)

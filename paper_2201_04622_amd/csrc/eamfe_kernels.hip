@@ -458,12 +458,13 @@ __device__ __forceinline__ double3 sep(const RepDesc& R, const double4& a, const
 // pre[r] (atoms of flagged replicas before r), pre[n_rep + 1 + r] (cells of
 // flagged replicas before r), totals at index n_rep and 2 n_rep + 1.  One
 // block (any size, multiple of 64); the list kernels take their work items
-// from these, so each of them needs no pass over all atoms or cells.
-__device__ void flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_rep, int32_t* pre)
+// from these, so each of them needs no pass over all atoms or cells.  Every
+// thread returns the number of flagged replicas.
+__device__ int flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_rep, int32_t* pre)
 {
-    __shared__ int wa[16], wc[16];
+    __shared__ int wa[16], wc[16], wr[16];
     const int lw = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int ca = 0, cc = 0;
+    int ca = 0, cc = 0, cr = 0;
     for (int base = 0; base < n_rep; base += blockDim.x) {
         const int r = base + threadIdx.x;
         int va = 0, vc = 0;
@@ -480,17 +481,20 @@ __device__ void flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_r
                 xc += yc;
             }
         }
+        const int nf = __popcll(__ballot(va > 0));   // flagged replicas of this wavefront
         if (lw == 63) {
             wa[w] = xa;
             wc[w] = xc;
+            wr[w] = nf;
         }
         __syncthreads();
-        int oa = 0, oc = 0, ta = 0, tc = 0;
+        int oa = 0, oc = 0, ta = 0, tc = 0, tr = 0;
         for (int q = 0; q < nw; ++q) {
             oa += q < w ? wa[q] : 0;
             oc += q < w ? wc[q] : 0;
             ta += wa[q];
             tc += wc[q];
+            tr += wr[q];
         }
         if (r < n_rep) {
             pre[r] = ca + oa + xa - va;
@@ -498,12 +502,14 @@ __device__ void flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_r
         }
         ca += ta;
         cc += tc;
+        cr += tr;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         pre[n_rep] = ca;
         pre[2 * n_rep + 1] = cc;
     }
+    return cr;
 }
 
 // Replica holding work item f of a prefix p[0..n_rep] (non-decreasing,
@@ -560,7 +566,11 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
         return;
     }
     if (blockIdx.x == 1) {
-        flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
+        const int flagged = flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
+        if (s.step_kernel && threadIdx.x == 0) {   // rebuild history of the step passes
+            s.row_acc[a.n_rep + 1] += (double)flagged;
+            s.row_acc[a.n_rep + 2] += (double)a.flag_pre[a.n_rep];
+        }
         return;
     }
     const int stride = (gridDim.x - 2) * blockDim.x;

@@ -76,6 +76,7 @@ def lib():
         "eamfe_kernel_timing": (i32, [vp, _dp, C.POINTER(i64)]),
         "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
         "eamfe_row_history": (i32, [vp, _dp, C.POINTER(i64), i32]),
+        "eamfe_list_rebuilds": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "eamfe_msd": (i32, [vp, vp, _dp]),
         "eamfe_set_spring_scale": (i32, [vp, vp]),
         "eamfe_pressure": (i32, [vp, vp, vp, _dp]),
@@ -326,6 +327,13 @@ class Context:
         m, n = C.c_double(), C.c_int64()
         self._c(self._lib.eamfe_row_history(self._h, C.byref(m), C.byref(n), int(bool(reset))))
         return m.value, n.value
+
+    def list_rebuilds(self):
+        """(replica list rebuilds, atoms rebuilt) of the step passes since the
+        last row-history reset."""
+        r, a = C.c_int64(), C.c_int64()
+        self._c(self._lib.eamfe_list_rebuilds(self._h, C.byref(r), C.byref(a)))
+        return r.value, a.value
 
     def list_stats(self):
         m, mx, cap = C.c_double(), C.c_int(), C.c_int()

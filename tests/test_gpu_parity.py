@@ -366,6 +366,34 @@ def test_row_history_weights_each_step_pass_by_its_rows():
     ctx.close()
 
 
+def test_list_rebuild_history_counts_the_rebuilding_passes():
+    """With no skin every atom leaves its list's reference position each
+    step.  A one-step call runs two force passes: the first at the positions
+    its predecessor's last pass listed (nothing to rebuild), the second after
+    the step (every replica rebuilt). K calls therefore rebuild K n_rep
+    replica lists holding K N atoms, and a reset of the row history clears
+    the count."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()
+    ctx, x0, arrs = make_ctx(reps, FP32, 2, 256)
+    p = E.protocol("fl", 20, 40, 0, 0, skin=0.0)
+    x = x0.clone()
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, True)
+    ctx.neigh_build(x, 0.0, 0)
+    ctx.row_history(reset=True)
+    assert ctx.list_rebuilds() == (0, 0)
+    K = 10
+    for s in range(K):
+        ctx.run_switching(p, x, v, s, s + 1)
+    assert ctx.list_rebuilds() == (K * len(reps), K * ctx.N)
+    ctx.row_history(reset=True)
+    assert ctx.list_rebuilds() == (0, 0)
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", [FP32, FP64])
 def test_graph_replay_matches_eager(prec):
     """Middle iterations replayed from a captured graph give bit-identical
