@@ -11,6 +11,8 @@
  *                        RS lambda(tau) = 1/(1 + tau (1/l_f - 1)) (Sec. RS in LAMMPS)
  *   estimators           Eq. W12, Eq. Ediss, Eq. fl (+ Eq. cm), Eq. rs, Eq. jarz
  *   spring constants     Eq. msd (mean-squared displacement), per-atom springs
+ *   constant pressure    pressure tensor; isotropic stochastic cell rescaling
+ *                        between fixed-volume stretches (RS at p = 0 gives G(T))
  *
  * Conventions for every entry point:
  *   - Units are LAMMPS "metal": eV, Angstrom, ps, amu, K.
