@@ -80,6 +80,32 @@ def measured_traffic(kernel, workload, prec, launch):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def measured_issue(kernel, workload, prec, launch):
+    """VALU issue and LDS bank-conflict shares of ``kernel``'s cycles over the
+    timed dispatches, from the committed SQ counter summary, or None when it
+    does not cover this kernel, workload, precision and launch, or the kernel
+    sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_force_k_density_{workload}_{prec}_issue_utilisation.txt")
+    if not os.path.exists(path) or launch != (2, 1024):
+        return None
+    kv, name, src = {}, None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = (t.strip() for t in line.split(":", 1))
+            if k == "kernel_source_sha256":
+                src = v
+            elif k == "kernel":
+                name = v
+            elif name and name.startswith(kernel + "<"):
+                kv[k] = v
+    if src != kernel_source_hash() or "valu_issue" not in kv:
+        return None
+    return {"valu_issue": float(kv["valu_issue"]), "lds_conflict": float(kv["lds_conflict"]),
+            "resident_waves_per_simd": float(kv["resident_waves_per_simd"])}
+
+
 def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None):
     import torch
 
@@ -208,6 +234,7 @@ def main():
     achieved = bytes_launch / (avg_ms / 1e3) / 1e9
     kname = "k_force" if dom == "force" else "k_density"
     traffic = measured_traffic(kname, args.workload, args.precision, main_run["launch"])
+    issue = measured_issue(kname, args.workload, args.precision, tuple(main_run["launch"]))
 
     plain = None
     if not args.no_fp64:
@@ -255,6 +282,8 @@ def main():
             "bound": "hbm", "kernel": kname,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "algorithmic_bytes": bytes_launch, "bytes_per_atom": bpa,
+            # the same kernel's VALU issue and LDS-conflict shares from SQ counters (what bounds it)
+            "issue": issue,
             "avg_launch_us": avg_ms * 1e3,
         },
         "fp64_plain_single_replica": plain,
