@@ -171,3 +171,31 @@ def test_rs_at_zero_pressure_matches_fl_at_the_zero_pressure_volume():
         f"+- {se_rs:.1e}, F_FL(600) {fl[Tf].mean():.6f} +- {se_fl:.1e} eV/atom, diff {d * 1e3:+.4f} meV/atom")
     assert a_hot == pytest.approx(a[Tf], rel=3e-4)
     assert abs(d) < 5e-4 and abs(d) < 3.0 * np.hypot(se_rs, se_fl) + 2e-5
+
+
+def test_barostat_rejects_bad_input_and_too_small_boxes():
+    """Non-positive tau_p is EINVAL; a move that would take a box edge to
+    2 (r_cut + skin) or below is EBOX and changes neither the boxes nor the
+    positions and velocities."""
+    import torch
+
+    import paper_2201_04622_amd.barostat as B
+    import paper_2201_04622_amd.eamfe as E
+    rep = I.Replica("bcc", 0, I.A_BCC_STABLE, 300.0, 0.0, 5, cells=(6, 6, 6))   # edge 11.79 A, 2 (r_c + skin) = 11.2
+    ctx, x0, _ = make_ctx([rep], FP64, 2, 256)
+    p = E.protocol("rs", 20, 1, 0, 0, lambda_f=1.0, skin=0.3)
+    x = x0.clone()
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, True)
+    ctx.run_switching(p, x, v, 0, 10)
+    with pytest.raises(E.EamfeError) as e:
+        ctx.barostat_step(B.barostat(0.0, 0.0, 0.3, 0.001, 10), 10, 1.0, x, v)
+    assert e.value.code == 1
+    xs, vs, L = x.clone(), v.clone(), ctx.boxes()
+    # p0 = 10 eV/A^3 (1.6 TPa) with a fast coupling: the box would shrink by several per cent
+    with pytest.raises(E.EamfeError) as e:
+        ctx.barostat_step(B.barostat(10.0, 0.1, 1.0, 0.001, 10), 10, 1.0, x, v)
+    assert e.value.code == 5
+    assert np.array_equal(ctx.boxes(), L)
+    assert torch.equal(x, xs) and torch.equal(v, vs)
+    ctx.close()
