@@ -354,6 +354,20 @@ int eamfe_replays(const eamfe_ctx* ctx, int64_t* n);
 /* Per-replica work after the last stepping call: host W_host[n_rep]. */
 int eamfe_get_work(eamfe_ctx* ctx, double* W_host);
 
+/* Checkpoint and resume.  Besides x, v and the step index (the caller's),
+ * the state a run carries from one step to the next is each replica's
+ * accumulated work and the positions at which the neighbour lists were last
+ * built (the noise is a function of seed and step only).  get_state copies
+ * the work to W_host[n_rep] (host), those positions to xref_dev (device SoA
+ * [3][N_tot] FP64; ESTATE if no lists were built yet) and the lists' skin to
+ * *skin; any pointer may be NULL.  set_state, on a context set up with the
+ * same potential, replicas and launch shape, loads the work and builds the
+ * lists at xref_dev with that skin.  run_switching from the saved step then
+ * continues bitwise as the uninterrupted run would (a range starting at step
+ * 0 clears the work instead).  Both synchronise. */
+int eamfe_get_state(eamfe_ctx* ctx, double* W_host, double* xref_dev, double* skin);
+int eamfe_set_state(eamfe_ctx* ctx, const double* W_host, const double* xref_dev, double skin);
+
 /* ---- differentiation --------------------------------------------------- */
 
 /* dU_EAM/dtheta at x, theta = the knot values (phi_k, rho_k, F_k) given to

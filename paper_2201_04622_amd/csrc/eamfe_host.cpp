@@ -1332,6 +1332,32 @@ int eamfe_get_work(eamfe_ctx* c, double* W)
     return EAMFE_OK;
 }
 
+int eamfe_get_state(eamfe_ctx* c, double* W, double* xref, double* skin)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (W) HIPCHK(c, hipMemcpy(W, c->W_state_d.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToHost));
+    if (xref) {
+        if (!c->have_list) return fail(c, EAMFE_ESTATE, "get_state: no neighbour lists have been built");
+        HIPCHK(c, hipMemcpy(xref, c->xref_d.p, (size_t)3 * c->N * sizeof(double), hipMemcpyDeviceToDevice));
+    }
+    if (skin) *skin = c->have_list ? c->skin : 0.0;
+    return EAMFE_OK;
+}
+
+int eamfe_set_state(eamfe_ctx* c, const double* W, const double* xref, double skin)
+{
+    if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (W) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(c->W_state_d.p, W, (size_t)c->n_rep * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (xref) OK(neigh_build(c, xref, skin, 0));   // the rows a build at those positions gives
+    return EAMFE_OK;
+}
+
 int eamfe_adjoint_theta(eamfe_ctx* c, const double* x, const double* w_host, int reduce, double* dtheta)
 {
     if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;

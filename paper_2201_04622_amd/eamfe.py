@@ -92,6 +92,8 @@ def lib():
         "run_switching": (i32, [vp, C.POINTER(Protocol), i64, i64, vp, vp, vp, vp, vp, i32]),
         "switch_step": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, vp, vp]),
         "eamfe_get_work": (i32, [vp, _dp]),
+        "eamfe_get_state": (i32, [vp, _dp, vp, _dp]),
+        "eamfe_set_state": (i32, [vp, _dp, vp, dbl]),
         "eamfe_set_chunk": (i32, [vp, i64]),
         "eamfe_replays": (i32, [vp, C.POINTER(i64)]),
         "eamfe_adjoint_theta": (i32, [vp, vp, _dp, i32, vp]),
@@ -395,6 +397,20 @@ class Context:
         W = np.zeros(self.n_rep)
         self._c(self._lib.eamfe_get_work(self._h, W.ctypes.data_as(_dp)))
         return W
+
+    def get_state(self):
+        """(work [n_rep], list reference positions (device [3, N_tot]), skin):
+        with x, v and the step index, what a resumed run needs."""
+        import torch
+        W, skin = np.zeros(self.n_rep), C.c_double()
+        xref = torch.zeros(3, self.N, dtype=torch.float64, device="cuda")
+        self._c(self._lib.eamfe_get_state(self._h, W.ctypes.data_as(_dp), _ptr(xref), C.byref(skin)))
+        return W, xref, skin.value
+
+    def set_state(self, W, xref, skin):
+        """Load a saved work vector and build the lists at the saved reference positions."""
+        Wc = np.ascontiguousarray(W, dtype=np.float64)
+        self._c(self._lib.eamfe_set_state(self._h, Wc.ctypes.data_as(_dp), _ptr(xref), float(skin)))
 
     def adjoint_theta(self, x, dtheta, weights=None, reduce=False):
         """dtheta (device float64, [n_rep, 3, n] or [3, n] with reduce) += w_r dU_r/dtheta."""

@@ -366,6 +366,50 @@ def test_row_history_weights_each_step_pass_by_its_rows():
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_resume_in_a_new_context_is_bitwise_the_straight_run(prec):
+    """A run stopped at step 67, its state saved (x, v, work, list reference
+    positions) and the context destroyed, then resumed in a new context,
+    gives the positions, velocities and traces of the uninterrupted run bit
+    for bit (a small skin makes the lists rebuild on both sides of the
+    split)."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    reps = _mixed_batch()[:4]
+    skin, S, mid = 0.2, 150, 67
+    p = E.protocol("fl", 10, 60, 10, 10, skin=skin)
+
+    def start():
+        ctx, x0, _ = make_ctx(reps, prec, 2, 256)
+        x = x0.clone()
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        ctx.neigh_build(x, skin, 0)
+        return ctx, x, v
+
+    ctx, x, v = start()
+    dH = torch.zeros(len(reps), S, dtype=torch.float64, device="cuda")
+    W = torch.zeros_like(dH)
+    ctx.run_switching(p, x, v, 0, S, None, dH, W)
+    ctx.close()
+
+    ctx, xs, vs = start()
+    dH1, W1 = torch.zeros_like(dH), torch.zeros_like(dH)
+    ctx.run_switching(p, xs, vs, 0, mid, None, dH1, W1)
+    Wm, xref, sk = ctx.get_state()
+    assert sk == skin and np.array_equal(Wm, W1[:, mid - 1].cpu().numpy())
+    xs, vs, xref = xs.clone(), vs.clone(), xref.clone()
+    ctx.close()
+    ctx, _, _ = make_ctx(reps, prec, 2, 256)
+    ctx.set_state(Wm, xref, sk)
+    ctx.run_switching(p, xs, vs, mid, S, None, dH1, W1)
+    assert ctx.list_stats()[0] > 0
+    ctx.close()
+    assert torch.equal(xs, x) and torch.equal(vs, v)
+    assert torch.equal(dH1, dH) and torch.equal(W1, W)
+
+
 def test_list_rebuild_history_counts_the_rebuilding_passes():
     """With no skin every atom leaves its list's reference position each
     step.  A one-step call runs two force passes: the first at the positions
