@@ -126,6 +126,50 @@ def test_neighbor_overflow_reported():
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_density_beyond_the_table_reported(opot, prec):
+    """A table that ends at rho_max = 5 (the stable crystal's densities are
+    near 85): the force evaluation reports ETABLE_RANGE, as the oracle flags
+    the same configuration."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    from oracle import oracle as O
+    knots = I.synthetic_eam_knots(rho_max=5.0)
+    rep = I.Replica("bcc", 6, I.A_BCC_STABLE, 300.0, 5.0, 9)
+    ctx, x0, _ = make_ctx([rep], prec, knots=knots)
+    ctx.neigh_build(x0, 0.3, 0)
+    f = torch.zeros_like(x0)
+    U = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(E.EamfeError) as e:
+        ctx.eam_forces(x0, f, U)
+    assert e.value.code == 8
+    ctx.close()
+    assert O.Potential.from_knots(knots).eam(rep.sites(), rep.box)["status"] & O.ETABLE
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_non_finite_position_reported(prec):
+    """A NaN coordinate: the lists and the pair passes stay in bounds (box
+    codes and cells are bounded for any input), and the evaluation reports
+    ENONFINITE."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    rep = I.Replica("bcc", 6, I.A_BCC_STABLE, 300.0, 5.0, 9)
+    ctx, x0, _ = make_ctx([rep], prec)
+    x = rep.sites()
+    x[17, 1] = np.nan
+    xd = E.to_soa(x)
+    ctx.neigh_build(xd, 0.3, 0)
+    f = torch.zeros_like(xd)
+    U = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(E.EamfeError) as e:
+        ctx.eam_forces(xd, f, U)
+    assert e.value.code == 9
+    ctx.close()
+
+
 def test_small_box_rejected():
     import paper_2201_04622_amd.eamfe as E
     reps = [I.Replica("bcc", 3, I.A_BCC_VERBATIM, 300.0, 5.0, 9)]   # L = 8.57 < 2 (5.3 + 0.3)
