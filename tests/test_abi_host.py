@@ -157,3 +157,9 @@ def test_switch_works_take_the_two_legs():
     assert np.allclose(Wf0, W0[:, 10], atol=0) and np.allclose(Wb0, W0[:, 26] - W0[:, 15], atol=0)
     with pytest.raises(E.EamfeError):
         E.switch_works(p, W[:, : S - 4])   # the backward leg ends at step 33
+
+
+def test_runner_rejects_unknown_workloads():
+    from paper_2201_04622_amd import run as R
+    with pytest.raises(ValueError):
+        R.run_workload("no_such_workload")
