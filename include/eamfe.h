@@ -439,6 +439,19 @@ int eamfe_switch_works(const eamfe_protocol* p, int n_rep, const double* W_trace
 int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W_trace, double F0_T0, double T0,
                          double n_eff, int n_T, const double* T_grid, double* F_out);
 
+/* Eq. rs for a run with a fixed centre of mass (fix_com), the form to use
+ * with an F0(T0) from eamfe_fl_free_energy that includes Eq. cm.  Such a run
+ * samples the crystal with its centre of mass fixed, and Eq. rs maps that
+ * system's free energy from T0 to T exactly; Eq. cm is the step from it to the
+ * free crystal at each temperature.  So
+ *   F(T) = rs(F0(T0) - cm(T0)) + cm(T),  cm(T) = eamfe_fixed_cm_correction(N, V, T, k),
+ * with rs the map of eamfe_rs_free_energy, N atoms, V the box volume and k
+ * the spring constant F0(T0) was found with.  Scaling cm(T0) by 1/l instead
+ * would be off by (3/2) kB T ln(T/T0) per system. */
+int eamfe_rs_free_energy_cm(const eamfe_protocol* p, const double* W_trace, double F0_T0, double T0,
+                            double n_eff, double N, double V, double k, int n_T, const double* T_grid,
+                            double* F_out);
+
 #ifdef __cplusplus
 }
 #endif

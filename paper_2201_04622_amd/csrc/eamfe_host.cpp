@@ -1834,4 +1834,15 @@ int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W, double F0_T0,
     return EAMFE_OK;
 }
 
+int eamfe_rs_free_energy_cm(const eamfe_protocol* p, const double* W, double F0_T0, double T0, double n_eff,
+                            double N, double V, double k, int n_T, const double* T_grid, double* F_out)
+{
+    if (!(N > 0.0) || !(V > 0.0) || !(k > 0.0)) return EAMFE_EINVAL;
+    const int st = eamfe_rs_free_energy(p, W, F0_T0 - eamfe_fixed_cm_correction(N, V, T0, k), T0, n_eff, n_T,
+                                        T_grid, F_out);
+    if (st != EAMFE_OK) return st;
+    for (int q = 0; q < n_T; ++q) F_out[q] += eamfe_fixed_cm_correction(N, V, T_grid[q], k);
+    return EAMFE_OK;
+}
+
 }  // extern "C"

@@ -103,6 +103,7 @@ def lib():
         "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fl_free_energy": (i32, [i32, _dp, _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp, _dp]),
         "eamfe_rs_free_energy": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, i32, _dp, _dp]),
+        "eamfe_rs_free_energy_cm": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp]),
         "eamfe_jarzynski": (i32, [i32, _dp, dbl, _dp, _dp]),
         "eamfe_switch_works": (i32, [C.POINTER(Protocol), i32, _dp, i64, _dp, _dp]),
     }
@@ -169,6 +170,17 @@ def switch_works(p: Protocol, W_trace):
     _chk(None, lib().eamfe_switch_works(C.byref(p), W.shape[0], W.ctypes.data_as(_dp), W.shape[1],
                                         Wf.ctypes.data_as(_dp), Wb.ctypes.data_as(_dp)))
     return Wf, Wb
+
+
+def rs_free_energy_cm(p: Protocol, W_trace, F0_T0, T0, n_eff, N, V, k, T_grid):
+    """Eq. rs for a fixed-centre-of-mass run from an F0(T0) that includes Eq. cm."""
+    W = np.ascontiguousarray(W_trace, dtype=np.float64)
+    Tg = np.ascontiguousarray(T_grid, dtype=np.float64)
+    out = np.zeros_like(Tg)
+    _chk(None, lib().eamfe_rs_free_energy_cm(C.byref(p), W.ctypes.data_as(_dp), float(F0_T0), float(T0),
+                                             float(n_eff), float(N), float(V), float(k), len(Tg),
+                                             Tg.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+    return out
 
 
 def rs_free_energy(p: Protocol, W_trace, F0_T0, T0, n_eff, T_grid):

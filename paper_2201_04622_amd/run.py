@@ -144,7 +144,12 @@ def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2
         n_eff = N - 1 if sch.fix_com else N
         Tf = T0 / sch.lambda_f
         grid = np.arange(T0, Tf + 0.5, 1.0)
-        F = np.array([E.rs_free_energy(p, W[q], F0_T0, T0, n_eff, grid) for q in range(len(reps))]) / N
+        if sch.fix_com:   # F0(T0) includes Eq. cm, the run keeps the centre of mass fixed
+            V = float(np.prod(reps[0].box))
+            F = np.array([E.rs_free_energy_cm(p, W[q], F0_T0, T0, n_eff, N, V, reps[0].k, grid)
+                          for q in range(len(reps))]) / N
+        else:
+            F = np.array([E.rs_free_energy(p, W[q], F0_T0, T0, n_eff, grid) for q in range(len(reps))]) / N
         rec["run"] = stats
         rec["companion_fl"] = {"run": fstats, "system": fl_sys[0]}
         rec["T_grid"] = grid.tolist()

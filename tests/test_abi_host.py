@@ -100,6 +100,30 @@ def test_rs_estimator_matches_oracle():
     assert np.abs(got - ref).max() < 1e-10
 
 
+def test_rs_with_fixed_centre_of_mass_is_exact_for_the_einstein_crystal():
+    """Scaling an Einstein crystal (fixed centre of mass, 3 (N - 1) modes) by
+    lambda at T0 costs the reversible work (3 (N - 1) / 2) kB T0 ln(lambda).
+    Fed that work, the fixed-CM form of Eq. rs turns F0(T0) (Eq. einstein plus
+    Eq. cm) into the same closed form at every T of the scan. The plain form,
+    which scales cm(T0) by 1/lambda, misses by (3/2) kB T ln(T/T0)."""
+    KB = 8.617333262e-5
+    N, k, m, T0, lf = 432, 20.0, 55.845, 300.0, 0.25
+    V = 432 * 7.58
+    n_eq, n_sw, n_hold = 10, 2000, 10
+    p = E.protocol("rs", n_eq=n_eq, n_sw=n_sw, n_hold=n_hold, n_hold2=0, lambda_f=lf)
+    lam = E.lambda_schedule(p)
+    w_rev = 1.5 * (N - 1) * KB * T0 * np.log(lam)           # reversible work from lambda = 1
+    W = w_rev[1:]                                             # cumulative work after each step
+    F0 = E.einstein_free_energy(N - 1, T0, k, m) + E.fixed_cm_correction(N, V, T0, k)
+    # temperatures on whole steps of the scan, where the work needs no interpolation
+    T = T0 + (T0 / lf - T0) * np.array([0, 333, 1000, 1666, n_sw]) / n_sw
+    got = E.rs_free_energy_cm(p, W, F0, T0, N - 1, N, V, k, T)
+    want = np.array([E.einstein_free_energy(N - 1, t, k, m) + E.fixed_cm_correction(N, V, t, k) for t in T])
+    assert np.abs(got - want).max() < 1e-9 * np.abs(want).max()
+    plain = E.rs_free_energy(p, W, F0, T0, N - 1, T)
+    assert np.allclose(plain - got, -1.5 * KB * T * np.log(T / T0), rtol=1e-9, atol=1e-12)
+
+
 def test_jarzynski_matches_oracle_and_its_invariants():
     """Eq. jarz in the library against the oracle's estimator, and properties
     that fix it independently: a constant work gives that work, a shift of

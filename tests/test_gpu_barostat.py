@@ -161,7 +161,11 @@ def test_rs_at_zero_pressure_matches_fl_at_the_zero_pressure_volume():
     ctx.close()
     W = W.cpu().numpy()
     F0 = fl[T0].mean() * N
-    G = np.array([E.rs_free_energy(p, W[r], F0, T0, N - 1, np.array([Tf]))[0] for r in range(len(reps))]) / N
+    # Eq. rs in its fixed-centre-of-mass form; the volume in Eq. cm is the one at T0 (at 600 K the box is
+    # 0.3 % larger, which moves Eq. cm by 1e-6 eV/atom)
+    V0 = float(np.prod(reps[0].box))
+    G = np.array([E.rs_free_energy_cm(p, W[r], F0, T0, N - 1, N, V0, k, np.array([Tf]))[0]
+                  for r in range(len(reps))]) / N
     a_hot = tr.boxes[n_eq // 10 + n_sw // 10: n_eq // 10 + n_sw // 10 + n_hold // 10, :, 0].mean() / cells[0]
     # the RS estimate inherits F0(T0) / lambda: its error doubles at lambda = 1/2
     se_rs = np.hypot(G.std(ddof=1) / np.sqrt(len(G)), 2.0 * fl[T0].std(ddof=1) / np.sqrt(len(fl[T0])))
