@@ -101,9 +101,33 @@ def fl_results(reps, p, W):
     return out, diffs
 
 
-def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2000, 20000, 2000)):
-    import torch
+def msd_springs(reps, precision, skin, n_steps=4000, every=100, discard=1000):
+    """The replicas with each system's spring constant replaced by k = 3 kB T
+    / msd (Eq. msd), the mean over the system's realizations of an
+    equilibrium run of H0 (springs.spring_constants)."""
+    import dataclasses
 
+    from . import springs as SP
+    ctx, x, v = _context(reps, precision, skin)
+    ctx.init_velocities(v, True)
+    ctx.neigh_build(x, skin, 0)
+    k, _, _ = SP.spring_constants(ctx, reps, x, v, n_steps, every, skin=skin, discard=discard)
+    ctx.close()
+    groups = OrderedDict()
+    for q, r in enumerate(reps):
+        groups.setdefault(_system_key(r), []).append(q)
+    out = list(reps)
+    for rows in groups.values():
+        km = float(np.mean(k[rows]))
+        for q in rows:
+            out[q] = dataclasses.replace(reps[q], k=km)
+    return out
+
+
+def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2000, 20000, 2000), k_msd=False):
+    """``k_msd``: replace the workload's spring constants by the ones the
+    mean-squared displacement gives (for the FL runs, including the RS
+    scan's companion)."""
     wl = I.workload(name, stable=stable)
     reps, sch = wl.replicas, wl.schedule
     p = E.protocol_from_schedule(sch, skin=skin)
@@ -112,6 +136,8 @@ def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2
            "replicas": len(reps), "atoms": int(sum(r.natoms for r in reps)), "steps": S, "skin": skin,
            "data": "synthetic"}
     if sch.mode == "fl":
+        if k_msd:
+            reps = msd_springs(reps, precision, skin)
         ctx, x, v = _context(reps, precision, skin)
         ctx.init_velocities(v, sch.fix_com)
         ctx.neigh_build(x, skin, 0)
@@ -126,16 +152,17 @@ def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2
         n_eq, n_sw, n_hold = fl_companion
         pf = E.protocol("fl", n_eq, n_sw, n_hold, 0, function=2, dt=sch.dt, damp=sch.damp, fix_com=sch.fix_com,
                         skin=skin)
-        ctx, x, v = _context(reps, precision, skin)
+        creps = msd_springs(reps, precision, skin) if k_msd else reps   # the companion FL's replicas
+        ctx, x, v = _context(creps, precision, skin)
         ctx.init_velocities(v, sch.fix_com)
         ctx.neigh_build(x, skin, 0)
         Wfl, fstats = _run(ctx, pf, x, v, n_eq + 2 * n_sw + n_hold)
-        fl_sys, _ = fl_results(reps, pf, Wfl)
+        ctx.close()
+        fl_sys, _ = fl_results(creps, pf, Wfl)
         F0_T0 = fl_sys[0]["F0_per_atom"] * reps[0].natoms if len(fl_sys) == 1 else None
         if F0_T0 is None:
             raise ValueError("run: the replicas of an RS scan must be realizations of one system")
-        x = E.to_soa(I.batch_arrays(reps)["x0"])
-        v = torch.zeros_like(x)
+        ctx, x, v = _context(reps, precision, skin)
         ctx.init_velocities(v, sch.fix_com)
         ctx.neigh_build(x, skin, 0)
         W, stats = _run(ctx, p, x, v, S)
@@ -146,7 +173,7 @@ def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2
         grid = np.arange(T0, Tf + 0.5, 1.0)
         if sch.fix_com:   # F0(T0) includes Eq. cm, the run keeps the centre of mass fixed
             V = float(np.prod(reps[0].box))
-            F = np.array([E.rs_free_energy_cm(p, W[q], F0_T0, T0, n_eff, N, V, reps[0].k, grid)
+            F = np.array([E.rs_free_energy_cm(p, W[q], F0_T0, T0, n_eff, N, V, creps[0].k, grid)
                           for q in range(len(reps))]) / N
         else:
             F = np.array([E.rs_free_energy(p, W[q], F0_T0, T0, n_eff, grid) for q in range(len(reps))]) / N
@@ -166,9 +193,11 @@ def main(argv=None):
     ap.add_argument("--stable", action="store_true", help="the potential's own zero-pressure lattice constants")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--k-msd", action="store_true", help="spring constants from the mean-squared displacement")
     ap.add_argument("--out", default=None, help="JSON file (default: stdout)")
     args = ap.parse_args(argv)
-    rec = run_workload(args.workload, args.stable, E.FP32 if args.precision == "fp32" else E.FP64, args.skin)
+    rec = run_workload(args.workload, args.stable, E.FP32 if args.precision == "fp32" else E.FP64, args.skin,
+                       k_msd=args.k_msd)
     text = json.dumps(rec)
     if args.out:
         with open(args.out, "w") as fh:
