@@ -193,13 +193,14 @@ def _batch_shapes(a_bcc: float, a_fcc: float):
 
 
 def workload(name: str, stable: bool = False) -> Workload:
-    """The five workloads, by name:
+    """The workloads, by name:
 
     fl_bcc4   FL in FP64, one bcc 4^3 replica (128 atoms), T=100 K, k=5
     fl_mid    FL, one bcc 10^3 (2000) and one fcc 8^3 (2048) replica, T=1400 K, k=3
     batch64   64 FL replicas of uneven size (bcc 6..12^3, fcc 5..10^3; 113,090
               atoms), T = 100 (1 + r mod 16) K, k=5, seeds 0..63
     rs_scan   RS scan 100 -> 1600 K, 8 bcc 20^3 replicas (128,000 atoms)
+    rs_small  RS scan 300 -> 600 K, 4 bcc 6^3 replicas (1,728 atoms), k=20
     fl_large  FL, 16 bcc 30^3 + 16 fcc 24^3 replicas (1,748,736 atoms), T=1200 K
 
     ``stable`` swaps in the synthetic
@@ -228,6 +229,11 @@ def workload(name: str, stable: bool = False) -> Workload:
         reps = [Replica("bcc", 20, ab, 100.0, 5.0, s) for s in range(8)]
         sch = Schedule("rs", 10000, 100000, 10000, 0, lambda_f=100.0 / 1600.0)
         desc = "RS scan 100->1600 K, 8 x bcc 20^3"
+    elif name == "rs_small":
+        n = 6 if stable else 4
+        reps = [Replica("bcc", n, ab, 300.0, 20.0, s) for s in range(4)]
+        sch = Schedule("rs", 1000, 8000, 1000, 0, lambda_f=0.5)
+        desc = f"RS scan 300->600 K, 4 x bcc {n}^3"
     elif name == "fl_large":
         reps = [Replica("bcc", 30, ab, 1200.0, 5.0, s) for s in range(16)]
         reps += [Replica("fcc", 24, af, 1200.0, 5.0, s) for s in range(16)]

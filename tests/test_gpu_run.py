@@ -47,3 +47,48 @@ def test_runner_record_matches_the_direct_estimate(tmp_path):
     assert rec["run"]["atom_steps_per_s"] > 0 and rec["run"]["mean_neighbour_row"] > 0
     assert S < rec["run"]["force_passes"] <= S + S // 1000 + 1   # one pass per step plus one per chunk
     assert rec["dF_bcc_to_fcc"] == []
+
+
+def test_runner_rs_scan_matches_the_direct_estimate():
+    """rs_small (stable: 4 x bcc 6^3, 300 -> 600 K) through the runner: its
+    companion FL and its F(T) curve (fixed-centre-of-mass Eq. rs) equal the
+    same estimators applied by hand to runs with the same seeds."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    from paper_2201_04622_amd import run as R
+    rec = R.run_workload("rs_small", stable=True, precision=E.FP32, fl_companion=(500, 2000, 500))
+    wl = I.workload("rs_small", stable=True)
+    reps, sch = wl.replicas, wl.schedule
+    N = reps[0].natoms
+
+    def batch():
+        ctx = E.Context(0, E.FP32)
+        ctx.eam_setup(I.synthetic_eam_knots())
+        x = E.to_soa(I.batch_arrays(reps)["x0"])
+        ctx.system_setup(reps, x)
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        ctx.neigh_build(x, 0.3, 0)
+        return ctx, x, v
+
+    ctx, x, v = batch()
+    pf = E.protocol("fl", 500, 2000, 500, 0, function=2, skin=0.3)
+    Wfl = torch.zeros(len(reps), 5000, dtype=torch.float64, device="cuda")
+    ctx.run_switching(pf, x, v, 0, 5000, W_out=Wfl)
+    ctx.close()
+    Wf, Wb = E.switch_works(pf, Wfl.cpu().numpy())
+    V = float(np.prod(reps[0].box))
+    F0, _, _ = E.fl_free_energy(Wf, Wb, N - 1, reps[0].T, reps[0].k, reps[0].mass, N=N, V=V)
+    assert rec["companion_fl"]["system"]["F0_per_atom"] == F0 / N
+    ctx, x, v = batch()
+    p = E.protocol_from_schedule(sch, skin=0.3)
+    W = torch.zeros(len(reps), sch.total_steps, dtype=torch.float64, device="cuda")
+    ctx.run_switching(p, x, v, 0, sch.total_steps, W_out=W)
+    ctx.close()
+    grid = np.array(rec["T_grid"])
+    F = np.array([E.rs_free_energy_cm(p, W[q].cpu().numpy(), F0, 300.0, N - 1, N, V, reps[0].k, grid)
+                  for q in range(len(reps))]) / N
+    say(f"runner F(600 K) {rec['F_per_atom'][-1]:.6f} eV/atom, direct {F.mean(axis=0)[-1]:.6f}")
+    assert grid[0] == 300.0 and grid[-1] == 600.0 and len(grid) == 301
+    assert np.array_equal(np.array(rec["F_per_atom"]), F.mean(axis=0))
