@@ -134,6 +134,7 @@ class Replica:
     k2: float = 0.0      # second spring constant (harmonic -> harmonic test mode only)
     cells: tuple = None  # (nx, ny, nz) conventional cells of an orthorhombic supercell; None: n per edge
     vacuum: float = 0.0  # empty space added to the box along z (A): a slab with two free z faces
+    vacancies: tuple = ()  # site ids (of the full supercell) left empty: point defects
 
     @property
     def dims(self) -> tuple:
@@ -141,7 +142,7 @@ class Replica:
 
     @property
     def natoms(self) -> int:
-        return len(BASIS[self.kind]) * int(np.prod(self.dims))
+        return len(BASIS[self.kind]) * int(np.prod(self.dims)) - len(set(self.vacancies))
 
     @property
     def box(self) -> np.ndarray:
@@ -150,7 +151,12 @@ class Replica:
         return L
 
     def sites(self) -> np.ndarray:
-        return lattice_sites(self.kind, self.dims, self.a)
+        x = lattice_sites(self.kind, self.dims, self.a)
+        if self.vacancies:
+            keep = np.ones(len(x), dtype=bool)
+            keep[list(set(self.vacancies))] = False
+            x = np.ascontiguousarray(x[keep])
+        return x
 
 
 @dataclass(frozen=True)
