@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import eamfe as E
+from . import fl as FL
 
 
 def with_vacancy(replica, site=0):
@@ -49,8 +49,6 @@ def vacancy_formation_free_energy(ctx, replicas, x0, n_perfect, t_s, n_eq, n_hol
     first ``n_perfect`` realizations of the perfect crystal, then
     realizations of the same crystal with one vacancy (the same site in
     each), and ``x0`` holds their lattice sites (device SoA)."""
-    import torch
-
     perfect, vac = list(replicas[:n_perfect]), list(replicas[n_perfect:])
     if not perfect or not vac:
         raise ValueError("vacancy_formation_free_energy: need realizations of both crystals")
@@ -60,25 +58,10 @@ def vacancy_formation_free_energy(ctx, replicas, x0, n_perfect, t_s, n_eq, n_hol
     if any(_key(r) != _key(p0) or r.vacancies != v0.vacancies for r in vac) or len(set(v0.vacancies)) != 1:
         raise ValueError("vacancy_formation_free_energy: the defect replicas must be the crystal with one vacancy")
 
-    p = E.protocol("fl", n_eq, int(t_s), n_hold, 0, function=function, dt=dt, damp=damp, skin=skin)
-    S = n_eq + 2 * int(t_s) + n_hold
-    x = x0.clone()
-    v = torch.zeros_like(x)
-    ctx.init_velocities(v, bool(p.fix_com))
-    ctx.neigh_build(x, skin, 0)
-    W = torch.zeros(len(replicas), S, dtype=torch.float64, device=x.device)
-    ctx.run_switching(p, x, v, 0, S, W_out=W)
-    Wf, Wb = E.switch_works(p, W.cpu().numpy())
-    V = float(np.prod(p0.box))
-
-    def f0(rows, rep):
-        N = rep.natoms
-        n_eff = N - 1 if p.fix_com else N
-        return E.fl_free_energy(Wf[rows], Wb[rows], n_eff, rep.T, rep.k, rep.mass, N if p.fix_com else None,
-                                V if p.fix_com else None)
-
-    Fp, Edp, ep = f0(slice(0, n_perfect), p0)
-    Fv, Edv, ev = f0(slice(n_perfect, len(replicas)), v0)
+    p, Wf, Wb = FL.run(ctx, x0, t_s, n_eq, n_hold, dt=dt, damp=damp, skin=skin, function=function)
+    V = float(np.prod(p0.box))   # both systems in the perfect crystal's box
+    Fp, Edp, ep = FL.system_free_energy(p, Wf[:n_perfect], Wb[:n_perfect], p0, V)
+    Fv, Edv, ev = FL.system_free_energy(p, Wf[n_perfect:], Wb[n_perfect:], v0, V)
     N = p0.natoms
     G = Fv - (N - 1) / N * Fp
     return VacancyFormation(G, float(np.hypot(ev, (N - 1) / N * ep)), Fp, ep, Fv, ev, Edp, Edv)

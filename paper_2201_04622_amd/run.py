@@ -29,6 +29,7 @@ from collections import OrderedDict
 import numpy as np
 
 from . import eamfe as E
+from . import fl as FL
 from . import inputs as I
 
 
@@ -78,8 +79,7 @@ def fl_results(reps, p, W):
         N = r0.natoms
         n_eff = N - 1 if p.fix_com else N
         V = float(np.prod(r0.box))
-        F0, Ed, err = E.fl_free_energy(Wf[rows], Wb[rows], n_eff, r0.T, r0.k, r0.mass, N if p.fix_com else None,
-                                       V if p.fix_com else None)
+        F0, Ed, err = FL.system_free_energy(p, Wf[rows], Wb[rows], r0, V)
         FE = E.einstein_free_energy(n_eff, r0.T, r0.k, r0.mass)
         cm = E.fixed_cm_correction(N, V, r0.T, r0.k) if p.fix_com else 0.0
         jf, jfe = E.jarzynski(Wf[rows], r0.T)

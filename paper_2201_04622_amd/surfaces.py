@@ -27,7 +27,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import eamfe as E
+from . import fl as FL
 
 
 def slab(replica, vacuum: float):
@@ -69,8 +69,6 @@ def surface_free_energy(ctx, replicas, x0, n_bulk, t_s, n_eq, n_hold, dt=0.001, 
     T, k and mass, one positive vacuum), and ``x0`` holds their lattice sites
     (device SoA).  Each system's F0 is the FL estimate over its realizations;
     gamma_err combines the two standard errors."""
-    import torch
-
     bulk, slabs = list(replicas[:n_bulk]), list(replicas[n_bulk:])
     if not bulk or not slabs:
         raise ValueError("surface_free_energy: need realizations of both the bulk and the slab")
@@ -80,25 +78,8 @@ def surface_free_energy(ctx, replicas, x0, n_bulk, t_s, n_eq, n_hold, dt=0.001, 
     if any(_system_key(r) != _system_key(b0) or r.vacuum != s0.vacuum for r in slabs) or not s0.vacuum > 0.0:
         raise ValueError("surface_free_energy: the slab replicas must be the bulk crystal with one positive vacuum")
 
-    p = E.protocol("fl", n_eq, int(t_s), n_hold, 0, function=function, dt=dt, damp=damp, skin=skin)
-    S = n_eq + 2 * int(t_s) + n_hold
-    x = x0.clone()
-    v = torch.zeros_like(x)
-    ctx.init_velocities(v, bool(p.fix_com))
-    ctx.neigh_build(x, skin, 0)
-    W = torch.zeros(len(replicas), S, dtype=torch.float64, device=x.device)
-    ctx.run_switching(p, x, v, 0, S, W_out=W)
-    Wf, Wb = E.switch_works(p, W.cpu().numpy())
-
-    N = b0.natoms
-    n_eff = N - 1 if p.fix_com else N
-
-    def f0(rows, rep):
-        V = float(np.prod(rep.box))
-        return E.fl_free_energy(Wf[rows], Wb[rows], n_eff, rep.T, rep.k, rep.mass, N if p.fix_com else None,
-                                V if p.fix_com else None)
-
-    Fb, Edb, eb = f0(slice(0, n_bulk), b0)
-    Fs, Eds, es = f0(slice(n_bulk, len(replicas)), s0)
+    p, Wf, Wb = FL.run(ctx, x0, t_s, n_eq, n_hold, dt=dt, damp=damp, skin=skin, function=function)
+    Fb, Edb, eb = FL.system_free_energy(p, Wf[:n_bulk], Wb[:n_bulk], b0)
+    Fs, Eds, es = FL.system_free_energy(p, Wf[n_bulk:], Wb[n_bulk:], s0)
     A = surface_area(s0)
     return SurfaceFreeEnergy((Fs - Fb) / A, float(np.hypot(es, eb)) / A, Fb, eb, Fs, es, A, Edb, Eds)
