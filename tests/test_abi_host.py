@@ -187,3 +187,16 @@ def test_runner_rejects_unknown_workloads():
     from paper_2201_04622_amd import run as R
     with pytest.raises(ValueError):
         R.run_workload("no_such_workload")
+
+
+def test_transition_temperature_of_crossing_curves():
+    """The sign change of G_a - G_b, linear between grid points; None when
+    the difference keeps one sign."""
+    from paper_2201_04622_amd import transitions as TR
+    T = np.arange(300.0, 901.0, 1.0)
+    z = np.zeros_like(T)
+    a = TR.GibbsCurve("bcc", 1.0, 1.0, T, -0.001 * (T - 487.25), z, 0.0, 0.0)
+    b = TR.GibbsCurve("fcc", 1.0, 1.0, T, z, z, 0.0, 0.0)
+    assert TR.transition_temperature(a, b) == pytest.approx(487.25, abs=1e-9)
+    c = TR.GibbsCurve("hcp", 1.0, 1.0, T, z + 0.01, z, 0.0, 0.0)
+    assert TR.transition_temperature(c, b) is None
