@@ -37,9 +37,13 @@ def test_vacancy_forces_match_oracle(opot, prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", [FP64, FP32])
-def test_vacancy_formation_free_energy_at_low_temperature(opot, prec):
-    """At 10 K the FL estimate of G_f for fcc 5^3 must reproduce the oracle's
+@pytest.mark.parametrize("kind,a,cells,prec", [
+    ("fcc", I.A_FCC_STABLE, (5, 5, 5), FP64),
+    ("fcc", I.A_FCC_STABLE, (5, 5, 5), FP32),
+    ("hcp", I.A_FCC_STABLE / np.sqrt(2.0), (7, 4, 4), FP32),
+])
+def test_vacancy_formation_free_energy_at_low_temperature(opot, kind, a, cells, prec):
+    """At 10 K the FL estimate of G_f for fcc 5^3 (and hcp) must reproduce the oracle's
     0 K formation energy of the FIRE-relaxed vacancy (8.15 eV, relaxed from
     the sites plus a small seeded perturbation, so no symmetric saddle holds
     it) to 0.5 % plus three standard errors. The vacancy's vibrational
@@ -50,8 +54,8 @@ def test_vacancy_formation_free_energy_at_low_temperature(opot, prec):
     differently in every realization."""
     from oracle.minimize import fire
     T, k = 10.0, 50.0
-    perfect = [I.Replica("fcc", 0, I.A_FCC_STABLE, T, k, s, cells=(5, 5, 5)) for s in range(4)]
-    vac = [D.with_vacancy(I.Replica("fcc", 0, I.A_FCC_STABLE, T, k, 100 + s, cells=(5, 5, 5)), 0) for s in range(4)]
+    perfect = [I.Replica(kind, 0, a, T, k, s, cells=cells) for s in range(4)]
+    vac = [D.with_vacancy(I.Replica(kind, 0, a, T, k, 100 + s, cells=cells), 0) for s in range(4)]
     reps = perfect + vac
     ctx, x0, _ = make_ctx(reps, prec, 2, 256)
     res = D.vacancy_formation_free_energy(ctx, reps, x0, len(perfect), t_s=8000, n_eq=1000, n_hold=500)
@@ -62,6 +66,6 @@ def test_vacancy_formation_free_energy_at_low_temperature(opot, prec):
     _, Uv, _ = fire(opot, xs + 0.03 * np.random.default_rng(1).standard_normal(xs.shape), vac[0].box, fmax=1e-6,
                     max_steps=100000)
     Ef = Uv - (N - 1) / N * Ub
-    say(f"prec {prec}: G_f {res.G_f:.5f} +- {res.G_f_err:.1e} eV vs relaxed E_f {Ef:.5f}; dissipation perfect "
+    say(f"{kind} prec {prec}: G_f {res.G_f:.5f} +- {res.G_f_err:.1e} eV vs relaxed E_f {Ef:.5f}; dissipation perfect "
         f"{res.E_diss_perfect:.3f}, vacancy {res.E_diss_vacancy:.3f} eV")
     assert abs(res.G_f - Ef) <= 5e-3 * Ef + 3.0 * res.G_f_err
