@@ -135,6 +135,7 @@ class Replica:
     cells: tuple = None  # (nx, ny, nz) conventional cells of an orthorhombic supercell; None: n per edge
     vacuum: float = 0.0  # empty space added to the box along z (A): a slab with two free z faces
     vacancies: tuple = ()  # site ids (of the full supercell) left empty: point defects
+    c_over_a: float = None  # hcp only: c / a of the cell (None: the ideal sqrt(8/3))
 
     @property
     def dims(self) -> tuple:
@@ -144,14 +145,23 @@ class Replica:
     def natoms(self) -> int:
         return len(BASIS[self.kind]) * int(np.prod(self.dims)) - len(set(self.vacancies))
 
+    def _zscale(self) -> float:
+        if self.c_over_a is None:
+            return 1.0
+        if self.kind != "hcp":
+            raise ValueError("c_over_a applies to hcp only")
+        return float(self.c_over_a) / float(CELL["hcp"][2])
+
     @property
     def box(self) -> np.ndarray:
         L = np.asarray(self.dims, dtype=np.float64) * CELL[self.kind] * self.a
+        L[2] *= self._zscale()
         L[2] += self.vacuum
         return L
 
     def sites(self) -> np.ndarray:
         x = lattice_sites(self.kind, self.dims, self.a)
+        x[:, 2] *= self._zscale()
         if self.vacancies:
             keep = np.ones(len(x), dtype=bool)
             keep[list(set(self.vacancies))] = False

@@ -83,3 +83,57 @@ def _batch_root(kind, cells, T, a_guess, rel_span, n_trials, n_steps, discard, e
         pe = np.full(n_trials, np.nan)
     slope, icpt = np.polyfit(a, pm, 1)
     return ZeroPressure(float(-icpt / slope), float(slope), a, pm, pe, len(obs))
+
+
+@dataclass
+class ZeroStressHcp:
+    a: float                   # A
+    c_over_a: float
+    P: np.ndarray              # [trials, 3] mean diagonal pressure of each trial (eV/A^3)
+    trials: np.ndarray         # [trials, 2] (a, c/a) of each trial
+
+
+def zero_stress_hcp(cells, T, a_guess, q_guess=np.sqrt(8.0 / 3.0), rel_span=0.004, n_steps=4000, discard=1000,
+                    every=20, k=5.0, seed=0, precision=E.FP32, skin=0.3, lanes=2, block=256, iterations=2):
+    """hcp with both cell lengths free: a 3 x 3 batch of fixed-volume runs over
+    (a, c/a) around the guess, a plane fitted to the in-plane pressure
+    (P_xx + P_yy) / 2 and one to P_zz, and the point where both vanish.  Each
+    further iteration centres a new batch on the last solution (a Newton
+    step); the last one spans a third as much."""
+    import torch
+
+    a0, q0 = float(a_guess), float(q_guess)
+    out = None
+    for it in range(iterations):
+        span = rel_span if it < iterations - 1 else rel_span / 3.0
+        grid = [(a0 * (1.0 + span * da), q0 * (1.0 + span * dq)) for da in (-1, 0, 1) for dq in (-1, 0, 1)]
+        dims = I.cell_counts(cells)
+        reps = [I.Replica("hcp", dims[0], ak, float(T), float(k), seed + 1000 * it + j, cells=dims, c_over_a=qk)
+                for j, (ak, qk) in enumerate(grid)]
+        ctx = E.Context(0, precision)
+        try:
+            ctx.set_launch(lanes, block)
+            ctx.eam_setup(I.synthetic_eam_knots())
+            x = E.to_soa(I.batch_arrays(reps)["x0"])
+            ctx.system_setup(reps, x)
+            v = torch.zeros_like(x)
+            ctx.init_velocities(v, True)
+            ctx.neigh_build(x, skin, 0)
+            p = E.protocol("fl", n_steps, 1, 0, 0, skin=skin)   # lambda = 0 throughout: the EAM crystal
+            obs = []
+            for s in range(0, n_steps - n_steps % every, every):
+                ctx.run_switching(p, x, v, s, s + every)
+                if s + every > discard:
+                    obs.append(ctx.pressure(x, v))
+        finally:
+            ctx.close()
+        P = np.mean(obs, axis=0)                                   # [9, 3]
+        g = np.array(grid)
+        A = np.c_[np.ones(len(g)), g[:, 0] - a0, g[:, 1] - q0]
+        c_in, *_ = np.linalg.lstsq(A, 0.5 * (P[:, 0] + P[:, 1]), rcond=None)
+        c_z, *_ = np.linalg.lstsq(A, P[:, 2], rcond=None)
+        M = np.array([[c_in[1], c_in[2]], [c_z[1], c_z[2]]])
+        da, dq = np.linalg.solve(M, -np.array([c_in[0], c_z[0]]))
+        a0, q0 = a0 + da, q0 + dq
+        out = ZeroStressHcp(float(a0), float(q0), P, g)
+    return out

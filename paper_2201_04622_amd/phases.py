@@ -6,8 +6,8 @@ lattice parameter at T (batched fixed-volume runs, lattice.py), choose the
 Einstein spring constant from its mean-squared displacement (Eq. msd,
 springs.py), and run FL on a batch of realizations (Eq. W12 in Eq. fl with
 Eq. cm).  The free energies per atom at zero pressure then rank the phases,
-as the paper's bcc/fcc/hcp comparisons do.  The lattice parameter is scaled
-isotropically, so hcp keeps its ideal c/a.
+as the paper's bcc/fcc/hcp comparisons do.  hcp relaxes both cell lengths
+(lattice.zero_stress_hcp).
 
 Every step runs through the library; this module only sequences the runs.
 """
@@ -23,7 +23,7 @@ from . import inputs as I
 from . import lattice as LT
 from . import springs as SP
 
-CELLS = {"bcc": (6, 6, 6), "fcc": (5, 5, 5), "hcp": (7, 4, 4)}   # every edge above 2 (r_cut + skin)
+CELLS = {"bcc": (6, 6, 6), "fcc": (5, 5, 5), "hcp": (7, 4, 5)}   # every edge above 2 (r_cut + skin)
 A_GUESS = {"bcc": I.A_BCC_STABLE, "fcc": I.A_FCC_STABLE, "hcp": I.A_FCC_STABLE / np.sqrt(2.0)}
 
 
@@ -35,6 +35,7 @@ class Phase:
     F_per_atom: float     # eV
     F_err: float
     E_diss_per_atom: float
+    c_over_a: float = None   # hcp: relaxed c/a at T
 
 
 def phase_free_energy(kind, T, cells=None, realizations=4, t_s=8000, n_eq=1000, n_hold=1000, precision=E.FP32,
@@ -43,9 +44,15 @@ def phase_free_energy(kind, T, cells=None, realizations=4, t_s=8000, n_eq=1000, 
     import torch
 
     cells = CELLS[kind] if cells is None else cells
-    zp = LT.zero_pressure_lattice(kind, cells, T, A_GUESS[kind], rel_span=0.004, n_trials=8, n_steps=4000,
-                                  discard=1000, iterations=2, seed=seed, precision=precision, skin=skin)
-    reps = [I.Replica(kind, 0, zp.a0, T, 1.0, seed + 10 + s, cells=cells) for s in range(realizations)]
+    if kind == "hcp":   # both cell lengths free
+        zs = LT.zero_stress_hcp(cells, T, A_GUESS[kind], rel_span=0.004, n_steps=4000, discard=1000, seed=seed,
+                                precision=precision, skin=skin, iterations=5)
+        a0, q0 = zs.a, zs.c_over_a
+    else:
+        a0 = LT.zero_pressure_lattice(kind, cells, T, A_GUESS[kind], rel_span=0.004, n_trials=8, n_steps=4000,
+                                      discard=1000, iterations=2, seed=seed, precision=precision, skin=skin).a0
+        q0 = None
+    reps = [I.Replica(kind, 0, a0, T, 1.0, seed + 10 + s, cells=cells, c_over_a=q0) for s in range(realizations)]
 
     def context(rs):
         ctx = E.Context(0, precision)
@@ -71,7 +78,7 @@ def phase_free_energy(kind, T, cells=None, realizations=4, t_s=8000, n_eq=1000, 
         ctx.close()
     F0, Ed, err = FL.system_free_energy(p, Wf, Wb, reps[0])
     N = reps[0].natoms
-    return Phase(kind, zp.a0, reps[0].k, F0 / N, err / N, Ed / N)
+    return Phase(kind, a0, reps[0].k, F0 / N, err / N, Ed / N, q0)
 
 
 def rank_phases(T, kinds=("bcc", "fcc", "hcp"), **kw):

@@ -101,3 +101,24 @@ def test_same_noise_trajectory(oracle_lib, opot):
         assert np.abs(dH[r].cpu().numpy() - dHo).max() < 1e-9 * scale, r
         assert np.abs(W[r].cpu().numpy() - Wo).max() < 1e-9 * scale, r
     ctx.close()
+
+
+def test_hcp_zero_stress_cell_at_low_temperature(opot):
+    """hcp with a and c free. At 1 K, fixed-volume runs locate the cell where
+    the in-plane and the axial pressures both vanish. There the oracle's
+    static pressure tensor of the perfect lattice must be near zero in every
+    component: below 1 % of the axial pressure that a 1 % change of c/a
+    produces, which pins c/a to about 0.01 %. The relaxed c/a of this
+    potential is 1.560, 4.5 % below the ideal 1.633, where P_zz would be
+    about 0.4 eV/A^3."""
+    import paper_2201_04622_amd.lattice as LT
+    cells = (7, 4, 5)
+    res = LT.zero_stress_hcp(cells, 1.0, A_HCP_STABLE, rel_span=0.004, n_steps=1500, discard=500, every=50,
+                             precision=FP64, iterations=5)
+    r = I.Replica("hcp", 0, res.a, 1.0, 5.0, 0, cells=cells, c_over_a=res.c_over_a)
+    P = opot.pressure(r.sites(), r.box)
+    r2 = I.Replica("hcp", 0, res.a, 1.0, 5.0, 0, cells=cells, c_over_a=res.c_over_a * 1.01)
+    dPz = abs(opot.pressure(r2.sites(), r2.box)[2] - P[2])
+    say(f"hcp zero stress at 1 K: a {res.a:.5f} A, c/a {res.c_over_a:.5f} (ideal {np.sqrt(8 / 3):.5f}); "
+        f"static P {P} eV/A^3, axial response to 1 % of c/a {dPz:.3e}")
+    assert np.abs(P).max() < 1e-2 * dPz
