@@ -6,7 +6,8 @@ fcc_hcp): for each structure, FL at T0 in the box of its zero-pressure
 lattice parameter gives G(T0) (at p = 0, G = F up to terms of order kB T per
 system); reversible scaling under the barostat from T0 to T_f then gives
 G(T) on a 1 K grid (Eq. rs in its fixed-centre-of-mass form, with G for F).
-Where G_a(T) - G_b(T) changes sign the stable structure changes.
+Where G_a(T) - G_b(T) changes sign the stable structure changes.  hcp starts
+from its cell relaxed at T0 (a and c/a); the isotropic barostat keeps its c/a.
 
 Every step runs through the library; this module only sequences the runs.
 """
@@ -52,9 +53,15 @@ def gibbs_curve(kind, T0, Tf, cells=None, realizations=4, fl_steps=(1000, 16000,
     import torch
 
     cells = CELLS[kind] if cells is None else cells
-    a0 = LT.zero_pressure_lattice(kind, cells, T0, A_GUESS[kind], rel_span=0.004, n_trials=8, n_steps=4000,
-                                  discard=1000, iterations=2, seed=seed, precision=precision, skin=skin).a0
-    reps = [I.Replica(kind, 0, a0, T0, 1.0, seed + 10 + s, cells=cells) for s in range(realizations)]
+    if kind == "hcp":   # the cell relaxed at T0; the isotropic barostat then keeps its c/a
+        zs = LT.zero_stress_hcp(cells, T0, A_GUESS[kind], rel_span=0.004, n_steps=4000, discard=1000, seed=seed,
+                                precision=precision, skin=skin, iterations=5)
+        a0, q0 = zs.a, zs.c_over_a
+    else:
+        a0 = LT.zero_pressure_lattice(kind, cells, T0, A_GUESS[kind], rel_span=0.004, n_trials=8, n_steps=4000,
+                                      discard=1000, iterations=2, seed=seed, precision=precision, skin=skin).a0
+        q0 = None
+    reps = [I.Replica(kind, 0, a0, T0, 1.0, seed + 10 + s, cells=cells, c_over_a=q0) for s in range(realizations)]
     ctx, x = _context(reps, precision)
     try:
         v = torch.zeros_like(x)
@@ -74,7 +81,7 @@ def gibbs_curve(kind, T0, Tf, cells=None, realizations=4, fl_steps=(1000, 16000,
     per = np.array([FL.system_free_energy(p, Wf[q:q + 1], Wb[q:q + 1], reps[0])[0] for q in range(len(reps))])
     G0, G0_err = per.mean(), per.std(ddof=1) / np.sqrt(len(per))
 
-    rs_reps = [I.Replica(kind, 0, a0, T0, 0.0, seed + 50 + s, cells=cells) for s in range(realizations)]
+    rs_reps = [I.Replica(kind, 0, a0, T0, 0.0, seed + 50 + s, cells=cells, c_over_a=q0) for s in range(realizations)]
     ctx, x = _context(rs_reps, precision)
     try:
         v = torch.zeros_like(x)
