@@ -58,12 +58,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload, prec, launch):
+def measured_traffic(kernel, workload, prec, launch, skin):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes, each scaled by the factor the same
     counter reads for a plain copy), or None when there is no summary for this
-    kernel, workload, precision and launch shape, or the kernel sources have
-    changed since the counters were taken."""
+    kernel, workload, precision, launch shape and skin, or the kernel sources
+    have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -77,14 +77,16 @@ def measured_traffic(kernel, workload, prec, launch):
         return None
     if kv.get("launch") != f"lanes {launch[0]} block {launch[1]}":
         return None
+    if kv.get("skin") is None or float(kv["skin"]) != float(skin):
+        return None
     return float(kv["traffic_bytes_per_launch"])
 
 
-def measured_issue(kernel, workload, prec, launch):
+def measured_issue(kernel, workload, prec, launch, skin):
     """VALU issue and LDS bank-conflict shares of ``kernel``'s cycles over the
     timed dispatches, from the committed SQ counter summary, or None when it
-    does not cover this kernel, workload, precision and launch, or the kernel
-    sources have changed since the counters were taken."""
+    does not cover this kernel, workload, precision, launch and skin, or the
+    kernel sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"k_force_k_density_{workload}_{prec}_issue_utilisation.txt")
     if not os.path.exists(path) or launch != (2, 1024):
         return None
@@ -96,11 +98,13 @@ def measured_issue(kernel, workload, prec, launch):
             k, v = (t.strip() for t in line.split(":", 1))
             if k == "kernel_source_sha256":
                 src = v
+            elif k == "skin":
+                kv["skin"] = v
             elif k == "kernel":
                 name = v
             elif name and name.startswith(kernel + "<"):
                 kv[k] = v
-    if src != kernel_source_hash() or "valu_issue" not in kv:
+    if src != kernel_source_hash() or "valu_issue" not in kv or float(kv.get("skin", "nan")) != float(skin):
         return None
     return {"valu_issue": float(kv["valu_issue"]), "lds_conflict": float(kv["lds_conflict"]),
             "resident_waves_per_simd": float(kv["resident_waves_per_simd"])}
@@ -202,7 +206,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--skin", type=float, default=0.5)
+    ap.add_argument("--skin", type=float, default=0.65)   # fastest of a 0.35..1.2 sweep on the 64-replica batch
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -233,8 +237,8 @@ def main():
     bytes_launch = bpa * main_run["natoms"]
     achieved = bytes_launch / (avg_ms / 1e3) / 1e9
     kname = "k_force" if dom == "force" else "k_density"
-    traffic = measured_traffic(kname, args.workload, args.precision, main_run["launch"])
-    issue = measured_issue(kname, args.workload, args.precision, tuple(main_run["launch"]))
+    traffic = measured_traffic(kname, args.workload, args.precision, main_run["launch"], args.skin)
+    issue = measured_issue(kname, args.workload, args.precision, tuple(main_run["launch"]), args.skin)
 
     plain = None
     if not args.no_fp64:
