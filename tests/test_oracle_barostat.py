@@ -3,6 +3,7 @@ rescaling between fixed-volume stretches), pinned by the zero-coupling limit
 and by the 0 K zero-pressure lattice parameter found from the static
 pressure alone."""
 import numpy as np
+import pytest
 
 from paper_2201_04622_amd import inputs as I
 
@@ -57,3 +58,59 @@ def test_relaxes_to_the_zero_pressure_lattice_at_low_temperature(oracle_lib, opo
     assert abs(late.mean() / a0 - 1.0) < 2e-4, (late.mean(), a0)
     assert Ps[0] < 0.0            # the expanded start is under tension
     assert abs(Ps[-20:].mean()) < 2e-3 * abs(Ps[0])
+
+
+def _virial_trace_by_strain(opot, x, L, h=1e-5):
+    """Trace of the pair virial, sum over pairs of r_ij . f_ij, from the energy
+    alone: under a uniform dilation x -> s x, L -> s L the energy changes by
+    dU/ds = -tr W at s = 1 (central difference)."""
+    up = opot.eam(x * (1 + h), L * (1 + h))["U"]
+    dn = opot.eam(x * (1 - h), L * (1 - h))["U"]
+    return -(up - dn) / (2 * h)
+
+
+def test_move_statistics_match_the_published_rescaling(oracle_lib, opot):
+    """One stochastic cell-rescaling move (Bernetti and Bussi 2020) at a fixed
+    configuration: d eps = ln(V'/V) has the drift
+    -(beta_T/tau_p)(p0 - P - kB T/V) dt and the variance
+    2 kB T beta_T dt / (V tau_p), with P = (sum m v^2 + tr W)/(3 V) the internal
+    pressure.  P is rebuilt here from a strain derivative of the energy, and
+    the constants from SI values.  Over many steps (each keys its own
+    deviate) the sample mean and variance of d eps must match, and since the
+    deviate is a known function of (seed, step), each move must equal drift +
+    amplitude z to rounding, which resolves the kB T / V term as well."""
+    from oracle import barostat as OB
+    rep = I.Replica("bcc", 0, I.A_BCC_STABLE * 1.01, 600.0, 0.0, 5, cells=(6, 6, 6))
+    p = oracle_lib.RunParams(mode="rs", T=rep.T, k=0.0, seed=rep.seed)
+    x0 = I.displaced(rep.sites(), 0.04, seed=9)
+    v0 = oracle_lib.init_velocities(p, rep.natoms)
+    L = np.asarray(rep.box, dtype=np.float64)
+    V = float(np.prod(L))
+    w_eam, tau_p, beta_T, dt = 0.8, 0.2, 0.3, 0.01
+    mass = 55.845
+    P = (mass * _MVV2E_SI * float(np.sum(v0 * v0)) + w_eam * _virial_trace_by_strain(opot, x0, L)) / (3 * V)
+    kT = _KB_SI * rep.T
+    amp = np.sqrt(2 * kT * beta_T * dt / (V * tau_p))
+    for p0 in (P + 0.05, P + kT / V):    # a strong drift, then the stationary point
+        drift = -(beta_T / tau_p) * (p0 - P - kT / V) * dt
+        deps, zs = [], []
+        for step in range(1, 801):
+            x, v = x0.copy(), v0.copy()
+            L1, mu, Pm = OB.move(opot, x, v, L, rep.T, mass, rep.seed, step, w_eam, p0, tau_p, beta_T, dt)
+            assert Pm == pytest.approx(P, rel=1e-7)
+            assert np.allclose(L1, L * mu) and np.allclose(x, x0 * mu) and np.allclose(v, v0 / mu)
+            deps.append(3 * np.log(mu))
+            zs.append(oracle_lib.gauss3(rep.seed, 0, step, 3)[0])
+        deps, zs = np.asarray(deps), np.asarray(zs)
+        n = len(deps)
+        assert abs(deps.mean() - drift) < 4 * amp / np.sqrt(n), (deps.mean(), drift)
+        assert abs(deps.var(ddof=1) / amp ** 2 - 1) < 4 * np.sqrt(2.0 / (n - 1))
+        # move by move: d eps - amp z is the drift; the kB T / V part of it is
+        # (beta_T / tau_p)(kB T / V) dt, far above this bound
+        assert np.abs(deps - amp * zs - drift).max() < 1e-3 * (beta_T / tau_p) * (kT / V) * dt
+
+
+# the oracle-independent metal-unit constants (SI, CODATA 2018)
+_EV_J = 1.602176634e-19
+_MVV2E_SI = 1.66053906660e-27 * 1e-20 / 1e-24 / _EV_J
+_KB_SI = 1.380649e-23 / _EV_J

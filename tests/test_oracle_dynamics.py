@@ -240,3 +240,35 @@ def test_energy_conserved_with_per_atom_springs(oracle_lib):
     scale = 1.0 + 2.0 * (np.arange(N) % 3)
     _, _, e, _ = O.run(None, p, x0, np.full(3, 1000.0), x, v, np.ones(4001), energies=True, spring_scale=scale)
     assert np.ptp(e) < 2e-3 * np.abs(e).mean(), (np.ptp(e), e.mean())
+
+
+# Metal-unit constants rebuilt from SI values (CODATA 2018 exact and
+# recommended), independently of the literals the oracle carries.
+_EV_J = 1.602176634e-19
+_AMU_KG = 1.66053906660e-27
+_MVV2E_SI = _AMU_KG * 1e-20 / 1e-24 / _EV_J      # 1 amu A^2 / ps^2 in eV
+_KB_SI = 1.380649e-23 / _EV_J                     # eV / K
+
+
+@pytest.mark.parametrize("fix_com", [False, True])
+def test_initial_velocities_have_the_maxwell_boltzmann_amplitude(oracle_lib, fix_com):
+    """Initial velocities (Sec. p_fl, thermal start at T): each Cartesian
+    component is Gaussian with variance kB T / m, so sum m v^2 / (N_dof kB T)
+    = 1 with N_dof = 3N, or 3(N - 1) once the mean velocity is removed; the
+    ratio of the sum of N_dof independent squared deviates has relative
+    standard deviation sqrt(2 / N_dof).  A wrong factor in the amplitude
+    (sqrt 2, a missing unit conversion, T for kB T) fails by many sigma."""
+    N, T, mass = 100000, 300.0, 55.845
+    p = oracle_lib.RunParams(mode="fl", T=T, mass=mass, seed=11, fix_com=fix_com)
+    v = oracle_lib.init_velocities(p, N)
+    dof = 3 * (N - 1) if fix_com else 3 * N
+    ratio = mass * _MVV2E_SI * float(np.sum(v * v)) / (dof * _KB_SI * T)
+    assert abs(ratio - 1.0) < 4.0 * np.sqrt(2.0 / dof), ratio
+    sig = np.sqrt(_KB_SI * T / (mass * _MVV2E_SI))
+    for c in range(3):   # each component alone, and its shape
+        rc = float(np.sum(v[:, c] ** 2)) / (N * sig * sig)
+        assert abs(rc - 1.0) < 4.0 * np.sqrt(2.0 / N), (c, rc)
+        assert stats.kstest(v[:, c] / sig, "norm").pvalue > 1e-4
+    # a second temperature scales the amplitude as sqrt(T)
+    p2 = oracle_lib.RunParams(mode="fl", T=4 * T, mass=mass, seed=11, fix_com=fix_com)
+    assert np.allclose(oracle_lib.init_velocities(p2, N), 2.0 * v, rtol=1e-13, atol=1e-13)

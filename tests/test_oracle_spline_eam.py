@@ -57,24 +57,6 @@ def _shells(kind, a, rc):
     return d
 
 
-# Static values of the perfect lattices computed independently with numpy from
-# the analytic functions (density per atom, energy per atom in eV), to the
-# digits recorded.
-STATIC = {("bcc", 2.855): (10.9645, -10.37651), ("fcc", 3.65): (9.9515, -9.84921),
-          ("bcc", 1.9646): (84.67, -18.7229), ("fcc", 2.5216): (77.52, -18.7117)}
-
-
-@pytest.mark.parametrize("kind,a,n", [("bcc", 2.855, 4), ("fcc", 3.65, 3), ("bcc", 1.9646, 6), ("fcc", 2.5216, 5)])
-def test_perfect_lattice_recorded_values(opot, kind, a, n):
-    rho_ref, u_ref = STATIC[(kind, a)]
-    x = I.lattice_sites(kind, n, a)
-    r = opot.eam(x, np.full(3, n * a))
-    digits_rho = len(str(rho_ref).split(".")[1])
-    digits_u = len(str(u_ref).split(".")[1])
-    assert np.allclose(r["rho"], rho_ref, rtol=0, atol=0.51 * 10.0 ** -digits_rho)
-    assert r["U"] / len(x) == pytest.approx(u_ref, abs=0.51 * 10.0 ** -digits_u)
-
-
 @pytest.mark.parametrize("kind,a,n", [("bcc", 2.855, 4), ("fcc", 3.65, 3), ("bcc", 1.9646, 6), ("fcc", 2.5216, 5)])
 def test_perfect_lattice_energy_equals_shell_sum(opot, kind, a, n):
     d = _shells(kind, a, I.R_CUT)
