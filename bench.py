@@ -29,9 +29,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2201_04622_amd/csrc/eamfe_kernels.hip", "paper_2201_04622_amd/csrc/eamfe_internal.h")
-# HIP-event pairs around the kernels of one iteration in this many: each pair
-# costs ~10 us of stream time, so sampling keeps the timed region unperturbed
-KERNEL_TIMING_STRIDE = 50
+# worker threads of the all-core oracle leg: at most the host share of one GPU
+CPU_THREADS_MAX = 16
+
+
+def timing_stride(steps):
+    """Iterations between two HIP-event samples of the dominant kernel inside
+    the timed region.  The first timed iteration is always sampled, then every
+    stride-th.  An event pair adds about 5 us of stream time to a step of
+    60-80 us, so one sample in ten or fewer keeps the timed value within
+    about 1 % of an unsampled run (measured: 10 % at one in two); long runs
+    take one in fifty."""
+    return max(10, min(50, steps // 10))
 
 
 def force_bytes_per_atom(n_list, prec):
@@ -110,7 +119,12 @@ def measured_issue(kernel, workload, prec, launch, skin):
             "resident_waves_per_simd": float(kv["resident_waves_per_simd"])}
 
 
-def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None):
+def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None, stride=None, graph=0):
+    """Run warmup + steps steps of a workload's protocol on the GPU; the
+    last `steps` are timed with HIP events around one run_switching call on
+    the library's stream (torch's current stream).  Inside the timed region
+    the force pass of the first timed iteration and then of every
+    stride-th one is bracketed by its own event pair (stride 0: none)."""
     import torch
 
     import paper_2201_04622_amd.eamfe as E
@@ -139,9 +153,12 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
         ctx.run_switching(p, x, v, 0, warmup, sync=True)
     if autotune and not lanes:
         tuned = ctx.autotune(p, warmup, x, v, trial_steps=20)
+    if graph:
+        ctx.set_graph(graph)
     natoms = int(arrs["x0"].shape[0])
     torch.cuda.synchronize()
-    ctx.set_kernel_timing(KERNEL_TIMING_STRIDE)
+    stride = timing_stride(steps) if stride is None else stride
+    ctx.set_kernel_timing(stride, kinds=("force",))
     ctx.row_history(reset=True)   # list work of the timed passes only
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -153,6 +170,7 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     kt = ctx.kernel_timing()
+    ctx.set_kernel_timing(0)
     ctx.check()
     mean_nl, passes = ctx.row_history()   # time average over the timed force passes
     rebuilt_reps, rebuilt_atoms = ctx.list_rebuilds()
@@ -160,38 +178,157 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     launch = ctx.get_launch()
     ctx.close()
     return {
-        "natoms": natoms, "n_rep": len(reps), "ms": ms, "wall_s": wall, "kt": kt, "mean_nl": mean_nl,
-        "passes": passes, "rebuilt_reps": rebuilt_reps, "rebuilt_atoms": rebuilt_atoms, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch, "tuned": tuned, "desc": wl.description,
+        "natoms": natoms, "n_rep": len(reps), "steps": steps, "ms": ms, "wall_s": wall, "kt": kt,
+        "stride": stride, "mean_nl": mean_nl, "passes": passes, "rebuilt_reps": rebuilt_reps,
+        "rebuilt_atoms": rebuilt_atoms, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch,
+        "tuned": tuned, "desc": wl.description,
     }
 
 
-def cpu_baseline(target_s=12.0):
-    """The FP64 oracle as it stands on one host core: one 2000-atom replica
-    of the default workload (bcc 10^3, T = 500 K), Verlet candidates with
-    0.3 A skin, FL protocol from the lattice start."""
-    import numpy as np
+def roofline(run, prec, workload, skin):
+    """The dominant kernel's (the force pass's) HBM roofline figure from a
+    run_gpu record: algorithmic bytes per launch (per-atom bytes at the mean
+    row length of the timed passes, times the atoms one launch processes)
+    over the mean event-timed launch duration.  None when the timed region
+    had no sampled launch (timing switched off)."""
+    ms, n = run["kt"]["force"]
+    if n <= 0 or not ms > 0.0:
+        return None
+    avg_ms = ms / n
+    bpa = force_bytes_per_atom(run["mean_nl"], prec)
+    bytes_launch = bpa * run["natoms"]
+    achieved = bytes_launch / (avg_ms / 1e3) / 1e9
+    return {
+        "bound": "hbm", "kernel": "k_force",
+        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": measured_traffic("k_force", workload, prec, run["launch"], skin),
+        "algorithmic_bytes": bytes_launch, "bytes_per_atom": bpa,
+        # the same kernel's VALU issue and LDS-conflict shares from SQ counters (what bounds it)
+        "issue": measured_issue("k_force", workload, prec, tuple(run["launch"]), skin),
+        "avg_launch_us": avg_ms * 1e3, "launches_timed": n, "timing_stride": run["stride"],
+    }
+
+
+def host_cpu():
+    """Threads this process may run on (the machine's host share, capped) and the
+    host's CPU model and clock as /proc/cpuinfo reports them."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model, mhz = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                if k.strip() == "model name" and model == "unknown":
+                    model = v.strip()
+                elif k.strip() == "cpu MHz" and mhz is None:
+                    mhz = float(v)
+    except OSError:
+        pass
+    return {"threads_available": avail, "model": model, "mhz": mhz}
+
+
+def cpu_baseline(target_s=8.0):
+    """The FP64 oracle as it stands (plain C, scalar loops, Verlet candidate
+    lists with a 0.3 A skin), timed on the host on a bounded sample of the
+    default workload's Frenkel--Ladd protocol from the lattice start:
+      * one core: replica 4 of the batch (bcc 10^3, 2000 atoms) for about
+        target_s seconds;
+      * all cores: one worker thread per available core (at most
+        CPU_THREADS_MAX), each running a different replica of the batch
+        (uneven sizes, replicas 0, 1, ...) in 20-step chunks for about
+        target_s seconds; the rate is all atom-steps over the leg's wall time.
+    The oracle is a single C call per chunk (ctypes releases the GIL), so the
+    threads run concurrently.  `value` is the all-core rate."""
+    from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
     from paper_2201_04622_amd import inputs as I
     O.build()
     wl = I.workload("batch64")
-    r = wl.replicas[4]
     pot = O.Potential.from_knots(I.synthetic_eam_knots())
-    prm = O.RunParams(mode="fl", T=r.T, k=r.k, seed=r.seed, fix_com=True, skin=0.3, nlist_cap=512)
-    x0 = r.sites()
-    x, v = x0.copy(), O.init_velocities(prm, r.natoms)
     lam = O.schedule("fl", 2000, 20000, 2000, 0)
-    done, step, t_used = 0, 0, 0.0
-    chunk = 20
-    while t_used < target_s:
-        t = time.perf_counter()
-        O.run(pot, prm, x0, r.box, x, v, lam[step: step + chunk + 1], step0=step)
-        t_used += time.perf_counter() - t
-        done += chunk
-        step += chunk
-    return {"value": r.natoms * done / t_used, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, 1 replica bcc 10^3 (2000 atoms) of the batch, FL steps 0..{done}, "
-                      f"{t_used:.1f} s on one host core"}
+
+    def leg(r, budget, chunk=20):
+        """Steps of replica r in chunks until `budget` seconds have passed;
+        (atom-steps done, seconds used)."""
+        prm = O.RunParams(mode="fl", T=r.T, k=r.k, seed=r.seed, fix_com=True, skin=0.3, nlist_cap=512)
+        x0 = r.sites()
+        x, v = x0.copy(), O.init_velocities(prm, r.natoms)
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            O.run(pot, prm, x0, r.box, x, v, lam[done: done + chunk + 1], step0=done)
+            done += chunk
+        return r.natoms * done, time.perf_counter() - t0
+
+    one = wl.replicas[4]
+    as1, t1 = leg(one, target_s)
+    rate1 = as1 / t1
+    host = host_cpu()
+    n_thr = max(1, min(CPU_THREADS_MAX, host["threads_available"]))
+    reps = [wl.replicas[q % len(wl.replicas)] for q in range(n_thr)]
+    t = time.perf_counter()
+    with ThreadPoolExecutor(n_thr) as ex:
+        res = list(ex.map(lambda r: leg(r, target_s), reps))
+    wall = time.perf_counter() - t
+    as_all = sum(a for a, _ in res)
+    steps_each = [a // r.natoms for (a, _), r in zip(res, reps)]
+    return {
+        "value": as_all / wall, "unit": "atom-steps/s", "cores": n_thr, "kind": "oracle",
+        "sample": (f"FP64 oracle, {n_thr} threads each running one replica of the 64-replica batch "
+                   f"({sum(r.natoms for r in reps)} atoms in all, {min(steps_each)}-{max(steps_each)} FL steps "
+                   f"each from the lattice start, {wall:.1f} s wall); one core: bcc 10^3 (2000 atoms), "
+                   f"{as1 // one.natoms} steps in {t1:.1f} s"),
+        "single_core": {"value": rate1, "unit": "atom-steps/s", "cores": 1},
+        "host": host,
+    }
+
+
+def result_line(args, main_run, plain, cpu):
+    """The bench's one JSON line from the measured legs (no GPU calls here)."""
+    value = main_run["natoms"] * main_run["steps"] / (main_run["ms"] / 1e3)
+    kt = main_run["kt"]
+    out = {
+        "metric": "atom-steps/s, EAM switching MD: batched FP32 vs plain FP64, dF <=0.5 meV/atom",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": main_run["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms"] / main_run["steps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {main_run['desc']}",
+            "replicas": main_run["n_rep"],
+            "atoms": main_run["natoms"],
+            "precision": ("f32 pair terms and densities, f64 positions/velocities/energies/work, "
+                          "2^-32 fixed-point per-atom sums") if args.precision == "fp32" else "f64 throughout",
+            "mean_neighbour_row": round(main_run["mean_nl"], 2),   # over the timed force passes
+            "final_neighbour_row": round(main_run["end_nl"], 2),
+            "max_neighbour_row": main_run["max_nl"],
+            "force_passes": main_run["passes"],
+            # list rebuilds of the timed passes: replica lists per step, atoms per step
+            "list_rebuilds_per_step": round(main_run["rebuilt_reps"] / main_run["steps"], 3),
+            "atoms_rebuilt_per_step": round(main_run["rebuilt_atoms"] / main_run["steps"], 1),
+            "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
+                       "autotuned": main_run["tuned"] is not None},
+            "skin": args.skin,
+            "force_kernel_ms_sampled": round(kt["force"][0], 4),
+            "force_launches_sampled": kt["force"][1],
+        },
+        "roofline": roofline(main_run, args.precision, args.workload, args.skin),
+        "fp64_plain_single_replica": plain,
+        "cpu_baseline": cpu,
+    }
+    if plain:
+        out["batched_fp32_over_plain_fp64"] = value / plain["value"]
+    return out
 
 
 def main():
@@ -207,6 +344,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--skin", type=float, default=0.65)   # fastest of a 0.35..1.2 sweep on the 64-replica batch
+    ap.add_argument("--timing-stride", type=int, default=None,
+                    help="iterations between event-timed force passes in the timed region (0: none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -225,77 +364,22 @@ def main():
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
               "(replicas would shard across GPUs with only a final gather of the work traces)", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: need --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
 
     main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup, args.lanes, args.block,
-                       not args.no_autotune, args.skin)
-    atom_steps = main_run["natoms"] * args.steps
-    value = atom_steps / (main_run["ms"] / 1e3)
-    kt = main_run["kt"]
-    dom = "force" if kt["force"][0] >= kt["density"][0] else "density"
-    avg_ms = kt[dom][0] / max(1, kt[dom][1])
-    bpa = (force_bytes_per_atom if dom == "force" else density_bytes_per_atom)(main_run["mean_nl"], args.precision)
-    bytes_launch = bpa * main_run["natoms"]
-    achieved = bytes_launch / (avg_ms / 1e3) / 1e9
-    kname = "k_force" if dom == "force" else "k_density"
-    traffic = measured_traffic(kname, args.workload, args.precision, main_run["launch"], args.skin)
-    issue = measured_issue(kname, args.workload, args.precision, tuple(main_run["launch"]), args.skin)
-
+                       not args.no_autotune, args.skin, stride=args.timing_stride)
     plain = None
     if not args.no_fp64:
-        pr = run_gpu("fl_mid", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0])
+        pr = run_gpu("fl_mid", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0], stride=0)
         plain = {
             "value": pr["natoms"] * 2000 / (pr["ms"] / 1e3), "unit": "atom-steps/s",
             "workload": "one FL replica, bcc 10^3 (2000 atoms), T=1400 K, k=3, FP64, autotuned launch",
             "ms_per_step": pr["ms"] / 2000,
         }
     cpu = None if args.no_cpu else cpu_baseline()
-
-    out = {
-        "metric": "atom-steps/s, EAM switching MD: batched FP32 vs plain FP64, dF <=0.5 meV/atom",
-        "value": value,
-        "unit": "atom-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": main_run["ms"] / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: {main_run['desc']}",
-            "replicas": main_run["n_rep"],
-            "atoms": main_run["natoms"],
-            "precision": ("f32 pair terms and densities, f64 positions/velocities/energies/work, "
-                          "2^-32 fixed-point per-atom sums") if args.precision == "fp32" else "f64 throughout",
-            "mean_neighbour_row": round(main_run["mean_nl"], 2),   # over the timed force passes
-            "final_neighbour_row": round(main_run["end_nl"], 2),
-            "max_neighbour_row": main_run["max_nl"],
-            "force_passes": main_run["passes"],
-            # list rebuilds of the timed passes: replica lists per step, atoms per step
-            "list_rebuilds_per_step": round(main_run["rebuilt_reps"] / args.steps, 3),
-            "atoms_rebuilt_per_step": round(main_run["rebuilt_atoms"] / args.steps, 1),
-            "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
-                       "autotuned": main_run["tuned"] is not None},
-            "skin": args.skin,
-            "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
-            "kernel_launches": {k: v[1] for k, v in kt.items()},
-        },
-        "roofline": {
-            "bound": "hbm", "kernel": kname,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic, "algorithmic_bytes": bytes_launch, "bytes_per_atom": bpa,
-            # the same kernel's VALU issue and LDS-conflict shares from SQ counters (what bounds it)
-            "issue": issue,
-            "avg_launch_us": avg_ms * 1e3,
-        },
-        "fp64_plain_single_replica": plain,
-        "cpu_baseline": cpu,
-    }
-    if plain:
-        out["batched_fp32_over_plain_fp64"] = value / plain["value"]
-    print(json.dumps(out), flush=True)
+    print(json.dumps(result_line(args, main_run, plain, cpu)), flush=True)
 
 
 if __name__ == "__main__":

@@ -163,12 +163,16 @@ int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
  * (EAMFE_ENEIGH_OVERFLOW ...), clearing it. */
 int eamfe_check(eamfe_ctx* ctx);
 
-/* Time the kernel launches of every `stride`-th iteration (global step index
- * divisible by stride) with HIP events recorded around them on the context's
- * stream; 0 stops.  An event pair costs about 10 us of stream time, so a
- * stride of tens leaves the timed work essentially unperturbed.  Switching
- * resets the accumulators. */
-int eamfe_set_kernel_timing(eamfe_ctx* ctx, int stride);
+/* Time kernel launches with HIP events recorded around them on the context's
+ * stream: the first iteration run after this call and then every
+ * `stride`-th iteration (counted over the iterations the stepping calls run,
+ * so any range of at least one iteration is sampled); stride 0 stops.
+ * `kinds` selects the kernels timed: bit 0 the density pass, bit 1 the force
+ * pass, bit 2 the neighbour-list rebuild sequence (0 = all three).  An event
+ * pair adds a few microseconds of stream time, so a stride of tens and one
+ * kind keep the timed work essentially unperturbed.  Each call resets the
+ * accumulators. */
+int eamfe_set_kernel_timing(eamfe_ctx* ctx, int stride, int kinds);
 
 /* Synchronise and return the summed event times (ms) and launch counts of
  * the density pass [0], the force pass [1] and the neighbour-list rebuild
@@ -406,9 +410,13 @@ double eamfe_einstein_free_energy(double n_eff, double T, double k, double mass)
 double eamfe_fixed_cm_correction(double N, double V, double T, double k);
 
 /* Frenkel--Ladd: from n replicas' forward (H0 -> H_E) and backward works,
- * F0 = F_E + (mean W_bwd - mean W_fwd)/2 [+ delta F_CM if add_cm]
- * (Eq. fl with the sign implied by Eq. W12).  Outputs: F0, the dissipation
- * (Eq. Ediss) and the standard error of F0 (any may be NULL). */
+ * F0 = F_E(n_eff) + (mean W_bwd - mean W_fwd)/2 [+ delta F_CM(N, V, T, k) if add_cm]
+ * (Eq. fl with the sign implied by Eq. W12, plus Eq. cm).  n_eff is the
+ * number of oscillators of the Einstein crystal, the atom count N: with the
+ * centre of mass held in the run (fix_com), Eq. cm alone accounts for the
+ * constraint, and F_E(N) + Eq. cm is the free crystal's free energy.
+ * Outputs: F0, the dissipation (Eq. Ediss) and the standard error of F0
+ * (any may be NULL). */
 int eamfe_fl_free_energy(int n, const double* W_fwd, const double* W_bwd, double n_eff, double N,
                          double V, double T, double k, double mass, int add_cm,
                          double* F0, double* E_diss, double* F0_err);
@@ -439,18 +447,19 @@ int eamfe_switch_works(const eamfe_protocol* p, int n_rep, const double* W_trace
 int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W_trace, double F0_T0, double T0,
                          double n_eff, int n_T, const double* T_grid, double* F_out);
 
-/* Eq. rs for a run with a fixed centre of mass (fix_com), the form to use
- * with an F0(T0) from eamfe_fl_free_energy that includes Eq. cm.  Such a run
- * samples the crystal with its centre of mass fixed, and Eq. rs maps that
- * system's free energy from T0 to T exactly; Eq. cm is the step from it to the
- * free crystal at each temperature.  So
- *   F(T) = rs(F0(T0) - cm(T0)) + cm(T),  cm(T) = eamfe_fixed_cm_correction(N, V, T, k),
- * with rs the map of eamfe_rs_free_energy, N atoms, V the box volume and k
- * the spring constant F0(T0) was found with.  Scaling cm(T0) by 1/l instead
- * would be off by (3/2) kB T ln(T/T0) per system. */
+/* Eq. rs for a run with the centre of mass held (fix_com), from an F0(T0)
+ * of the free crystal (eamfe_fl_free_energy with Eq. cm).  Such a run samples
+ * the held system, N atoms with 3(N-1) momenta and the configurational
+ * integral at one centre-of-mass position; Eq. rs maps that system's free
+ * energy from T0 to T exactly with n_eff = N - 1 in its kinetic term.  The
+ * free crystal differs from the held one by
+ *   c(T) = -kB T ln(V/N) + 3 kB T ln Lambda(T),  Lambda = sqrt(2 pi hbar^2 / (m kB T)),
+ * the convention under which F_E(N) + Eq. cm is the free crystal's value, so
+ *   F(T) = rs_{N-1}(F0(T0) - c(T0)) + c(T),
+ * rs the map of eamfe_rs_free_energy, N atoms, V the box volume, mass in amu.
+ * EAMFE_EINVAL for N <= 1, V <= 0 or mass <= 0, or as eamfe_rs_free_energy. */
 int eamfe_rs_free_energy_cm(const eamfe_protocol* p, const double* W_trace, double F0_T0, double T0,
-                            double n_eff, double N, double V, double k, int n_T, const double* T_grid,
-                            double* F_out);
+                            double N, double V, double mass, int n_T, const double* T_grid, double* F_out);
 
 #ifdef __cplusplus
 }

@@ -79,6 +79,8 @@ struct eamfe_ctx {
 
     // optional per-launch timing with HIP events on the context's stream
     int timing = 0;          // sample every timing-th iteration (0 = off)
+    int timing_kinds = 7;    // kernels timed: bit 0 density, bit 1 force, bit 2 list rebuild
+    int64_t timing_seen = 0; // iterations run since timing was switched on
     bool timing_now = false; // current iteration is sampled
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -677,7 +679,7 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
 // Record a timing event (kind: 0 density, 1 force, 2 lists; end = 0 start, 1 stop).
 int mark(eamfe_ctx* c, int kind, int end)
 {
-    if (!c->timing || !c->timing_now) return EAMFE_OK;
+    if (!c->timing || !c->timing_now || !(c->timing_kinds & (1 << kind))) return EAMFE_OK;
     if (c->ev_used == c->ev_pool.size()) {
         hipEvent_t e;
         HIPCHK(c, hipEventCreate(&e));
@@ -698,7 +700,11 @@ int mark(eamfe_ctx* c, int kind, int end)
 int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool has_eam, hipStream_t st, bool sample,
                   int64_t it)
 {
-    c->timing_now = c->timing > 0 && it % c->timing == 0;
+    // sampled: the first iteration after timing was switched on, then every
+    // timing-th one, so any range of at least one iteration has a sample
+    c->timing_now = c->timing > 0 && c->timing_seen % c->timing == 0;
+    if (c->timing > 0) ++c->timing_seen;
+    (void)it;
     if (has_eam) {
         NeighArgs na = neigh_args(c, cur);
         OK(mark(c, 2, 0));
@@ -1397,10 +1403,12 @@ int eamfe_adjoint_samples(const eamfe_ctx* c, int64_t* n)
     return EAMFE_OK;
 }
 
-int eamfe_set_kernel_timing(eamfe_ctx* c, int stride)
+int eamfe_set_kernel_timing(eamfe_ctx* c, int stride, int kinds)
 {
-    if (!c || stride < 0) return EAMFE_EINVAL;
+    if (!c || stride < 0 || kinds < 0 || kinds > 7) return EAMFE_EINVAL;
     c->timing = stride;
+    c->timing_kinds = kinds ? kinds : 7;
+    c->timing_seen = 0;
     c->ev_used = 0;
     c->ev_kind.clear();
     return EAMFE_OK;
@@ -1834,14 +1842,19 @@ int eamfe_rs_free_energy(const eamfe_protocol* p, const double* W, double F0_T0,
     return EAMFE_OK;
 }
 
-int eamfe_rs_free_energy_cm(const eamfe_protocol* p, const double* W, double F0_T0, double T0, double n_eff,
-                            double N, double V, double k, int n_T, const double* T_grid, double* F_out)
+int eamfe_rs_free_energy_cm(const eamfe_protocol* p, const double* W, double F0_T0, double T0, double N, double V,
+                            double mass, int n_T, const double* T_grid, double* F_out)
 {
-    if (!(N > 0.0) || !(V > 0.0) || !(k > 0.0)) return EAMFE_EINVAL;
-    const int st = eamfe_rs_free_energy(p, W, F0_T0 - eamfe_fixed_cm_correction(N, V, T0, k), T0, n_eff, n_T,
-                                        T_grid, F_out);
+    if (!(N > 1.0) || !(V > 0.0) || !(mass > 0.0)) return EAMFE_EINVAL;
+    // c(T): free crystal minus the crystal with its centre of mass held
+    auto c_of = [&](double T) {
+        const double kT = kB * T;
+        const double lam_dB = std::sqrt(2.0 * M_PI * hbar * hbar / (mass * mvv2e * kT));
+        return -kT * std::log(V / N) + 3.0 * kT * std::log(lam_dB);
+    };
+    const int st = eamfe_rs_free_energy(p, W, F0_T0 - c_of(T0), T0, N - 1.0, n_T, T_grid, F_out);
     if (st != EAMFE_OK) return st;
-    for (int q = 0; q < n_T; ++q) F_out[q] += eamfe_fixed_cm_correction(N, V, T_grid[q], k);
+    for (int q = 0; q < n_T; ++q) F_out[q] += c_of(T_grid[q]);
     return EAMFE_OK;
 }
 

@@ -71,7 +71,7 @@ def lib():
         "eamfe_get_grid": (i32, [vp, C.POINTER(i32)]),
         "eamfe_set_xcd_affinity": (i32, [vp, i32]),
         "eamfe_check": (i32, [vp]),
-        "eamfe_set_kernel_timing": (i32, [vp, i32]),
+        "eamfe_set_kernel_timing": (i32, [vp, i32, i32]),
         "eamfe_autotune": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, i32, C.POINTER(i32), C.POINTER(i32), _dp]),
         "eamfe_kernel_timing": (i32, [vp, _dp, C.POINTER(i64)]),
         "eamfe_list_stats": (i32, [vp, _dp, C.POINTER(i32), C.POINTER(i32)]),
@@ -103,7 +103,7 @@ def lib():
         "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fl_free_energy": (i32, [i32, _dp, _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp, _dp]),
         "eamfe_rs_free_energy": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, i32, _dp, _dp]),
-        "eamfe_rs_free_energy_cm": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp]),
+        "eamfe_rs_free_energy_cm": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp]),
         "eamfe_jarzynski": (i32, [i32, _dp, dbl, _dp, _dp]),
         "eamfe_switch_works": (i32, [C.POINTER(Protocol), i32, _dp, i64, _dp, _dp]),
     }
@@ -172,13 +172,14 @@ def switch_works(p: Protocol, W_trace):
     return Wf, Wb
 
 
-def rs_free_energy_cm(p: Protocol, W_trace, F0_T0, T0, n_eff, N, V, k, T_grid):
-    """Eq. rs for a fixed-centre-of-mass run from an F0(T0) that includes Eq. cm."""
+def rs_free_energy_cm(p: Protocol, W_trace, F0_T0, T0, N, V, mass, T_grid):
+    """Eq. rs for a run with the centre of mass held, from the free crystal's
+    F0(T0) (Eq. fl + Eq. cm): F(T) on T_grid."""
     W = np.ascontiguousarray(W_trace, dtype=np.float64)
     Tg = np.ascontiguousarray(T_grid, dtype=np.float64)
     out = np.zeros_like(Tg)
     _chk(None, lib().eamfe_rs_free_energy_cm(C.byref(p), W.ctypes.data_as(_dp), float(F0_T0), float(T0),
-                                             float(n_eff), float(N), float(V), float(k), len(Tg),
+                                             float(N), float(V), float(mass), len(Tg),
                                              Tg.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
     return out
 
@@ -281,9 +282,11 @@ class Context:
                                          C.byref(a), C.byref(b), C.byref(ms)))
         return a.value, b.value, ms.value
 
-    def set_kernel_timing(self, stride=1):
-        """Time the kernels of every stride-th iteration with HIP events (0 = off)."""
-        self._c(self._lib.eamfe_set_kernel_timing(self._h, int(stride)))
+    def set_kernel_timing(self, stride=1, kinds=("density", "force", "lists")):
+        """Time the kernels of the first and then every stride-th iteration with
+        HIP events (0 = off); kinds: which of density, force, lists."""
+        mask = sum(1 << q for q, k in enumerate(("density", "force", "lists")) if k in kinds)
+        self._c(self._lib.eamfe_set_kernel_timing(self._h, int(stride), int(mask)))
 
     def kernel_timing(self):
         """{'density'|'force'|'lists': (total ms, launches)} since timing was enabled."""

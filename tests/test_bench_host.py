@@ -2,6 +2,7 @@
 the checks that keep a committed counter summary from being reported for a
 kernel, launch or list skin it was not taken at."""
 import importlib.util
+import json
 import os
 import subprocess
 import sys
@@ -78,3 +79,52 @@ def test_issue_summary_only_for_the_skin_it_was_taken_at(bench):
     assert dens is not None and dens != got
     assert bench.measured_issue("k_force", "batch64", "fp32", (2, 1024), skin - 0.15) is None
     assert bench.measured_issue("k_force", "batch64", "fp32", (4, 1024), skin) is None
+
+
+def _fake_run(force_ms, force_n, steps=20):
+    return {"natoms": 113090, "n_rep": 64, "steps": steps, "ms": 1.6, "wall_s": 0.002,
+            "kt": {"density": (0.0, 0), "force": (force_ms, force_n), "lists": (0.0, 0)},
+            "stride": 10, "mean_nl": 70.0, "passes": steps, "rebuilt_reps": 3, "rebuilt_atoms": 5000,
+            "end_nl": 71.0, "max_nl": 80, "cap": 160, "launch": (2, 1024), "tuned": (2, 1024, 0.08),
+            "desc": "64 replicas"}
+
+
+class _Args:
+    warmup, precision, workload, skin = 5, "fp32", "batch64", 0.65
+
+
+def test_timing_stride_samples_every_short_run(bench):
+    # the driver's short run (20 timed steps) and the default long run both get samples;
+    # the first timed iteration is always sampled, so any steps >= 1 has one
+    # at most one sample in ten iterations (each event pair costs ~5 us of a 60-80 us step)
+    assert bench.timing_stride(1) == 10 and bench.timing_stride(20) == 10
+    assert bench.timing_stride(42000) == 50
+
+
+def test_result_line_with_the_driver_step_counts(bench):
+    out = bench.result_line(_Args, _fake_run(0.066, 2), None, None)
+    assert out["steps"] == 20 and out["warmup"] == 5
+    assert out["ms_per_step"] == pytest.approx(1.6 / 20)
+    assert out["value"] == pytest.approx(113090 * 20 / 1.6e-3)
+    rf = out["roofline"]
+    assert rf["avg_launch_us"] == pytest.approx(33.0)
+    bpa = bench.force_bytes_per_atom(70.0, "fp32")
+    assert rf["achieved"] == pytest.approx(bpa * 113090 / 33e-6 / 1e9)
+    assert rf["frac"] == pytest.approx(rf["achieved"] / 8000.0)
+    json.dumps(out)
+
+
+def test_result_line_without_timed_launches_has_no_roofline(bench):
+    # timing switched off (or nothing sampled): no division, roofline null
+    out = bench.result_line(_Args, _fake_run(0.0, 0), None, None)
+    assert out["roofline"] is None
+    assert out["value"] > 0
+    json.dumps(out)
+
+
+def test_cpu_baseline_reports_threads_model_and_both_legs(bench):
+    cpu = bench.cpu_baseline(target_s=0.3)
+    assert cpu["kind"] == "oracle" and cpu["unit"] == "atom-steps/s"
+    assert 1 <= cpu["cores"] <= bench.CPU_THREADS_MAX
+    assert cpu["value"] > 0 and cpu["single_core"]["value"] > 0 and cpu["single_core"]["cores"] == 1
+    assert cpu["host"]["threads_available"] >= 1 and isinstance(cpu["host"]["model"], str)
