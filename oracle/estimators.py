@@ -14,8 +14,9 @@ MVV2E = 1.0364269e-4     # eV per amu A^2/ps^2
 
 def einstein_free_energy(n_eff, T, k, mass):
     """F_E = 3 N kB T ln(hbar w / kB T), w = sqrt(k/m)  (Eq. einstein and the
-    closed form below it).  ``n_eff`` is N, or N-1 when the centre of mass is
-    held fixed and only internal degrees of freedom count."""
+    closed form below it), ``n_eff`` oscillators.  In Eq. fl the Einstein
+    crystal has all N atoms: the fixed centre of mass enters through Eq. cm
+    alone, so n_eff = N there."""
     omega = np.sqrt(k / (mass * MVV2E))          # 1/ps
     return 3.0 * n_eff * KB * T * np.log(HBAR * omega / (KB * T))
 
@@ -61,7 +62,10 @@ def jarzynski(W, T):
 def frenkel_ladd(W_fwd, W_bwd, n_eff, T, k, mass, N=None, V=None):
     """F0 = F_E + (W_{E->0} - W_{0->E})/2 [+ delta F_CM]  (Eq. fl with the forward
     run taking H0 to H_E; the sign follows from Eq. W12 with 1 = H0, 2 = H_E).
-    The fixed-CM term is added when N and V are given."""
+    The fixed-CM term (Eq. cm) is added when N and V are given; F_E then has
+    all n_eff = N oscillators, as Eq. fl writes it: the switching work is
+    that of the two systems with the centre of mass held, and Eq. cm takes
+    the Einstein crystal's value to the free crystal's."""
     dF, ediss, err = forward_backward(W_fwd, W_bwd)   # dF = F_E - F0
     F0 = einstein_free_energy(n_eff, T, k, mass) - dF
     if N is not None and V is not None:
@@ -98,3 +102,36 @@ def reversible_scaling(F0_T0, T0, lambda_f, n_eff, W_fwd_curve, W_bwd_cum, T_gri
     wb_total = W_bwd_cum[-1]
     w2 = wb_total - np.interp((1.0 - tau) * n_sw, q, W_bwd_cum)
     return F0_T0 / lam + 1.5 * n_eff * KB * T0 * np.log(lam) / lam + (w1 - w2) / (2.0 * lam)
+
+
+def thermal_wavelength(T, mass):
+    """de Broglie wavelength Lambda = sqrt(2 pi hbar^2 / (m kB T)) in A, the
+    momentum integral per degree of freedom of the partition function (the
+    Lambda of the partition-function expression in the reversible-scaling
+    section)."""
+    return np.sqrt(2.0 * np.pi * HBAR ** 2 / (mass * MVV2E * KB * T))
+
+
+def free_minus_fixed_cm(N, V, T, mass):
+    """c(T) = F(free crystal) - F(crystal with its centre of mass held):
+    -kB T ln(V/N) + 3 kB T ln Lambda(T).  The held system has 3(N-1) momenta
+    and a configurational integral constrained at one centre-of-mass
+    position; the free crystal integrates that position over the V/N volume
+    per lattice translation and has all 3N momenta.  This is the convention
+    under which Eq. einstein with N oscillators plus Eq. cm is the free
+    crystal's free energy (the Gaussian integrals of the held Einstein crystal
+    give F_E(N) + Eq. cm = F_E(held) + c)."""
+    kT = KB * T
+    return -kT * np.log(V / N) + 3.0 * kT * np.log(thermal_wavelength(T, mass))
+
+
+def reversible_scaling_fixed_cm(F0_T0, T0, lambda_f, N, V, mass, W_fwd_curve, W_bwd_cum, T_grid):
+    """Eq. rs for a run with the centre of mass held (every run here): the run
+    samples the held system, whose free energy Eq. rs maps from T0 to T
+    exactly with its 3(N-1) momenta in the kinetic term; the free crystal's
+    F0(T0) (Eq. fl + Eq. cm) is taken to the held system and back with c:
+      F(T) = rs_{N-1}(F0(T0) - c(T0)) + c(T)."""
+    T_grid = np.asarray(T_grid, dtype=np.float64)
+    held = reversible_scaling(F0_T0 - free_minus_fixed_cm(N, V, T0, mass), T0, lambda_f, N - 1,
+                              W_fwd_curve, W_bwd_cum, T_grid)
+    return held + free_minus_fixed_cm(N, V, T_grid, mass)

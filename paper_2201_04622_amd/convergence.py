@@ -69,7 +69,7 @@ def fl_sweep(ctx, replicas, x0, t_s_list, n_eq, n_hold, dt=0.001, damp=0.1, skin
         W = torch.zeros(len(replicas), S, dtype=torch.float64, device=x.device)
         ctx.run_switching(p, x, v, 0, S, W_out=W)
         Wf, Wb = E.switch_works(p, W.cpu().numpy())
-        n_eff = N - 1 if p.fix_com else N
+        n_eff = N   # Eq. fl: all N oscillators; the held centre of mass enters through Eq. cm
         FE = E.einstein_free_energy(n_eff, r0.T, r0.k, mass)
         cm = E.fixed_cm_correction(N, V, r0.T, r0.k) if p.fix_com else 0.0
         F0, Ed, err = E.fl_free_energy(Wf, Wb, n_eff, r0.T, r0.k, mass, N if p.fix_com else None,

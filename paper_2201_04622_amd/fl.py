@@ -37,7 +37,7 @@ def system_free_energy(p, W_fwd, W_bwd, rep, V=None):
     replica ``rep`` (inputs.Replica) with works W_fwd, W_bwd; ``V`` is the
     volume in Eq. cm (default: the replica's box)."""
     N = rep.natoms
-    n_eff = N - 1 if p.fix_com else N
+    n_eff = N   # Eq. fl: all N oscillators; the held centre of mass enters through Eq. cm
     V = float(np.prod(rep.box)) if V is None else float(V)
     return E.fl_free_energy(np.asarray(W_fwd), np.asarray(W_bwd), n_eff, rep.T, rep.k, rep.mass,
                             N if p.fix_com else None, V if p.fix_com else None)

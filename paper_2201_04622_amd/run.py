@@ -77,7 +77,7 @@ def fl_results(reps, p, W):
     for key, rows in systems.items():
         r0 = reps[rows[0]]
         N = r0.natoms
-        n_eff = N - 1 if p.fix_com else N
+        n_eff = N   # Eq. fl: all N oscillators; the held centre of mass enters through Eq. cm
         V = float(np.prod(r0.box))
         F0, Ed, err = FL.system_free_energy(p, Wf[rows], Wb[rows], r0, V)
         FE = E.einstein_free_energy(n_eff, r0.T, r0.k, r0.mass)
@@ -168,15 +168,14 @@ def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2
         W, stats = _run(ctx, p, x, v, S)
         ctx.close()
         N = reps[0].natoms
-        n_eff = N - 1 if sch.fix_com else N
         Tf = T0 / sch.lambda_f
         grid = np.arange(T0, Tf + 0.5, 1.0)
         if sch.fix_com:   # F0(T0) includes Eq. cm, the run keeps the centre of mass fixed
             V = float(np.prod(reps[0].box))
-            F = np.array([E.rs_free_energy_cm(p, W[q], F0_T0, T0, n_eff, N, V, creps[0].k, grid)
+            F = np.array([E.rs_free_energy_cm(p, W[q], F0_T0, T0, N, V, reps[0].mass, grid)
                           for q in range(len(reps))]) / N
         else:
-            F = np.array([E.rs_free_energy(p, W[q], F0_T0, T0, n_eff, grid) for q in range(len(reps))]) / N
+            F = np.array([E.rs_free_energy(p, W[q], F0_T0, T0, N, grid) for q in range(len(reps))]) / N
         rec["run"] = stats
         rec["companion_fl"] = {"run": fstats, "system": fl_sys[0]}
         rec["T_grid"] = grid.tolist()

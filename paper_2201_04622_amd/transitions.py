@@ -97,7 +97,7 @@ def gibbs_curve(kind, T0, Tf, cells=None, realizations=4, fl_steps=(1000, 16000,
     W = W.cpu().numpy()
     grid = np.arange(T0, Tf + 0.5, 1.0)
     V0 = float(np.prod(rs_reps[0].box))
-    G = np.array([E.rs_free_energy_cm(pr, W[q], G0, T0, N - 1, N, V0, k, grid) for q in range(len(rs_reps))]) / N
+    G = np.array([E.rs_free_energy_cm(pr, W[q], G0, T0, N, V0, rs_reps[0].mass, grid) for q in range(len(rs_reps))]) / N
     err = np.hypot(G.std(axis=0, ddof=1) / np.sqrt(len(G)), G0_err / N * grid / T0)
     return GibbsCurve(kind, a0, k, grid, G.mean(axis=0), err, G0 / N, G0_err / N)
 

@@ -100,28 +100,46 @@ def test_rs_estimator_matches_oracle():
     assert np.abs(got - ref).max() < 1e-10
 
 
-def test_rs_with_fixed_centre_of_mass_is_exact_for_the_einstein_crystal():
-    """Scaling an Einstein crystal (fixed centre of mass, 3 (N - 1) modes) by
-    lambda at T0 costs the reversible work (3 (N - 1) / 2) kB T0 ln(lambda).
-    Fed that work, the fixed-CM form of Eq. rs turns F0(T0) (Eq. einstein plus
-    Eq. cm) into the same closed form at every T of the scan. The plain form,
-    which scales cm(T0) by 1/lambda, misses by (3/2) kB T ln(T/T0)."""
-    KB = 8.617333262e-5
+def test_rs_with_fixed_centre_of_mass_maps_the_held_system_exactly():
+    """Scaling an Einstein crystal with its centre of mass held by lambda at T0
+    costs the reversible work (3 (N - 1) / 2) kB T0 ln(lambda), and the held
+    crystal's free energy is the closed form of its Gaussian integrals,
+      F_held(T) = -kB T [3/2 ln N + 3(N-1)/2 ln(2 pi kB T / k)] + 3 (N-1) kB T ln Lambda(T).
+    Fed that work, plain Eq. rs with N - 1 momenta maps F_held(T0) onto F_held(T);
+    the fixed-centre-of-mass form maps F_held(T0) + c(T0) onto F_held(T) + c(T),
+    c(T) = -kB T ln(V/N) + 3 kB T ln Lambda(T), and agrees with the oracle's."""
+    KB, HBAR, MVV2E = 8.617333262e-5, 6.582119569e-4, 1.0364269e-4
     N, k, m, T0, lf = 432, 20.0, 55.845, 300.0, 0.25
     V = 432 * 7.58
     n_eq, n_sw, n_hold = 10, 2000, 10
     p = E.protocol("rs", n_eq=n_eq, n_sw=n_sw, n_hold=n_hold, n_hold2=0, lambda_f=lf)
     lam = E.lambda_schedule(p)
-    w_rev = 1.5 * (N - 1) * KB * T0 * np.log(lam)           # reversible work from lambda = 1
-    W = w_rev[1:]                                             # cumulative work after each step
-    F0 = E.einstein_free_energy(N - 1, T0, k, m) + E.fixed_cm_correction(N, V, T0, k)
+    W = (1.5 * (N - 1) * KB * T0 * np.log(lam))[1:]           # cumulative reversible work after each step
+
+    def lam_db(t):
+        return np.sqrt(2 * np.pi * HBAR ** 2 / (m * MVV2E * KB * t))
+
+    def held(t):
+        kT = KB * t
+        return -kT * (1.5 * np.log(N) + 1.5 * (N - 1) * np.log(2 * np.pi * kT / k)) + 3 * (N - 1) * kT * np.log(lam_db(t))
+
+    def c(t):
+        return -KB * t * np.log(V / N) + 3 * KB * t * np.log(lam_db(t))
+
     # temperatures on whole steps of the scan, where the work needs no interpolation
     T = T0 + (T0 / lf - T0) * np.array([0, 333, 1000, 1666, n_sw]) / n_sw
-    got = E.rs_free_energy_cm(p, W, F0, T0, N - 1, N, V, k, T)
-    want = np.array([E.einstein_free_energy(N - 1, t, k, m) + E.fixed_cm_correction(N, V, t, k) for t in T])
-    assert np.abs(got - want).max() < 1e-9 * np.abs(want).max()
-    plain = E.rs_free_energy(p, W, F0, T0, N - 1, T)
-    assert np.allclose(plain - got, -1.5 * KB * T * np.log(T / T0), rtol=1e-9, atol=1e-12)
+    plain = E.rs_free_energy(p, W, held(T0), T0, N - 1, T)
+    assert np.abs(plain - held(T)).max() < 1e-9 * np.abs(held(T)).max()
+    got = E.rs_free_energy_cm(p, W, held(T0) + c(T0), T0, N, V, m, T)
+    assert np.abs(got - (held(T) + c(T))).max() < 1e-9 * np.abs(held(T)).max()
+    fw, bw = OE.rs_work_curves(W, n_eq, n_sw, n_hold)
+    ref = OE.reversible_scaling_fixed_cm(held(T0) + c(T0), T0, lf, N, V, m, fw, bw, T)
+    assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+    # the free crystal's F0 of Eq. fl (N oscillators + Eq. cm) is the held value plus c
+    F0 = E.einstein_free_energy(N, T0, k, m) + E.fixed_cm_correction(N, V, T0, k)
+    assert F0 == pytest.approx(held(T0) + c(T0), rel=0, abs=1e-10 * N)
+    with pytest.raises(E.EamfeError):
+        E.rs_free_energy_cm(p, W, 0.0, T0, 1.0, V, m, T)
 
 
 def test_jarzynski_matches_oracle_and_its_invariants():

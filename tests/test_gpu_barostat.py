@@ -121,7 +121,7 @@ def _fl_per_atom(reps, t_s, n_eq, n_hold):
     out = []
     for r, rep in enumerate(reps):
         N = rep.natoms
-        F0, _, _ = E.fl_free_energy(Wf[r:r + 1], Wb[r:r + 1], N - 1, rep.T, rep.k, rep.mass, N=N,
+        F0, _, _ = E.fl_free_energy(Wf[r:r + 1], Wb[r:r + 1], N, rep.T, rep.k, rep.mass, N=N,
                                     V=float(np.prod(rep.box)))
         out.append(F0 / N)
     return np.asarray(out)
@@ -164,7 +164,7 @@ def test_rs_at_zero_pressure_matches_fl_at_the_zero_pressure_volume():
     # Eq. rs in its fixed-centre-of-mass form; the volume in Eq. cm is the one at T0 (at 600 K the box is
     # 0.3 % larger, which moves Eq. cm by 1e-6 eV/atom)
     V0 = float(np.prod(reps[0].box))
-    G = np.array([E.rs_free_energy_cm(p, W[r], F0, T0, N - 1, N, V0, k, np.array([Tf]))[0]
+    G = np.array([E.rs_free_energy_cm(p, W[r], F0, T0, N, V0, reps[0].mass, np.array([Tf]))[0]
                   for r in range(len(reps))]) / N
     a_hot = tr.boxes[n_eq // 10 + n_sw // 10: n_eq // 10 + n_sw // 10 + n_hold // 10, :, 0].mean() / cells[0]
     # the RS estimate inherits F0(T0) / lambda: its error doubles at lambda = 1/2

@@ -156,8 +156,8 @@ def test_fl_free_energy_and_bcc_fcc_difference(gold, stable_runs, prec):
         Wfo = np.array([r["W_fwd"] for r in orc])
         Wbo = np.array([r["W_bwd"] for r in orc])
         # the product's and the oracle's estimators: the same constant part (F_E + dF_CM)
-        Fg, _, _ = E.fl_free_energy(Wf[sl], Wb[sl], N - 1, rep.T, rep.k, rep.mass, N=N, V=float(np.prod(rep.box)))
-        Fo, _, _ = OE.frenkel_ladd(Wfo, Wbo, N - 1, rep.T, rep.k, rep.mass, N=N, V=float(np.prod(rep.box)))
+        Fg, _, _ = E.fl_free_energy(Wf[sl], Wb[sl], N, rep.T, rep.k, rep.mass, N=N, V=float(np.prod(rep.box)))
+        Fo, _, _ = OE.frenkel_ladd(Wfo, Wbo, N, rep.T, rep.k, rep.mass, N=N, V=float(np.prod(rep.box)))
         cg = Fg - _half_diff(Wf[sl], Wb[sl]).mean()
         co = Fo - _half_diff(Wfo, Wbo).mean()
         assert cg == pytest.approx(co, rel=1e-12, abs=1e-9)

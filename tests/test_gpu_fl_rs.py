@@ -36,7 +36,7 @@ def _fl_per_atom(T, seeds, t_s=32000, n_eq=2000, n_hold=2000):
     Wf, Wb = E.switch_works(p, W.cpu().numpy())
     N = reps[0].natoms
     V = float(np.prod(reps[0].box))
-    return np.array([E.fl_free_energy(Wf[r:r + 1], Wb[r:r + 1], N - 1, T, K, reps[0].mass, N=N, V=V)[0]
+    return np.array([E.fl_free_energy(Wf[r:r + 1], Wb[r:r + 1], N, T, K, reps[0].mass, N=N, V=V)[0]
                      for r in range(len(reps))]) / N
 
 
@@ -62,7 +62,7 @@ def test_fl_points_lie_on_the_rs_curve():
     F0 = f0.mean() * N
     grid = np.array(checks)
     V = float(np.prod(reps[0].box))
-    F = np.array([E.rs_free_energy_cm(p, W[r], F0, T0, N - 1, N, V, K, grid) for r in range(len(reps))]) / N
+    F = np.array([E.rs_free_energy_cm(p, W[r], F0, T0, N, V, reps[0].mass, grid) for r in range(len(reps))]) / N
     for q, T in enumerate(checks):
         fl = _fl_per_atom(T, range(100 * q + 100, 100 * q + 108))
         lam = T0 / T

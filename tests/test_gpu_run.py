@@ -38,7 +38,7 @@ def test_runner_record_matches_the_direct_estimate(tmp_path):
     ctx.close()
     Wf, Wb = E.switch_works(p, W.cpu().numpy())
     N = rep.natoms
-    F0, Ed, _ = E.fl_free_energy(Wf, Wb, N - 1, rep.T, rep.k, rep.mass, N=N, V=float(np.prod(rep.box)))
+    F0, Ed, _ = E.fl_free_energy(Wf, Wb, N, rep.T, rep.k, rep.mass, N=N, V=float(np.prod(rep.box)))
     sysrec = rec["systems"][0]
     say(f"runner F0 {sysrec['F0_per_atom']:.8f} eV/atom, direct {F0 / N:.8f}; {rec['run']}")
     assert rec["steps"] == S and rec["atoms"] == N and len(rec["systems"]) == 1
@@ -79,7 +79,7 @@ def test_runner_rs_scan_matches_the_direct_estimate():
     ctx.close()
     Wf, Wb = E.switch_works(pf, Wfl.cpu().numpy())
     V = float(np.prod(reps[0].box))
-    F0, _, _ = E.fl_free_energy(Wf, Wb, N - 1, reps[0].T, reps[0].k, reps[0].mass, N=N, V=V)
+    F0, _, _ = E.fl_free_energy(Wf, Wb, N, reps[0].T, reps[0].k, reps[0].mass, N=N, V=V)
     assert rec["companion_fl"]["system"]["F0_per_atom"] == F0 / N
     ctx, x, v = batch()
     p = E.protocol_from_schedule(sch, skin=0.3)
@@ -87,7 +87,7 @@ def test_runner_rs_scan_matches_the_direct_estimate():
     ctx.run_switching(p, x, v, 0, sch.total_steps, W_out=W)
     ctx.close()
     grid = np.array(rec["T_grid"])
-    F = np.array([E.rs_free_energy_cm(p, W[q].cpu().numpy(), F0, 300.0, N - 1, N, V, reps[0].k, grid)
+    F = np.array([E.rs_free_energy_cm(p, W[q].cpu().numpy(), F0, 300.0, N, V, reps[0].mass, grid)
                   for q in range(len(reps))]) / N
     say(f"runner F(600 K) {rec['F_per_atom'][-1]:.6f} eV/atom, direct {F.mean(axis=0)[-1]:.6f}")
     assert grid[0] == 300.0 and grid[-1] == 600.0 and len(grid) == 301
