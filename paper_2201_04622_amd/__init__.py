@@ -7,7 +7,8 @@ sum of Eq. w_irr.  The compute path is a C-ABI shared library of hand-written
 HIP kernels for gfx950 (``csrc/``, declared in ``include/eamfe.h``); the Python
 side only marshals arguments.
 
-Submodules are imported explicitly (``from paper_2201_04622_amd import api``);
-importing the package itself loads nothing, so the seeded input generators in
-``inputs`` can be used without the native library.
+Submodules are imported explicitly (``import paper_2201_04622_amd.eamfe as E``
+for the binding, ``from paper_2201_04622_amd import inputs`` for the seeded
+input generators); importing the package itself loads nothing, so ``inputs``
+can be used without the native library.
 """

@@ -31,12 +31,16 @@ class EAMEnergy(torch.autograd.Function):
     @staticmethod
     def forward(fctx, theta, x, ctx, r_cut, rho_max):
         th = theta.detach().to("cpu", torch.float64).numpy()
-        ctx.eam_setup(_Knots(th, r_cut, rho_max))
+        knots = _Knots(th, r_cut, rho_max)
+        ctx.eam_setup(knots)
         U = torch.zeros(ctx.n_rep, dtype=torch.float64, device=x.device)
         f = torch.zeros_like(x)
         ctx.eam_forces(x.detach().contiguous(), f, U)
         fctx.save_for_backward(x, f)
         fctx.ctx, fctx.theta_device = ctx, theta.device
+        # dU/dtheta depends on theta itself (through F'(rho_i) and rho_i), so
+        # backward needs this node's tables even if a later forward replaced them
+        fctx.knots, fctx.version = knots, ctx.table_version
         fctx.n = th.shape[1]
         return U
 
@@ -47,7 +51,14 @@ class EAMEnergy(torch.autograd.Function):
         dtheta = None
         if fctx.needs_input_grad[0]:
             d = torch.zeros(3, fctx.n, dtype=torch.float64, device=x.device)
-            ctx.adjoint_theta(x.detach().contiguous(), d, weights=gU.detach().cpu().numpy(), reduce=True)
+            current = ctx.knots if ctx.table_version != fctx.version else None
+            if current is not None:
+                ctx.eam_setup(fctx.knots)      # this node's theta
+            try:
+                ctx.adjoint_theta(x.detach().contiguous(), d, weights=gU.detach().cpu().numpy(), reduce=True)
+            finally:
+                if current is not None:
+                    ctx.eam_setup(current)     # the context keeps the tables it had
             dtheta = d.to(fctx.theta_device)
         dx = None
         if fctx.needs_input_grad[1]:

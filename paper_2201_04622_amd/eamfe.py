@@ -235,6 +235,8 @@ class Context:
         self.n_rep = 0
         self.N = 0
         self.offsets = None
+        self.knots = None          # the knots of the current tables (last eam_setup)
+        self.table_version = 0     # counts eam_setup calls
 
     def close(self):
         if getattr(self, "_h", None):
@@ -365,6 +367,8 @@ class Context:
         F = np.ascontiguousarray(knots.embed, dtype=np.float64)
         self._c(self._lib.eam_setup(self._h, len(phi), float(knots.r_cut), phi.ctypes.data_as(_dp),
                                     rho.ctypes.data_as(_dp), len(F), float(knots.rho_max), F.ctypes.data_as(_dp)))
+        self.knots = knots
+        self.table_version += 1
 
     def system_setup(self, replicas: Sequence, x0_soa):
         """replicas: inputs.Replica list; x0_soa: device float64 [3, N_tot]."""

@@ -159,3 +159,42 @@ def test_autograd_function(knots):
     ref = (g * w[:, None, None]).sum(0).cpu()
     assert torch.allclose(theta.grad, ref, rtol=1e-10, atol=1e-8)
     ctx.close()
+
+
+def test_autograd_two_applies_on_one_context(knots):
+    """Two applies at different theta on one context before one backward
+    (a finite difference U(theta) - U(theta + h u) as a graph): each node's
+    dU/dtheta must be taken with its own tables, as on a fresh context each,
+    and the difference quotient of the energies must match the projected
+    gradient."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    from paper_2201_04622_amd.autograd import EAMEnergy
+    reps = _batch()
+    base = torch.tensor(knots.stacked(), dtype=torch.float64)
+    u = torch.zeros_like(base)
+    u[1] = torch.linspace(0.0, 1.0, base.shape[1]) * 0.02   # a smooth change of the rho knots
+    u[2] = torch.linspace(0.0, 1.0, base.shape[1]) * 0.05   # and of the F knots
+    h = 1e-3
+    ctx, x0, arrs = make_ctx(reps, FP64)
+    xd = E.to_soa(I.displaced(arrs["x0"], 0.05, seed=3))
+    t1 = base.clone().requires_grad_(True)
+    t2 = (base + h * u).requires_grad_(True)
+    w = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device="cuda")
+    U1 = EAMEnergy.apply(t1, xd, ctx, knots.r_cut, knots.rho_max)
+    U2 = EAMEnergy.apply(t2, xd, ctx, knots.r_cut, knots.rho_max)
+    ((U2 - U1) * w).sum().backward()
+    ctx.close()
+    for t, sign in ((t1, -1.0), (t2, 1.0)):
+        c2, _, _ = make_ctx(reps, FP64)
+        t_ref = t.detach().clone().requires_grad_(True)
+        U = EAMEnergy.apply(t_ref, xd, c2, knots.r_cut, knots.rho_max)
+        (sign * U * w).sum().backward()
+        c2.close()
+        assert torch.allclose(t.grad, t_ref.grad, rtol=1e-12, atol=1e-10)
+    # central difference along u against the mean of the two gradients
+    fd = float(((U2 - U1) * w).sum()) / h
+    proj = 0.5 * float(((-t1.grad + t2.grad) * u).sum())
+    say(f"two applies: FD {fd:.8e}, adjoint projection {proj:.8e}")
+    assert abs(fd - proj) < 1e-6 * abs(fd) + 1e-9
