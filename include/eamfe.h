@@ -19,11 +19,18 @@
  *   - "device" pointers are HIP device memory owned by the caller (for
  *     example a torch tensor's data_ptr()); "host" pointers are ordinary
  *     memory read or written before the call returns.  The library never
- *     frees caller memory.  Internal work buffers (neighbour lists, cell
- *     bins, tables, partial sums) are allocated by the library in
- *     eam_setup / eamfe_system_setup / neigh_build and freed by
- *     eamfe_destroy; the stepping calls allocate only when a larger lambda
- *     table than any before is needed.
+ *     frees caller memory.
+ *   - Internal device buffers (neighbour lists, cell bins, tables, packed
+ *     positions, partial sums, the lambda table, snapshots) live in one
+ *     arena.  Once the caller hands over a workspace (eamfe_set_workspace)
+ *     the arena is the caller's memory and the library allocates nothing on
+ *     the device: a call that needs more (a larger system, longer rows after
+ *     an overflow, a longer lambda table) returns EAMFE_ENOMEM without
+ *     effect, eamfe_workspace_bytes gives the size it needs, and the caller
+ *     passes a larger workspace and repeats the call (an interrupted
+ *     run_switching resumes at eamfe_resume_step).  Without a workspace the
+ *     library allocates its own arena in the setup calls and grows it
+ *     there, and frees it in eamfe_destroy.
  *   - Positions, velocities and forces are SoA float64 [3][N_tot]
  *     (x of all atoms, then y, then z); replicas are stored back to back in
  *     the order given to eamfe_system_setup.  Positions are unwrapped
@@ -107,11 +114,41 @@ typedef struct eamfe_protocol {
 
 /* Create a context on HIP device `device`, issuing work on `hip_stream`
  * (a hipStream_t; NULL = the legacy default stream).  precision is
- * EAMFE_FP64 or EAMFE_FP32.  *ctx is set on success. */
-int eamfe_create(eamfe_ctx** ctx, int device, void* hip_stream, int precision);
+ * EAMFE_FP64 or EAMFE_FP32.  deterministic (EAMFE_FP32 only; 0 or 1): 1
+ * rounds every float32 partial sum of four list slots to the 2^-32 grid and
+ * adds it exactly (results bitwise reproducible and independent of the
+ * launch shape, the precision form the method's work integral is stated
+ * for); 0 adds the float32 partials in float64 as they are (bitwise
+ * reproducible run to run for one launch shape, not across shapes).
+ * No device memory is taken here.  *ctx is set on success. */
+int eamfe_create(eamfe_ctx** ctx, int device, void* hip_stream, int precision, int deterministic);
 
-/* Free every library-owned buffer.  NULL is accepted. */
+/* Free the library's own arena (never a caller's workspace).  NULL is accepted. */
 int eamfe_destroy(eamfe_ctx* ctx);
+
+/* Device bytes the context's buffers need now, or, after a call returned
+ * EAMFE_ENOMEM for want of workspace, the bytes that call needs. */
+int eamfe_workspace_bytes(const eamfe_ctx* ctx, size_t* bytes);
+
+/* Hand the context a device workspace `dev` of `bytes` bytes (256-byte
+ * aligned; for example a torch uint8 tensor's data_ptr()), owned by the
+ * caller and kept valid until the next eamfe_set_workspace or
+ * eamfe_destroy.  The current buffers are copied into it (the stream is
+ * synchronised first), after which the previous workspace may be freed by
+ * its owner.  From then on the library allocates no device memory.
+ * dev = NULL with bytes = 0 selects caller-owned memory before any setup.
+ * EAMFE_ENOMEM if bytes is less than eamfe_workspace_bytes reports. */
+int eamfe_set_workspace(eamfe_ctx* ctx, void* dev, size_t bytes);
+
+/* After run_switching (or switch_step) returned EAMFE_ENOMEM: the step at
+ * which it stopped, with x, v and the carried work the state at that step;
+ * calling run_switching again from there (after a larger workspace) continues
+ * bitwise as the uninterrupted run.  -1 if no run was interrupted. */
+int eamfe_resume_step(const eamfe_ctx* ctx, int64_t* step);
+
+/* Device allocations the library made itself (hipMalloc calls); stays 0 for
+ * a context given a workspace before its first setup call. */
+int eamfe_device_allocations(const eamfe_ctx* ctx, int64_t* n);
 
 /* Text of the last error of this context (static storage inside ctx). */
 const char* eamfe_last_error(const eamfe_ctx* ctx);

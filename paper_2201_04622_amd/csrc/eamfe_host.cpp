@@ -28,10 +28,28 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Sizes that fix the layout of a context's device memory.
+struct Shape {
+    long N = 0;            // atoms
+    long n_rep = 0;        // replicas
+    long max_units = 0;    // work units at the finest launch shape (64/16 atoms per unit)
+    long max_slices = 0;   // blocks of a staged pair launch, at most
+    long n_r = 0, n_rho = 0;
+    long cap = 0, n_cells = 0, ccap = 0;
+    long lam_len = 0;      // entries of the lambda table
+};
+
+// Buffer groups of the arena, in layout order.  A group that changes size
+// moves only the groups after it, and those hold contents that are rebuilt
+// from host copies (tables, lambda table), rebuilt by the kernels (lists) or
+// scratch (adjoint bins).
+enum Group : int { G_CORE = 0, G_SYS, G_TAB, G_LIST, G_LAM, G_ADJ, G_COUNT };
+
 struct eamfe_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = EAMFE_FP64;
+    int deterministic = 1;   // FP32: 2^-32 fixed-point per-atom sums (shape-independent bits)
     int lanes = 4;
     int block = 256;
     int grid = 0;      // persistent pair-kernel blocks (0: every resident slot), a multiple of 8
@@ -110,6 +128,16 @@ struct eamfe_ctx {
     // lambda table
     DevBuf lam_d;
 
+    // device memory: one arena holding every buffer above, laid out by `shape`
+    Shape shape;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    bool caller_ws = false;     // the arena is the caller's (eamfe_set_workspace): never allocate
+    size_t need = 0;            // bytes the last call that ran out of workspace needed
+    int64_t resume_step = -1;   // where an interrupted run_switching stopped (-1: none)
+    int64_t device_allocs = 0;  // hipMalloc calls made by the library
+    long cap_min = 0;           // row capacity asked for after an overflow (kept across re-plans)
+
     long n_atoms_total() const { return N; }
     std::vector<double> lam_h;
     eamfe_protocol lam_key{};
@@ -140,33 +168,158 @@ int fail(eamfe_ctx* c, int code, const std::string& msg)
                                                 hipGetErrorString((hipError_t)e_));            \
     } while (0)
 
-void release(DevBuf& b)
-{
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-}
-
-// (Re)allocate to at least `bytes`; contents are not preserved.
-int ensure(eamfe_ctx* c, DevBuf& b, size_t bytes)
-{
-    if (bytes == 0) bytes = 8;
-    if (b.p && b.bytes >= bytes) return EAMFE_OK;
-    release(b);
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        return fail(c, EAMFE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    b.bytes = bytes;
-    return EAMFE_OK;
-}
-
 #define OK(expr)                        \
     do {                                \
         int r_ = (expr);                \
         if (r_ != EAMFE_OK) return r_;  \
     } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// Every device buffer of a context with the group it belongs to and its size
+// under shape s, in layout order.
+template <typename F>
+void for_regions(eamfe_ctx* c, const Shape& s, F&& f)
+{
+    const size_t N = (size_t)s.N, R = (size_t)s.n_rep, U = (size_t)s.max_units, d = sizeof(double);
+    const size_t real = c->precision == EAMFE_FP32 ? 4 : 8;
+    if (N || s.n_r) {
+        f(c->status_d, G_CORE, sizeof(int32_t));
+        f(c->iter_d, G_CORE, sizeof(int64_t));
+        f(c->pending_d, G_CORE, sizeof(int32_t));
+        f(c->stats_d, G_CORE, 2 * sizeof(unsigned long long));
+    }
+    if (N) {
+        f(c->reps_d, G_SYS, R * sizeof(RepDesc));
+        f(c->tiles_d, G_SYS, U * sizeof(Tile));
+        f(c->slices_d, G_SYS, (size_t)s.max_slices * sizeof(int4));
+        f(c->noise_part_d, G_SYS, U * 3 * d);
+        f(c->energy_part_d, G_SYS, U * 3 * d);
+        f(c->vir_d, G_SYS, U * 3 * d);
+        f(c->rep_of_d, G_SYS, N * sizeof(int32_t));
+        f(c->x0_d, G_SYS, 3 * N * d);
+        f(c->xref_d, G_SYS, 3 * N * d);
+        f(c->Pa_d, G_SYS, N * sizeof(double4));
+        f(c->Pb_d, G_SYS, N * sizeof(double4));
+        f(c->Qa_d, G_SYS, N * sizeof(uint4));
+        f(c->Qb_d, G_SYS, N * sizeof(uint4));
+        f(c->e_emb_d, G_SYS, N * d);
+        f(c->xi_d, G_SYS, 3 * N * d);
+        f(c->rho_d, G_SYS, N * d);
+        f(c->kscale_d, G_SYS, N * d);
+        f(c->U_rep_d, G_SYS, 2 * R * d);
+        f(c->W_state_d, G_SYS, R * d);
+        f(c->rebuild_d, G_SYS, R * sizeof(int32_t));
+        f(c->flag_pre_d, G_SYS, (2 * R + 2) * sizeof(int32_t));
+        f(c->row_acc_d, G_SYS, (R + 3) * d);
+        f(c->msd_d, G_SYS, R * d);
+        f(c->mu_d, G_SYS, 3 * R * d);
+        f(c->adj_w_d, G_SYS, R * d);
+        f(c->tune_x, G_SYS, 3 * N * d);
+        f(c->tune_v, G_SYS, 3 * N * d);
+        f(c->tune_w, G_SYS, R * d);
+        f(c->snap_P, G_SYS, N * sizeof(double4));
+        f(c->snap_Q, G_SYS, N * sizeof(uint4));
+        f(c->snap_v, G_SYS, 3 * N * d);
+        f(c->snap_w, G_SYS, R * d);
+        f(c->snap_rows, G_SYS, (R + 3) * d);
+    }
+    if (s.n_r) {
+        f(c->tab_pair, G_TAB, 8 * (size_t)(s.n_r - 1) * real);
+        f(c->tab_rho, G_TAB, 4 * (size_t)(s.n_r - 1) * real);
+        f(c->tab_F, G_TAB, 4 * (size_t)(s.n_rho - 1) * real);
+    }
+    if (N && s.cap) {
+        const size_t nc = (size_t)std::max(1L, s.n_cells);
+        f(c->nbr_d, G_LIST, N * (size_t)s.cap * sizeof(int32_t));
+        f(c->nnb_d, G_LIST, N * sizeof(int32_t));
+        f(c->cell_cnt_d, G_LIST, nc * sizeof(int32_t));
+        f(c->cell_atoms_d, G_LIST, nc * (size_t)s.ccap * sizeof(int32_t));
+        f(c->cell_rep_d, G_LIST, nc * sizeof(int32_t));
+    }
+    if (s.lam_len) f(c->lam_d, G_LAM, (size_t)s.lam_len * d);
+    if (N && s.n_r) {
+        const size_t nb = (size_t)std::max(s.n_r, s.n_rho) - 1;
+        f(c->bins_d, G_ADJ, R * 3 * nb * 4 * sizeof(unsigned long long));
+        f(c->adj_scratch_d, G_ADJ, R * 3 * 2 * (nb + 1) * d);
+    }
+}
+
+size_t layout_bytes(eamfe_ctx* c, const Shape& s)
+{
+    size_t off = 0;
+    for_regions(c, s, [&](DevBuf&, int, size_t b) { off += align_up(b); });
+    return off;
+}
+
+int upload_tables(eamfe_ctx* c);   // below
+void drop_graphs(eamfe_ctx* c);     // below
+
+// Make the arena hold the layout of shape s and point every buffer into it.
+// Contents keep their offsets when the arena is replaced (the live layout is
+// copied over); groups whose offset changes are rebuilt here (tables and the
+// lambda table from their host copies) or by their owners (lists are planned
+// and rebuilt by the caller that changed a group before them; adjoint bins
+// are scratch).  With a caller's workspace that is too small nothing
+// changes: EAMFE_ENOMEM, and `need` holds the bytes required.
+int bind(eamfe_ctx* c, const Shape& s)
+{
+    const size_t need = layout_bytes(c, s);
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // no pass in flight uses the old layout
+    if (need > c->arena_bytes) {
+        if (c->caller_ws) {
+            c->need = need;
+            return fail(c, EAMFE_ENOMEM, "workspace of " + std::to_string(c->arena_bytes) + " bytes is too small: " +
+                                             std::to_string(need) + " needed (eamfe_workspace_bytes)");
+        }
+        const size_t grow = need + need / 4;
+        void* p = nullptr;
+        ++c->device_allocs;
+        const hipError_t e = hipMalloc(&p, grow);
+        if (e != hipSuccess) return fail(c, EAMFE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        if (c->arena) {
+            const size_t used = layout_bytes(c, c->shape);
+            HIPCHK(c, hipMemcpy(p, c->arena, used, hipMemcpyDeviceToDevice));
+            (void)hipFree(c->arena);
+        }
+        c->arena = (char*)p;
+        c->arena_bytes = grow;
+    }
+    size_t old_off[G_COUNT], new_off[G_COUNT], old_len[G_COUNT], new_len[G_COUNT];
+    for (int g = 0; g < G_COUNT; ++g) old_off[g] = new_off[g] = old_len[g] = new_len[g] = 0;
+    {
+        size_t off = 0;
+        int last = -1;
+        for_regions(c, c->shape, [&](DevBuf&, int g, size_t b) {
+            if (g != last) old_off[g] = off, last = g;
+            old_len[g] += align_up(b);
+            off += align_up(b);
+        });
+        off = 0;
+        last = -1;
+        for_regions(c, s, [&](DevBuf& buf, int g, size_t b) {
+            if (g != last) new_off[g] = off, last = g;
+            new_len[g] += align_up(b);
+            buf.p = c->arena + off;
+            buf.bytes = b;
+            off += align_up(b);
+        });
+    }
+    const Shape old = c->shape;
+    c->shape = s;
+    c->need = 0;
+    drop_graphs(c);   // captured launches hold buffer addresses
+    if (new_len[G_CORE] && !old_len[G_CORE]) HIPCHK(c, hipMemset(c->status_d.p, 0, new_len[G_CORE]));
+    const bool tab_moved = old_off[G_TAB] != new_off[G_TAB] || old_len[G_TAB] != new_len[G_TAB];
+    const bool lam_moved = old_off[G_LAM] != new_off[G_LAM] || old_len[G_LAM] != new_len[G_LAM];
+    if (tab_moved && c->have_pot && s.n_r == old.n_r && s.n_rho == old.n_rho) OK(upload_tables(c));
+    if (lam_moved && c->lam_valid && s.lam_len == old.lam_len)
+        HIPCHK(c, hipMemcpy(c->lam_d.p, c->lam_h.data(), c->lam_h.size() * sizeof(double), hipMemcpyHostToDevice));
+    return EAMFE_OK;
+}
+
 
 // Natural cubic spline on x_k = k h through y[0..n-1] -> [n-1][4] (a, b, c, d)
 // with s(t) = a + t(b + t(c + t d)) on interval m, t = x/h - m.  The second
@@ -209,13 +362,15 @@ int upload_tables_t(eamfe_ctx* c)
     }
     for (int m = 0; m < mf; ++m)
         for (int q = 0; q < 4; ++q) F[4 * m + q] = (real)c->c_F[4 * m + q];
-    OK(ensure(c, c->tab_pair, pair.size() * sizeof(real)));
-    OK(ensure(c, c->tab_rho, rho.size() * sizeof(real)));
-    OK(ensure(c, c->tab_F, F.size() * sizeof(real)));
     HIPCHK(c, hipMemcpy(c->tab_pair.p, pair.data(), pair.size() * sizeof(real), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->tab_rho.p, rho.data(), rho.size() * sizeof(real), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->tab_F.p, F.data(), F.size() * sizeof(real), hipMemcpyHostToDevice));
     return EAMFE_OK;
+}
+
+int upload_tables(eamfe_ctx* c)
+{
+    return c->precision == EAMFE_FP32 ? upload_tables_t<float>(c) : upload_tables_t<double>(c);
 }
 
 Tables tables_of(const eamfe_ctx* c)
@@ -336,16 +491,13 @@ int build_tiles(eamfe_ctx* c)
         c->qoff[1] = (int)c->tiles.size();
         c->nq = 1;
     }
-    OK(ensure(c, c->tiles_d, std::max<size_t>(1, c->tiles.size()) * sizeof(Tile)));
+    if ((long)c->tiles.size() > c->shape.max_units) return fail(c, EAMFE_EINVAL, "internal: unit table overflow");
     if (!c->tiles.empty())
         HIPCHK(c, hipMemcpy(c->tiles_d.p, c->tiles.data(), c->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
     build_slices(c);
-    OK(ensure(c, c->slices_d, std::max<size_t>(1, c->slices.size()) * sizeof(int4)));
+    if ((long)c->slices.size() > c->shape.max_slices) return fail(c, EAMFE_EINVAL, "internal: slice table overflow");
     if (!c->slices.empty())
         HIPCHK(c, hipMemcpy(c->slices_d.p, c->slices.data(), c->slices.size() * sizeof(int4), hipMemcpyHostToDevice));
-    OK(ensure(c, c->noise_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
-    OK(ensure(c, c->energy_part_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
-    OK(ensure(c, c->reps_d, c->reps.size() * sizeof(RepDesc)));
     HIPCHK(c, hipMemcpy(c->reps_d.p, c->reps.data(), c->reps.size() * sizeof(RepDesc), hipMemcpyHostToDevice));
     return EAMFE_OK;
 }
@@ -442,18 +594,24 @@ StepArgs step_args(eamfe_ctx* c)
                        ? (int)c->slices.size()
                        : 0;
     a.half_skin2 = 0.25 * c->skin * c->skin;
+    a.fix = c->deterministic;
     return a;
 }
 
-// Neighbour-list geometry for the current system and skin.
+// Neighbour-list geometry for the current system and skin.  max_neighbors
+// > 0 fixes the row capacity (rounded up to a multiple of 32); 0 takes an
+// estimate from the densest replica, at least the capacity an earlier
+// overflow asked for (cap_min).  Nothing changes if the lists do not fit the
+// workspace.
 int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
 {
     const double rl = c->r_cut + skin;
     double dens_max = 0.0, cellvol_max = 0.0;
     int n_cells = 0;
     std::vector<int32_t> cell_rep;
+    std::vector<RepDesc> reps = c->reps;
     for (int r = 0; r < c->n_rep; ++r) {
-        RepDesc& R = c->reps[r];
+        RepDesc& R = reps[r];
         double V = R.L[0] * R.L[1] * R.L[2];
         for (int d = 0; d < 3; ++d)
             if (!(R.L[d] > 2.0 * rl))
@@ -480,20 +638,24 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
         }
     }
     // mean occupancy of the fullest cells, with room for clustering
-    c->ccap = std::max({32, c->min_ccap, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32});
-    if (max_neighbors <= 0) {
+    const int ccap = std::max({32, c->min_ccap, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32});
+    int cap;
+    if (max_neighbors > 0) {
+        cap = (max_neighbors + 31) / 32 * 32;   // rows are read four slots at a time, 16-byte aligned
+    } else {
         const double nmean = 4.0 / 3.0 * M_PI * rl * rl * rl * dens_max;
-        max_neighbors = (int)(std::ceil((nmean * 2.0 + 32.0) / 32.0) * 32.0);
+        cap = std::max((int)(std::ceil((nmean * 2.0 + 32.0) / 32.0) * 32.0), (int)c->cap_min);
     }
-    // rows are read four slots at a time from 16-byte aligned addresses
-    c->cap = (max_neighbors + 31) / 32 * 32;
+    Shape s2 = c->shape;
+    s2.cap = cap;
+    s2.n_cells = n_cells;
+    s2.ccap = ccap;
+    OK(bind(c, s2));
+    c->reps = reps;
+    c->ccap = ccap;
+    c->cap = cap;
     c->n_cells = n_cells;
     c->skin = skin;
-    OK(ensure(c, c->nbr_d, (size_t)c->N * c->cap * sizeof(int32_t)));
-    OK(ensure(c, c->nnb_d, (size_t)c->N * sizeof(int32_t)));
-    OK(ensure(c, c->cell_cnt_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
-    OK(ensure(c, c->cell_atoms_d, (size_t)std::max(1, n_cells) * c->ccap * sizeof(int32_t)));
-    OK(ensure(c, c->cell_rep_d, (size_t)std::max(1, n_cells) * sizeof(int32_t)));
     HIPCHK(c, hipMemsetAsync(c->cell_cnt_d.p, 0, (size_t)std::max(1, n_cells) * sizeof(int32_t), c->stream));
     HIPCHK(c, hipMemsetAsync(c->nnb_d.p, 0, (size_t)c->N * sizeof(int32_t), c->stream));
     if (n_cells)
@@ -501,6 +663,16 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
                             hipMemcpyHostToDevice));
     OK(upload_reps(c));
     return EAMFE_OK;
+}
+
+// Row or bin overflow seen (status bits st): ask for larger rows or bins and
+// plan the lists again (EAMFE_ENOMEM if they do not fit the workspace).
+int grow_lists(eamfe_ctx* c, int st)
+{
+    const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
+    if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
+    c->cap_min = std::max<long>(c->cap_min, new_cap);
+    return plan_lists(c, c->skin, new_cap);
 }
 
 int status_code(int st)
@@ -515,6 +687,7 @@ int status_code(int st)
 int read_status(eamfe_ctx* c)
 {
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->status_d.p) return EAMFE_OK;   // no device state yet
     int st = 0;
     HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
     if (st) {
@@ -585,9 +758,15 @@ int ensure_lambda(eamfe_ctx* c, const eamfe_protocol* p, int64_t* S_out)
     int64_t S = 0;
     OK(eamfe_lambda_schedule(p, nullptr, &S));
     if (!c->lam_valid || !proto_equal(c->lam_key, *p)) {
+        if (S + 1 > c->shape.lam_len) {   // a longer table than any before: a larger region
+            Shape s2 = c->shape;
+            s2.lam_len = S + 1;
+            c->lam_valid = false;
+            OK(bind(c, s2));
+        }
         c->lam_h.assign(S + 1, 0.0);
         OK(eamfe_lambda_schedule(p, c->lam_h.data(), &S));
-        OK(ensure(c, c->lam_d, (S + 1) * sizeof(double)));
+        HIPCHK(c, hipStreamSynchronize(c->stream));   // earlier passes may still read the old table
         HIPCHK(c, hipMemcpy(c->lam_d.p, c->lam_h.data(), (S + 1) * sizeof(double), hipMemcpyHostToDevice));
         c->lam_key = *p;
         c->lam_valid = true;
@@ -639,14 +818,15 @@ int pack(eamfe_ctx* c, const double* x)
 
 // dU/dtheta at the packed positions P (density pass already run with
 // rho_out, so F' and rho are current): bins -> knot gradients into out.
-int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce, double* out)
+// bins: n_rep * 3 * nb * 4 fixed-point words; fin: the knot transform's
+// work rows, (reduce ? 1 : n_rep) * 3 * 2 * (nb + 1) doubles.
+int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce, double* out,
+               unsigned long long* bins_p, double* fin_p)
 {
     if (c->n_r != c->n_rho) return fail(c, EAMFE_EINVAL, "adjoint: phi/rho and F tables must have equal knot counts");
     const int nb = std::max(c->n_r, c->n_rho) - 1;
-    const size_t bins = (size_t)c->n_rep * 3 * nb * 4 * sizeof(unsigned long long);
-    OK(ensure(c, c->bins_d, bins));
-    OK(ensure(c, c->adj_scratch_d, (size_t)c->n_rep * 3 * 2 * (nb + 1) * sizeof(double)));
-    HIPCHK(c, hipMemsetAsync(c->bins_d.p, 0, bins, c->stream));
+    const size_t bins = (size_t)c->n_rep * 3 * nb * 4;
+    LCHK(c, launch_fill_u64(bins_p, bins, 0ull, c->stream));   // a fill kernel: capturable, unlike a memset
     AdjointArgs a{};
     a.reps = (const RepDesc*)c->reps_d.p;
     a.P = P;
@@ -655,7 +835,7 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
     a.nnb = (const int32_t*)c->nnb_d.p;
     a.cap = c->cap;
     a.rho = (const double*)c->rho_d.p;
-    a.bins = (unsigned long long*)c->bins_d.p;
+    a.bins = bins_p;
     a.nb = nb;
     a.tab = tables_of(c);
     a.N = c->N;
@@ -666,13 +846,12 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
     LCHK(c, launch_adjoint(a, c->precision, grid, c->stream));
     const double* wd = nullptr;
     if (w_host) {
-        OK(ensure(c, c->adj_w_d, (size_t)c->n_rep * sizeof(double)));
         HIPCHK(c, hipMemcpyAsync(c->adj_w_d.p, w_host, (size_t)c->n_rep * sizeof(double), hipMemcpyHostToDevice,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));   // the host array may go away
         wd = (const double*)c->adj_w_d.p;
     }
-    LCHK(c, launch_adjoint_finish(a, wd, reduce, out, (double*)c->adj_scratch_d.p, c->stream));
+    LCHK(c, launch_adjoint_finish(a, wd, reduce, out, fin_p, c->stream));
     return EAMFE_OK;
 }
 
@@ -720,7 +899,8 @@ int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool ha
     LCHK(c, launch_density(a, c->precision, c->lanes, c->block, st));
     OK(mark(c, 0, 1));
     if (sample) {
-        OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out));
+        OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out,
+                      (unsigned long long*)c->bins_d.p, (double*)c->adj_scratch_d.p));
         ++c->adj_samples;
     }
     OK(mark(c, 1, 0));
@@ -811,6 +991,28 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
     return EAMFE_OK;
 }
 
+bool ready(eamfe_ctx* c, bool need_pot);
+
+// dU/dtheta at positions x with the adjoint's bins and knot-transform rows
+// at the given device addresses.
+int adjoint_theta_with(eamfe_ctx* c, const double* x, const double* w_host, int reduce, double* dtheta,
+                       unsigned long long* bins, double* fin)
+{
+    OK(pack(c, x));
+    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
+    NeighArgs na = neigh_args(c, PA(c));
+    LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
+    StepArgs a = step_args(c);
+    a.P = PA(c);
+    a.Q = QA(c);
+    a.has_eam = 1;
+    a.step_kernel = 0;
+    a.rho_out = (double*)c->rho_d.p;
+    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+    OK(adjoint_at(c, PA(c), w_host, reduce, dtheta, bins, fin));
+    return read_status(c);
+}
+
 bool ready(eamfe_ctx* c, bool need_pot)
 {
     if (!c) return false;
@@ -832,9 +1034,10 @@ bool ready(eamfe_ctx* c, bool need_pot)
 // ===========================================================================
 extern "C" {
 
-int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
+int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision, int deterministic)
 {
-    if (!out || (precision != EAMFE_FP64 && precision != EAMFE_FP32)) return EAMFE_EINVAL;
+    if (!out || (precision != EAMFE_FP64 && precision != EAMFE_FP32) || (deterministic != 0 && deterministic != 1))
+        return EAMFE_EINVAL;
     *out = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EAMFE_EDEVICE;
@@ -844,6 +1047,7 @@ int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->precision = precision;
+    c->deterministic = deterministic;
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
@@ -852,17 +1056,7 @@ int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision)
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
             c->max_lds = lds;
     }
-    int r = EAMFE_OK;
-    if ((r = ensure(c, c->iter_d, sizeof(int64_t))) ||
-        (r = ensure(c, c->status_d, sizeof(int32_t)))) {
-        eamfe_destroy(c);
-        return r;
-    }
-    if (hipMemset(c->status_d.p, 0, sizeof(int32_t)) != hipSuccess) {
-        eamfe_destroy(c);
-        return EAMFE_EDEVICE;
-    }
-    *out = c;
+    *out = c;   // no device memory yet: the first setup call lays out the arena
     return EAMFE_OK;
 }
 
@@ -872,30 +1066,63 @@ int eamfe_destroy(eamfe_ctx* c)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&c->tab_pair, &c->tab_rho, &c->tab_F, &c->reps_d, &c->tiles_d, &c->rep_of_d, &c->x0_d,
-                      &c->xref_d, &c->Pa_d, &c->Pb_d, &c->Qa_d, &c->Qb_d, &c->e_emb_d, &c->xi_d, &c->noise_part_d,
-                      &c->energy_part_d, &c->U_rep_d, &c->W_state_d, &c->iter_d, &c->rebuild_d, &c->flag_pre_d, &c->pending_d, &c->status_d, &c->slices_d, &c->row_acc_d, &c->msd_d, &c->kscale_d, &c->vir_d, &c->mu_d, &c->nbr_d,
-                      &c->nnb_d, &c->cell_cnt_d, &c->cell_atoms_d, &c->cell_rep_d, &c->lam_d};
-    for (DevBuf* b : bufs) release(*b);
-    release(c->stats_d);
-    release(c->rho_d);
-    release(c->bins_d);
-    release(c->adj_scratch_d);
-    release(c->adj_w_d);
-    release(c->tune_x);
-    release(c->tune_v);
-    release(c->tune_w);
-    release(c->snap_P);
-    release(c->snap_Q);
-    release(c->snap_v);
-    release(c->snap_w);
-    release(c->snap_rows);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     drop_graphs(c);
     if (c->ev_user) (void)hipEventDestroy(c->ev_user);
     if (c->ev_graph) (void)hipEventDestroy(c->ev_graph);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->arena && !c->caller_ws) (void)hipFree(c->arena);   // never the caller's workspace
     delete c;
+    return EAMFE_OK;
+}
+
+int eamfe_workspace_bytes(const eamfe_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return EAMFE_EINVAL;
+    const size_t cur = layout_bytes(const_cast<eamfe_ctx*>(c), c->shape);
+    *bytes = std::max(cur, c->need);
+    return EAMFE_OK;
+}
+
+int eamfe_set_workspace(eamfe_ctx* c, void* dev, size_t bytes)
+{
+    if (!c || (bytes && !dev)) return EAMFE_EINVAL;
+    if ((uintptr_t)dev % kAlign) return fail(c, EAMFE_EINVAL, "set_workspace: the workspace must be 256-byte aligned");
+    const size_t used = layout_bytes(c, c->shape);
+    if (bytes < used) {
+        c->need = std::max(c->need, used);
+        return fail(c, EAMFE_ENOMEM, "set_workspace: " + std::to_string(used) + " bytes needed");
+    }
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // every live buffer keeps its offset: one copy moves them all
+    if (c->arena && used && (char*)dev != c->arena)
+        HIPCHK(c, hipMemcpy(dev, c->arena, used, hipMemcpyDeviceToDevice));
+    if (c->arena && !c->caller_ws) (void)hipFree(c->arena);
+    c->arena = (char*)dev;
+    c->arena_bytes = bytes;
+    c->caller_ws = true;
+    size_t off = 0;
+    for_regions(c, c->shape, [&](DevBuf& b, int, size_t n) {
+        b.p = c->arena + off;
+        b.bytes = n;
+        off += align_up(n);
+    });
+    drop_graphs(c);
+    return EAMFE_OK;
+}
+
+int eamfe_resume_step(const eamfe_ctx* c, int64_t* step)
+{
+    if (!c || !step) return EAMFE_EINVAL;
+    *step = c->resume_step;
+    return EAMFE_OK;
+}
+
+int eamfe_device_allocations(const eamfe_ctx* c, int64_t* n)
+{
+    if (!c || !n) return EAMFE_EINVAL;
+    *n = c->device_allocs;
     return EAMFE_OK;
 }
 
@@ -988,6 +1215,10 @@ int eam_setup(eamfe_ctx* c, int n_r, double r_cut, const double* phi, const doub
         return fail(c, EAMFE_EINVAL, "eam_setup: bad table description");
     (void)hipSetDevice(c->device);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    Shape s2 = c->shape;
+    s2.n_r = n_r;
+    s2.n_rho = n_rho;
+    OK(bind(c, s2));   // nothing changes if the tables do not fit
     c->n_r = n_r;
     c->n_rho = n_rho;
     c->r_cut = r_cut;
@@ -998,7 +1229,7 @@ int eam_setup(eamfe_ctx* c, int n_r, double r_cut, const double* phi, const doub
     c->c_phi = natural_spline(phi, n_r, r_cut / (n_r - 1));
     c->c_rho = natural_spline(rho, n_r, r_cut / (n_r - 1));
     c->c_F = natural_spline(F, n_rho, rho_max / (n_rho - 1));
-    OK(c->precision == EAMFE_FP32 ? upload_tables_t<float>(c) : upload_tables_t<double>(c));
+    OK(upload_tables(c));
     c->have_pot = true;
     c->have_list = false;   // the cutoff may have changed
     return EAMFE_OK;
@@ -1020,6 +1251,17 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
         N += q.n_atoms;
     }
     if (N >= (1L << 28)) return fail(c, EAMFE_EINVAL, "too many atoms (at most 2^28 - 1)");
+    Shape s2 = c->shape;
+    s2.N = N;
+    s2.n_rep = n_rep;
+    s2.max_units = 0;   // units of 64/16 atoms, the finest launch shape
+    for (int r = 0; r < n_rep; ++r) s2.max_units += (in[r].n_atoms + 3) / 4;
+    s2.max_slices = 8L * std::max<long>(n_rep, c->n_cu);
+    s2.cap = s2.n_cells = s2.ccap = 0;   // lists are planned for the new system
+    OK(bind(c, s2));   // nothing changes if the system does not fit
+    c->have_list = false;
+    c->cap_min = 0;
+    c->min_ccap = 0;
     c->n_rep = n_rep;
     c->N = (int)N;
     c->reps_in.assign(in, in + n_rep);
@@ -1047,22 +1289,6 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
         off += q.n_atoms;
     }
     const size_t v3 = 3 * (size_t)N * sizeof(double);
-    OK(ensure(c, c->x0_d, v3));
-    OK(ensure(c, c->xref_d, v3));
-    OK(ensure(c, c->Pa_d, (size_t)N * sizeof(double4)));
-    OK(ensure(c, c->Qa_d, (size_t)N * sizeof(uint4)));
-    OK(ensure(c, c->Qb_d, (size_t)N * sizeof(uint4)));
-    OK(ensure(c, c->rho_d, (size_t)N * sizeof(double)));
-    OK(ensure(c, c->Pb_d, (size_t)N * sizeof(double4)));
-    OK(ensure(c, c->xi_d, v3));
-    OK(ensure(c, c->e_emb_d, (size_t)N * sizeof(double)));
-    OK(ensure(c, c->rep_of_d, (size_t)N * sizeof(int32_t)));
-    OK(ensure(c, c->U_rep_d, (size_t)n_rep * 2 * sizeof(double)));
-    OK(ensure(c, c->W_state_d, (size_t)n_rep * sizeof(double)));
-    OK(ensure(c, c->rebuild_d, (size_t)n_rep * sizeof(int32_t)));
-    OK(ensure(c, c->flag_pre_d, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
-    OK(ensure(c, c->pending_d, sizeof(int32_t)));
-    OK(ensure(c, c->row_acc_d, (size_t)(n_rep + 3) * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->x0_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemcpy(c->xref_d.p, x0_dev, v3, hipMemcpyDeviceToDevice));
     HIPCHK(c, hipMemset(c->xi_d.p, 0, v3));
@@ -1112,9 +1338,7 @@ int neigh_build(eamfe_ctx* c, const double* x, double skin, int max_neighbors)
         HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
         if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW))) break;
         HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
-        const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
-        if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
-        OK(plan_lists(c, skin, new_cap));
+        OK(grow_lists(c, st));
     }
     return read_status(c);
 }
@@ -1149,9 +1373,7 @@ int eam_forces(eamfe_ctx* c, const double* x, double* f, double* U, double* e_at
         if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW)) || attempt >= 6) break;
         // rows or bins too small for this configuration: enlarge and evaluate again
         HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
-        const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
-        if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
-        OK(plan_lists(c, c->skin, new_cap));
+        OK(grow_lists(c, st));
         OK(set_rebuild_all(c));
         ++c->replays;
     }
@@ -1208,18 +1430,13 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
     drop_graphs(c);   // captured kernel arguments belong to one call (pointers, protocol, shapes)
     OK(pack(c, x));
     double4* cur = PA(c);
+    c->resume_step = s0;   // nothing has run if the lists do not fit
     if (has_eam) OK(ensure_lists(c, p->skin, cur));
+    c->resume_step = -1;
     const size_t v3 = 3 * (size_t)c->N * sizeof(double);
     const size_t p4 = (size_t)c->N * sizeof(double4);
     const size_t wb = (size_t)c->n_rep * sizeof(double);
     const size_t q4 = (size_t)c->N * sizeof(uint4);
-    if (has_eam) {
-        OK(ensure(c, c->snap_Q, q4));
-        OK(ensure(c, c->snap_P, p4));
-        OK(ensure(c, c->snap_v, v3));
-        OK(ensure(c, c->snap_w, wb));
-        OK(ensure(c, c->snap_rows, wb + 3 * sizeof(double)));
-    }
     for (int64_t b = s0; b < s1; b += c->chunk) {
         const int64_t e = std::min(s1, b + c->chunk);
         if (has_eam) {
@@ -1251,11 +1468,8 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW))) break;
             if (attempt >= 6) return read_status(c);
             HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
-            const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
-            if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
-            OK(plan_lists(c, c->skin, new_cap));
-            OK(set_rebuild_all(c));
             drop_graphs(c);
+            // back to the chunk's start, then larger rows or bins
             cur = start;
             HIPCHK(c, hipMemcpyAsync(cur, c->snap_P.p, p4, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(Q_of(c, cur), c->snap_Q.p, q4, hipMemcpyDeviceToDevice, c->stream));
@@ -1264,6 +1478,21 @@ int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int6
             HIPCHK(c, hipMemcpyAsync(c->row_acc_d.p, c->snap_rows.p, wb + 3 * sizeof(double), hipMemcpyDeviceToDevice,
                                      c->stream));
             ++c->replays;
+            const int g = grow_lists(c, st);
+            if (g == EAMFE_ENOMEM) {
+                // the workspace is too small for the larger lists: hand the
+                // chunk's starting state back (x, v; the work is held) and
+                // stop there; the caller enlarges the workspace and resumes at
+                // step b, where the lists are planned and built again exactly
+                // as a replay here would have built them
+                LCHK(c, launch_unpack(x, cur, c->N, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                c->have_list = false;
+                c->resume_step = b;
+                return g;
+            }
+            OK(g);
+            OK(set_rebuild_all(c));
         }
     }
     LCHK(c, launch_unpack(x, cur, c->N, c->stream));
@@ -1283,7 +1512,9 @@ int run_switching(eamfe_ctx* c, const eamfe_protocol* p, int64_t s0, int64_t s1,
     if (!x || !v) return fail(c, EAMFE_EINVAL, "run_switching: null x or v");
     (void)hipSetDevice(c->device);
     int64_t S = 0;
+    c->resume_step = s0;   // nothing has run if the lambda table does not fit
     OK(ensure_lambda(c, p, &S));
+    c->resume_step = -1;
     if (s0 < 0 || s1 <= s0 || s1 > S) return fail(c, EAMFE_EINVAL, "run_switching: bad step range");
     double c1 = 1.0;
     OK(set_thermostat(c, p, &c1));
@@ -1369,19 +1600,8 @@ int eamfe_adjoint_theta(eamfe_ctx* c, const double* x, const double* w_host, int
     if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
     if (!x || !dtheta) return fail(c, EAMFE_EINVAL, "adjoint_theta: null argument");
     (void)hipSetDevice(c->device);
-    OK(pack(c, x));
-    OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
-    NeighArgs na = neigh_args(c, PA(c));
-    LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
-    StepArgs a = step_args(c);
-    a.P = PA(c);
-    a.Q = QA(c);
-    a.has_eam = 1;
-    a.step_kernel = 0;
-    a.rho_out = (double*)c->rho_d.p;
-    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
-    OK(adjoint_at(c, PA(c), w_host, reduce, dtheta));
-    return read_status(c);
+    return adjoint_theta_with(c, x, w_host, reduce, dtheta, (unsigned long long*)c->bins_d.p,
+                              (double*)c->adj_scratch_d.p);
 }
 
 int eamfe_set_adjoint_sampling(eamfe_ctx* c, int every, const double* w_host, int reduce, double* dtheta)
@@ -1448,9 +1668,6 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
     if (step < 0 || step >= S) return fail(c, EAMFE_EINVAL, "autotune: step out of range");
     const int64_t s1 = std::min<int64_t>(S, step + 2 + trial_steps);
     const size_t v3 = 3 * (size_t)c->N * sizeof(double);
-    OK(ensure(c, c->tune_x, v3));
-    OK(ensure(c, c->tune_v, v3));
-    OK(ensure(c, c->tune_w, (size_t)c->n_rep * sizeof(double)));
     HIPCHK(c, hipMemcpyAsync(c->tune_w.p, c->W_state_d.p, (size_t)c->n_rep * sizeof(double),
                              hipMemcpyDeviceToDevice, c->stream));
     const int timing = c->timing;
@@ -1584,7 +1801,6 @@ int eamfe_pressure(eamfe_ctx* c, const double* x, const double* v, double* P)
     (void)hipSetDevice(c->device);
     OK(pack(c, x));
     OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
-    OK(ensure(c, c->vir_d, (size_t)std::max(1, c->n_tiles) * 3 * sizeof(double)));
     for (int attempt = 0;; ++attempt) {
         NeighArgs na = neigh_args(c, PA(c));
         LCHK(c, launch_neigh_rebuild(na, step_args(c), c->lanes, c->block, c->stream));
@@ -1606,9 +1822,7 @@ int eamfe_pressure(eamfe_ctx* c, const double* x, const double* v, double* P)
         HIPCHK(c, hipMemcpy(&st, c->status_d.p, sizeof(int), hipMemcpyDeviceToHost));
         if (!(st & (ST_NEIGH_OVERFLOW | ST_CELL_OVERFLOW)) || attempt >= 6) break;
         HIPCHK(c, hipMemset(c->status_d.p, 0, sizeof(int)));
-        const int new_cap = (st & ST_NEIGH_OVERFLOW) ? (int)(std::ceil(c->cap * 1.5 / 32.0) * 32.0) : c->cap;
-        if (st & ST_CELL_OVERFLOW) c->min_ccap = (int)(std::ceil(c->ccap * 1.5 / 32.0) * 32.0);
-        OK(plan_lists(c, c->skin, new_cap));
+        OK(grow_lists(c, st));
         OK(set_rebuild_all(c));
         ++c->replays;
     }
@@ -1671,7 +1885,6 @@ int eamfe_barostat_step(eamfe_ctx* c, const eamfe_barostat* b, int64_t step, dou
             R.invL[d] = 1.0 / R.L[d];
         }
     }
-    OK(ensure(c, c->mu_d, (size_t)c->n_rep * sizeof(double)));
     HIPCHK(c, hipMemcpy(c->mu_d.p, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
     LCHK(c, launch_rescale(x, v, (const int32_t*)c->rep_of_d.p, (const double*)c->mu_d.p, c->N, c->stream));
     OK(upload_reps(c));
@@ -1700,7 +1913,6 @@ int eamfe_set_spring_scale(eamfe_ctx* c, const double* s)
         c->has_kscale = false;
         return EAMFE_OK;
     }
-    OK(ensure(c, c->kscale_d, (size_t)c->N * sizeof(double)));
     HIPCHK(c, hipMemcpyAsync(c->kscale_d.p, s, (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     c->has_kscale = true;
     return EAMFE_OK;
@@ -1711,7 +1923,6 @@ int eamfe_msd(eamfe_ctx* c, const double* x, double* msd)
     if (!ready(c, false)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
     if (!x || !msd) return fail(c, EAMFE_EINVAL, "msd: null argument");
     (void)hipSetDevice(c->device);
-    OK(ensure(c, c->msd_d, (size_t)c->n_rep * sizeof(double)));
     LCHK(c, launch_msd(x, (const double*)c->x0_d.p, (const RepDesc*)c->reps_d.p, c->n_rep, c->N, (double*)c->msd_d.p,
                        c->stream));
     HIPCHK(c, hipMemcpyAsync(msd, c->msd_d.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1724,7 +1935,6 @@ int eamfe_list_stats(eamfe_ctx* c, double* mean_len, int* max_len, int* capacity
     if (!c) return EAMFE_EINVAL;
     if (!c->have_list) return fail(c, EAMFE_ESTATE, "no neighbour lists");
     (void)hipSetDevice(c->device);
-    OK(ensure(c, c->stats_d, 2 * sizeof(unsigned long long)));
     HIPCHK(c, hipMemsetAsync(c->stats_d.p, 0, 2 * sizeof(unsigned long long), c->stream));
     hipLaunchKernelGGL(k_list_stats, dim3(256), dim3(256), 0, c->stream, (const int32_t*)c->nnb_d.p, c->N,
                        (unsigned long long*)c->stats_d.p);

@@ -146,6 +146,7 @@ struct StepArgs {
     int slice_grid;         // blocks of the staged FP32 pair launches (0: records gathered from global memory)
     int stage_atoms;        // records staged per block (atoms of the largest replica)
     int step_kernel;        // 1: integrate; 0: evaluate only (eam_forces)
+    int fix;                // FP32: 2^-32 fixed-point per-atom sums (1) or plain float64 sums of the partials (0)
     double dt;
     double c1;
     double half_skin2;
@@ -197,5 +198,7 @@ int launch_adjoint_finish(const AdjointArgs& a, const double* w, int reduce, dou
 int launch_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap, int32_t* out, int out_cap,
                          hipStream_t s);
 int launch_rho(const StepArgs& a, double* rho_out, int precision, int lanes, int block, hipStream_t s);
+// p[0 .. n) = v (a fill kernel, so that the clearing can sit inside a captured graph)
+int launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 
 }  // namespace eamfe

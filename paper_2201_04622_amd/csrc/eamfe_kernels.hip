@@ -133,17 +133,26 @@ struct Tab<double> {
 };
 
 // Accumulation of a lane block's partial sum into a float64 accumulator.
-template <typename real>
+// FP32 with kFix: the partial is rounded to the 2^-32 grid and carried as an
+// exact integer, so the sum does not depend on how slots are grouped into
+// lanes; without kFix the float32 partials are added in float64 as they are
+// (a fixed order for one launch shape, so still reproducible run to run).
+template <typename real, bool kFix>
 struct Acc;
-template <>
-struct Acc<double> {
+template <bool kFix>
+struct Acc<double, kFix> {
     static __device__ __forceinline__ double q(double p) { return p; }
     static __device__ __forceinline__ double fin(double a) { return a; }
 };
 template <>
-struct Acc<float> {
+struct Acc<float, true> {
     static __device__ __forceinline__ double q(float p) { return rint((double)p * kFixScale); }
     static __device__ __forceinline__ double fin(double a) { return a * kFixInv; }
+};
+template <>
+struct Acc<float, false> {
+    static __device__ __forceinline__ double q(float p) { return (double)p; }
+    static __device__ __forceinline__ double fin(double a) { return a; }
 };
 
 // interval index and local coordinate on a uniform grid; m clamped to [0, n-2]
@@ -812,7 +821,7 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 // --------------------------------------------------------------------------
 // Density pass.  FP32 tables are staged in LDS (32 KB for rho).
 // --------------------------------------------------------------------------
-template <typename real, int T, bool kStage = false>
+template <typename real, int T, bool kStage = false, bool kFix = true>
 __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
@@ -895,13 +904,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 if constexpr (kQ) part += v * (in[s] ? 1.f : 0.f);   // a product: the table read stays unconditional
                 else part += in[s] ? v : (real)0;
             }
-            acc += Acc<real>::q(part);
+            acc += Acc<real, kFix>::q(part);
         });
     }
 #pragma unroll
     for (int o = T / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, T);
     if (valid && lane == 0 && a.has_eam) {
-        const double rho = Acc<real>::fin(acc);
+        const double rho = Acc<real, kFix>::fin(acc);
         real t;
         const int m = interval<real>((real)rho, (real)a.tab.inv_h_rho, a.tab.n_rho, t);
         const auto c = Tab<real>::ld4(a.tab.F, m);
@@ -968,7 +977,7 @@ __device__ __forceinline__ void total_force(int mode, const double (&fe)[3], con
     }
 }
 
-template <typename real, int T, bool kStage = false, bool kVir = false>
+template <typename real, int T, bool kStage = false, bool kVir = false, bool kFix = true>
 __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
@@ -1094,14 +1103,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                     }
                 }
             }
-            f0 += Acc<real>::q(p0);
-            f1 += Acc<real>::q(p1);
-            f2 += Acc<real>::q(p2);
-            ep += Acc<real>::q(pe);
+            f0 += Acc<real, kFix>::q(p0);
+            f1 += Acc<real, kFix>::q(p1);
+            f2 += Acc<real, kFix>::q(p2);
+            ep += Acc<real, kFix>::q(pe);
             if constexpr (kVir) {
-                w0 += Acc<real>::q(q0);
-                w1 += Acc<real>::q(q1);
-                w2 += Acc<real>::q(q2);
+                w0 += Acc<real, kFix>::q(q0);
+                w1 += Acc<real, kFix>::q(q1);
+                w2 += Acc<real, kFix>::q(q2);
             }
         });
     }
@@ -1146,12 +1155,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 
     double e[3] = {0.0, 0.0, 0.0};   // U_EAM contribution, |x - x0|^2, row length (list work of the pass)
     if (valid && lane == 0) {
-        const double fe[3] = {Acc<real>::fin(f0), Acc<real>::fin(f1), Acc<real>::fin(f2)};
+        const double fe[3] = {Acc<real, kFix>::fin(f0), Acc<real, kFix>::fin(f1), Acc<real, kFix>::fin(f2)};
         double x[3] = {pi.x, pi.y, pi.z};
         // the spring displacement weighted by the atom's spring scale: the
         // spring force is -k ks (x - x0) and its energy k ks |x - x0|^2 / 2
         const double d[3] = {ks * (x[0] - x0i[0]), ks * (x[1] - x0i[1]), ks * (x[2] - x0i[2])};
-        e[0] = a.has_eam ? eemb + 0.5 * Acc<real>::fin(ep) : 0.0;
+        e[0] = a.has_eam ? eemb + 0.5 * Acc<real, kFix>::fin(ep) : 0.0;
         e[1] = (d[0] * (x[0] - x0i[0]) + d[1] * (x[1] - x0i[1]) + d[2] * (x[2] - x0i[2]));
         e[2] = (double)nrow;
         if (!isfinite(fe[0] + fe[1] + fe[2] + e[0] + e[1])) atomicOr(a.status, ST_NONFINITE);
@@ -1196,7 +1205,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     if constexpr (kVir) {   // pressure evaluation: (1/2) pair virial plus m v_a^2 of the atom, per unit
         double pv[3] = {0.0, 0.0, 0.0};
         if (valid && lane == 0) {
-            const double wv[3] = {Acc<real>::fin(w0), Acc<real>::fin(w1), Acc<real>::fin(w2)};
+            const double wv[3] = {Acc<real, kFix>::fin(w0), Acc<real, kFix>::fin(w1), Acc<real, kFix>::fin(w2)};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double vc = a.v ? a.v[c * N + i] : 0.0;
@@ -1357,6 +1366,20 @@ __global__ void k_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, i
     for (int q = n; q < out_cap; ++q) out[(size_t)i * out_cap + q] = -1;
 }
 
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s)
+{
+    if (n == 0) return 0;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return (int)hipGetLastError();
+}
+
 int launch_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap, int32_t* out, int out_cap,
                          hipStream_t s)
 {
@@ -1426,44 +1449,75 @@ static bool staged(const StepArgs& a)
     return sizeof(real) == 4 && a.has_eam && a.slice_grid > 0;
 }
 
-template <typename real, int T>
+template <typename real, int T, bool kFix>
 static void density_one(const StepArgs& a, int block, hipStream_t s)
 {
     if constexpr (sizeof(real) == 4) {
         if (staged<real>(a)) {
             const size_t sh = lds_bytes<real>(a, 1) + (size_t)a.stage_atoms * sizeof(uint4);
-            const void* f = reinterpret_cast<const void*>(&k_density<real, T, true>);
+            const void* f = reinterpret_cast<const void*>(&k_density<real, T, true, kFix>);
             allow_lds(f, sh);
-            hipLaunchKernelGGL((k_density<real, T, true>), dim3(a.slice_grid), dim3(block), sh, s, a);
+            hipLaunchKernelGGL((k_density<real, T, true, kFix>), dim3(a.slice_grid), dim3(block), sh, s, a);
             return;
         }
     }
     const size_t sh = lds_bytes<real>(a, 1);
-    const void* f = reinterpret_cast<const void*>(&k_density<real, T>);
-    hipLaunchKernelGGL((k_density<real, T>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
+    const void* f = reinterpret_cast<const void*>(&k_density<real, T, false, kFix>);
+    hipLaunchKernelGGL((k_density<real, T, false, kFix>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
 }
 
-template <typename real, int T>
+template <typename real, int T, bool kFix>
 static void force_one(const StepArgs& a, int block, hipStream_t s)
 {
     if (a.vir_part) {   // pressure evaluation (not a step): the persistent form with the virial
         const size_t sh = lds_bytes<real>(a, 2);
-        const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, true>);
-        hipLaunchKernelGGL((k_force<real, T, false, true>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
+        const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, true, kFix>);
+        hipLaunchKernelGGL((k_force<real, T, false, true, kFix>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh,
+                           s, a);
         return;
     }
     if constexpr (sizeof(real) == 4) {
         if (staged<real>(a)) {
             const size_t sh = lds_bytes<real>(a, 2) + (size_t)a.stage_atoms * sizeof(uint4);
-            const void* f = reinterpret_cast<const void*>(&k_force<real, T, true>);
+            const void* f = reinterpret_cast<const void*>(&k_force<real, T, true, false, kFix>);
             allow_lds(f, sh);
-            hipLaunchKernelGGL((k_force<real, T, true>), dim3(a.slice_grid), dim3(block), sh, s, a);
+            hipLaunchKernelGGL((k_force<real, T, true, false, kFix>), dim3(a.slice_grid), dim3(block), sh, s, a);
             return;
         }
     }
     const size_t sh = lds_bytes<real>(a, 2);
-    const void* f = reinterpret_cast<const void*>(&k_force<real, T>);
-    hipLaunchKernelGGL((k_force<real, T>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
+    const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, false, kFix>);
+    hipLaunchKernelGGL((k_force<real, T, false, false, kFix>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s,
+                       a);
+}
+
+// lanes per atom and, in FP32, the accumulation form as template arguments
+template <typename real, bool kFix>
+static int density_lanes(const StepArgs& a, int lanes, int block, hipStream_t s)
+{
+    switch (lanes) {
+    case 1: density_one<real, 1, kFix>(a, block, s); break;
+    case 2: density_one<real, 2, kFix>(a, block, s); break;
+    case 4: density_one<real, 4, kFix>(a, block, s); break;
+    case 8: density_one<real, 8, kFix>(a, block, s); break;
+    case 16: density_one<real, 16, kFix>(a, block, s); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+template <typename real, bool kFix>
+static int force_lanes(const StepArgs& a, int lanes, int block, hipStream_t s)
+{
+    switch (lanes) {
+    case 1: force_one<real, 1, kFix>(a, block, s); break;
+    case 2: force_one<real, 2, kFix>(a, block, s); break;
+    case 4: force_one<real, 4, kFix>(a, block, s); break;
+    case 8: force_one<real, 8, kFix>(a, block, s); break;
+    case 16: force_one<real, 16, kFix>(a, block, s); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
 }
 
 template <typename real>
@@ -1471,15 +1525,8 @@ static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t
 {
     if (a.n_tiles <= 0) return 0;
     if (block < 64 || block > kMaxBlock || block % 64) return (int)hipErrorInvalidValue;
-    switch (lanes) {
-    case 1: density_one<real, 1>(a, block, s); break;
-    case 2: density_one<real, 2>(a, block, s); break;
-    case 4: density_one<real, 4>(a, block, s); break;
-    case 8: density_one<real, 8>(a, block, s); break;
-    case 16: density_one<real, 16>(a, block, s); break;
-    default: return (int)hipErrorInvalidValue;
-    }
-    return (int)hipGetLastError();
+    if (sizeof(real) == 4 && !a.fix) return density_lanes<real, false>(a, lanes, block, s);
+    return density_lanes<real, true>(a, lanes, block, s);
 }
 
 template <typename real>
@@ -1487,15 +1534,8 @@ static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s
 {
     if (a.n_tiles <= 0) return 0;
     if (block < 64 || block > kMaxBlock || block % 64) return (int)hipErrorInvalidValue;
-    switch (lanes) {
-    case 1: force_one<real, 1>(a, block, s); break;
-    case 2: force_one<real, 2>(a, block, s); break;
-    case 4: force_one<real, 4>(a, block, s); break;
-    case 8: force_one<real, 8>(a, block, s); break;
-    case 16: force_one<real, 16>(a, block, s); break;
-    default: return (int)hipErrorInvalidValue;
-    }
-    return (int)hipGetLastError();
+    if (sizeof(real) == 4 && !a.fix) return force_lanes<real, false>(a, lanes, block, s);
+    return force_lanes<real, true>(a, lanes, block, s);
 }
 
 // --------------------------------------------------------------------------

@@ -60,7 +60,11 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
     sig = {
-        "eamfe_create": (i32, [C.POINTER(vp), i32, vp, i32]),
+        "eamfe_create": (i32, [C.POINTER(vp), i32, vp, i32, i32]),
+        "eamfe_workspace_bytes": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "eamfe_set_workspace": (i32, [vp, vp, C.c_size_t]),
+        "eamfe_resume_step": (i32, [vp, C.POINTER(i64)]),
+        "eamfe_device_allocations": (i32, [vp, C.POINTER(i64)]),
         "eamfe_destroy": (i32, [vp]),
         "eamfe_last_error": (C.c_char_p, [vp]),
         "eamfe_set_stream": (i32, [vp, vp]),
@@ -217,26 +221,83 @@ def from_soa(t) -> np.ndarray:
     return t.detach().cpu().numpy().T.copy()
 
 
-class Context:
-    """An eamfe_ctx on one device.  Methods are the ABI entry points."""
+ENOMEM = 2
 
-    def __init__(self, device: int = 0, precision: int = FP64, stream=None):
+
+class Context:
+    """An eamfe_ctx on one device.  Methods are the ABI entry points.
+
+    With ``workspace=True`` (the default) every device buffer of the context
+    is carved from one torch uint8 tensor that this object owns (the
+    library allocates no device memory): a call that needs more memory
+    returns EAMFE_ENOMEM, the tensor is replaced by a larger one (the
+    library moves the buffers over) and the call is repeated, a switching
+    run from the step where it stopped.  ``deterministic`` selects the
+    FP32 form's fixed-point per-atom sums (bitwise shape-independent) or
+    plain float64 sums of the float32 partials."""
+
+    def __init__(self, device: int = 0, precision: int = FP64, stream=None, deterministic: bool = True,
+                 workspace: bool = True):
         import torch
         self._lib = lib()
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
         h = C.c_void_p()
-        code = self._lib.eamfe_create(C.byref(h), int(device), C.c_void_p(stream), int(precision))
+        code = self._lib.eamfe_create(C.byref(h), int(device), C.c_void_p(stream), int(precision),
+                                      int(bool(deterministic)))
         if code:
             raise EamfeError(code, "eamfe_create failed")
         self._h = h
         self.precision = precision
+        self.deterministic = bool(deterministic)
         self.n_rep = 0
         self.N = 0
         self.offsets = None
         self.knots = None          # the knots of the current tables (last eam_setup)
         self.table_version = 0     # counts eam_setup calls
+        self._ws, self._ws_bytes = None, 0
+        self._own_ws = bool(workspace)
+        if self._own_ws:
+            self._c(self._lib.eamfe_set_workspace(self._h, None, 0))
+
+    def _grow(self):
+        """Replace the workspace by one of the size the context asks for;
+        False when it is already that large (then the failure is not a
+        shortfall of workspace)."""
+        if not self._own_ws:
+            return False
+        import torch
+        need = C.c_size_t()
+        self._c(self._lib.eamfe_workspace_bytes(self._h, C.byref(need)))
+        if need.value <= self._ws_bytes:
+            return False
+        nbytes = max(need.value, self._ws_bytes + self._ws_bytes // 4)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._c(self._lib.eamfe_set_workspace(self._h, C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes)))
+        self._ws, self._ws_bytes = ws, nbytes   # the previous tensor is released after the move
+        return True
+
+    def _r(self, fn, *args):
+        """Call entry point fn(ctx, *args), enlarging the workspace and
+        repeating the call while it runs short."""
+        while True:
+            code = fn(self._h, *args)
+            if code == ENOMEM and self._grow():
+                continue
+            return self._c(code)
+
+    def workspace_bytes(self):
+        """(bytes the context's buffers need, bytes of the workspace held)."""
+        n = C.c_size_t()
+        self._c(self._lib.eamfe_workspace_bytes(self._h, C.byref(n)))
+        return n.value, self._ws_bytes
+
+    def device_allocations(self):
+        """hipMalloc calls the library itself has made for this context."""
+        n = C.c_int64()
+        self._c(self._lib.eamfe_device_allocations(self._h, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None):
@@ -280,8 +341,8 @@ class Context:
 
     def autotune(self, p: Protocol, step, x, v, trial_steps=20):
         a, b, ms = C.c_int(), C.c_int(), C.c_double()
-        self._c(self._lib.eamfe_autotune(self._h, C.byref(p), int(step), _ptr(x), _ptr(v), int(trial_steps),
-                                         C.byref(a), C.byref(b), C.byref(ms)))
+        self._r(self._lib.eamfe_autotune, C.byref(p), int(step), _ptr(x), _ptr(v), int(trial_steps),
+                                         C.byref(a), C.byref(b), C.byref(ms))
         return a.value, b.value, ms.value
 
     def set_kernel_timing(self, stride=1, kinds=("density", "force", "lists")):
@@ -310,7 +371,7 @@ class Context:
         """Per-replica diagonal pressure tensor [n_rep, 3] (eV/A^3) at x (and
         velocities v, or the configurational part only)."""
         out = np.zeros((self.n_rep, 3))
-        self._c(self._lib.eamfe_pressure(self._h, _ptr(x), _ptr(v), out.ctypes.data_as(_dp)))
+        self._r(self._lib.eamfe_pressure, _ptr(x), _ptr(v), out.ctypes.data_as(_dp))
         return out
 
     def barostat_step(self, b: Barostat, step, w_eam, x, v):
@@ -319,8 +380,8 @@ class Context:
         v and the boxes in place; returns (mu[n_rep], P[n_rep] internal
         pressures, eV/A^3)."""
         mu, P = np.zeros(self.n_rep), np.zeros(self.n_rep)
-        self._c(self._lib.eamfe_barostat_step(self._h, C.byref(b), int(step), float(w_eam), _ptr(x), _ptr(v),
-                                              mu.ctypes.data_as(_dp), P.ctypes.data_as(_dp)))
+        self._r(self._lib.eamfe_barostat_step, C.byref(b), int(step), float(w_eam), _ptr(x), _ptr(v),
+                                              mu.ctypes.data_as(_dp), P.ctypes.data_as(_dp))
         return mu, P
 
     def boxes(self):
@@ -365,8 +426,8 @@ class Context:
         phi = np.ascontiguousarray(knots.phi, dtype=np.float64)
         rho = np.ascontiguousarray(knots.rho, dtype=np.float64)
         F = np.ascontiguousarray(knots.embed, dtype=np.float64)
-        self._c(self._lib.eam_setup(self._h, len(phi), float(knots.r_cut), phi.ctypes.data_as(_dp),
-                                    rho.ctypes.data_as(_dp), len(F), float(knots.rho_max), F.ctypes.data_as(_dp)))
+        self._r(self._lib.eam_setup, len(phi), float(knots.r_cut), phi.ctypes.data_as(_dp),
+                                    rho.ctypes.data_as(_dp), len(F), float(knots.rho_max), F.ctypes.data_as(_dp))
         self.knots = knots
         self.table_version += 1
 
@@ -378,16 +439,16 @@ class Context:
             for d in range(3):
                 q.box[d] = float(r.box[d])
             q.T, q.k, q.k2, q.mass, q.seed = float(r.T), float(r.k), float(r.k2), float(r.mass), int(r.seed)
-        self._c(self._lib.eamfe_system_setup(self._h, len(replicas), arr, _ptr(x0_soa)))
+        self._r(self._lib.eamfe_system_setup, len(replicas), arr, _ptr(x0_soa))
         self.n_rep = len(replicas)
         self.N = int(x0_soa.shape[1])
         self.offsets = np.concatenate([[0], np.cumsum([r.natoms for r in replicas])])
 
     def neigh_build(self, x, skin=0.3, max_neighbors=0):
-        self._c(self._lib.neigh_build(self._h, _ptr(x), float(skin), int(max_neighbors)))
+        self._r(self._lib.neigh_build, _ptr(x), float(skin), int(max_neighbors))
 
     def eam_forces(self, x, f=None, U=None, e_atom=None):
-        self._c(self._lib.eam_forces(self._h, _ptr(x), _ptr(f), _ptr(U), _ptr(e_atom)))
+        self._r(self._lib.eam_forces, _ptr(x), _ptr(f), _ptr(U), _ptr(e_atom))
 
     def init_velocities(self, v, fix_com=True):
         self._c(self._lib.eamfe_init_velocities(self._h, _ptr(v), int(bool(fix_com))))
@@ -398,11 +459,20 @@ class Context:
             S = C.c_int64()
             _chk(None, self._lib.eamfe_lambda_schedule(C.byref(p), None, C.byref(S)))
             step_end = S.value
-        self._c(self._lib.run_switching(self._h, C.byref(p), int(step_begin), int(step_end), _ptr(x), _ptr(v),
-                                        _ptr(lam_out), _ptr(dHdl_out), _ptr(W_out), int(bool(sync))))
+        s0 = int(step_begin)
+        while True:
+            code = self._lib.run_switching(self._h, C.byref(p), s0, int(step_end), _ptr(x), _ptr(v), _ptr(lam_out),
+                                           _ptr(dHdl_out), _ptr(W_out), int(bool(sync)))
+            if code == ENOMEM and self._grow():
+                r = C.c_int64()
+                self._c(self._lib.eamfe_resume_step(self._h, C.byref(r)))
+                if r.value >= 0:
+                    s0 = r.value   # x, v and the work are the state at that step
+                continue
+            return self._c(code)
 
     def switch_step(self, p: Protocol, step, x, v, W, dHdl=None):
-        self._c(self._lib.switch_step(self._h, C.byref(p), int(step), _ptr(x), _ptr(v), _ptr(W), _ptr(dHdl)))
+        self._r(self._lib.switch_step, C.byref(p), int(step), _ptr(x), _ptr(v), _ptr(W), _ptr(dHdl))
 
     def set_chunk(self, steps):
         self._c(self._lib.eamfe_set_chunk(self._h, int(steps)))
@@ -429,13 +499,13 @@ class Context:
     def set_state(self, W, xref, skin):
         """Load a saved work vector and build the lists at the saved reference positions."""
         Wc = np.ascontiguousarray(W, dtype=np.float64)
-        self._c(self._lib.eamfe_set_state(self._h, Wc.ctypes.data_as(_dp), _ptr(xref), float(skin)))
+        self._r(self._lib.eamfe_set_state, Wc.ctypes.data_as(_dp), _ptr(xref), float(skin))
 
     def adjoint_theta(self, x, dtheta, weights=None, reduce=False):
         """dtheta (device float64, [n_rep, 3, n] or [3, n] with reduce) += w_r dU_r/dtheta."""
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
-        self._c(self._lib.eamfe_adjoint_theta(self._h, _ptr(x), None if w is None else w.ctypes.data_as(_dp),
-                                              int(bool(reduce)), _ptr(dtheta)))
+        self._r(self._lib.eamfe_adjoint_theta, _ptr(x), None if w is None else w.ctypes.data_as(_dp),
+                                              int(bool(reduce)), _ptr(dtheta))
 
     def set_adjoint_sampling(self, every, dtheta=None, weights=None, reduce=False):
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)

@@ -51,8 +51,9 @@ def test_create_without_device_fails_cleanly():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = C.c_void_p()
-    code = E.lib().eamfe_create(C.byref(h), 0, None, 0)
+    code = E.lib().eamfe_create(C.byref(h), 0, None, 0, 1)
     assert code == 3 and not h.value       # EAMFE_EDEVICE
+    assert E.lib().eamfe_create(C.byref(h), 0, None, 0, 2) == 1   # EAMFE_EINVAL: deterministic is 0 or 1
 
 
 @pytest.mark.parametrize("mode,func,lf", [("fl", 2, 1.0), ("fl", 1, 1.0), ("hh", 2, 1.0), ("rs", 2, 0.0625),
