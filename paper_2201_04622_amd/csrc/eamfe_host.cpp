@@ -993,10 +993,12 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
 
 bool ready(eamfe_ctx* c, bool need_pot);
 
-// dU/dtheta at positions x with the adjoint's bins and knot-transform rows
-// at the given device addresses.
+// dU/dtheta at positions x.  The adjoint's bins and knot-transform rows are
+// the context's own (static_base null), or at static_base and static_base +
+// fin_off.  The context's are looked up only after the lists are in place:
+// planning the lists can move the adjoint group of the arena.
 int adjoint_theta_with(eamfe_ctx* c, const double* x, const double* w_host, int reduce, double* dtheta,
-                       unsigned long long* bins, double* fin)
+                       char* static_base, size_t fin_off)
 {
     OK(pack(c, x));
     OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
@@ -1009,6 +1011,8 @@ int adjoint_theta_with(eamfe_ctx* c, const double* x, const double* w_host, int 
     a.step_kernel = 0;
     a.rho_out = (double*)c->rho_d.p;
     LCHK(c, launch_density(a, c->precision, c->lanes, c->block, c->stream));
+    unsigned long long* bins = static_base ? (unsigned long long*)static_base : (unsigned long long*)c->bins_d.p;
+    double* fin = static_base ? (double*)(static_base + fin_off) : (double*)c->adj_scratch_d.p;
     OK(adjoint_at(c, PA(c), w_host, reduce, dtheta, bins, fin));
     return read_status(c);
 }
@@ -1600,8 +1604,7 @@ int eamfe_adjoint_theta(eamfe_ctx* c, const double* x, const double* w_host, int
     if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
     if (!x || !dtheta) return fail(c, EAMFE_EINVAL, "adjoint_theta: null argument");
     (void)hipSetDevice(c->device);
-    return adjoint_theta_with(c, x, w_host, reduce, dtheta, (unsigned long long*)c->bins_d.p,
-                              (double*)c->adj_scratch_d.p);
+    return adjoint_theta_with(c, x, w_host, reduce, dtheta, nullptr, 0);
 }
 
 int eamfe_set_adjoint_sampling(eamfe_ctx* c, int every, const double* w_host, int reduce, double* dtheta)
