@@ -428,6 +428,23 @@ int eamfe_set_state(eamfe_ctx* ctx, const double* W_host, const double* xref_dev
 int eamfe_adjoint_theta(eamfe_ctx* ctx, const double* x_dev, const double* w_host, int reduce,
                         double* dtheta_dev);
 
+/* eamfe_adjoint_theta for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same arguments, kernels and results, with the adjoint's per-call
+ * scratch (its fixed-point coefficient bins and the knot transform's work
+ * rows) in a fixed per-device region inside the library instead of the
+ * context's workspace, so the call allocates nothing, also in a context
+ * without a caller workspace (where the lists must then already fit: else
+ * EAMFE_ENOMEM, nothing allocated).  The region holds 32 MiB:
+ *   n_rep * 3 * (n_r - 1) * 32 bytes (rounded up to 256)
+ *   + (reduce ? 1 : n_rep) * 3 * 2 * n_r * 8 bytes
+ * must fit (116 replicas at 2000 knots with reduce = 0, 174 with
+ * reduce = 1); larger calls return EAMFE_EINVAL and do nothing.  Every call
+ * on one device uses that device's one region (cleared at each call): calls
+ * that overlap in time on one device, from any contexts or streams, race. */
+int eamfe_adjoint_theta_noalloc(eamfe_ctx* ctx, const double* x_dev, const double* w_host, int reduce,
+                                double* dtheta_dev);
+
 /* Sample dU/dtheta inside run_switching at every `every`-th step whose
  * lambda equals the protocol's start value (the H0 ensemble: lambda = 0 for
  * FL/HH, 1 for RS), accumulating as eamfe_adjoint_theta would into

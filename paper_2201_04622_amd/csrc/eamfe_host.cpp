@@ -11,11 +11,36 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <vector>
 
 using namespace eamfe;
+
+// Scratch of eamfe_adjoint_theta_noalloc, for callers that cannot allocate:
+// the adjoint's fixed-point coefficient bins, then the knot transform's work
+// rows.  Each device holds its own copy from the library's load to the end
+// of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (g_scratch_ptr), never through
+// this name.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch (the device is current), once per device.
+static int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return EAMFE_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return EAMFE_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EAMFE_EDEVICE;
+    g_scratch_ptr[device] = p;
+    return EAMFE_OK;
+}
 
 namespace eamfe {
 // eamfe_barostat.hip
@@ -136,6 +161,7 @@ struct eamfe_ctx {
     size_t need = 0;            // bytes the last call that ran out of workspace needed
     int64_t resume_step = -1;   // where an interrupted run_switching stopped (-1: none)
     int64_t device_allocs = 0;  // hipMalloc calls made by the library
+    bool no_alloc = false;      // inside a call that must not allocate (as with a caller's workspace)
     long cap_min = 0;           // row capacity asked for after an overflow (kept across re-plans)
 
     long n_atoms_total() const { return N; }
@@ -269,7 +295,7 @@ int bind(eamfe_ctx* c, const Shape& s)
     const size_t need = layout_bytes(c, s);
     HIPCHK(c, hipStreamSynchronize(c->stream));   // no pass in flight uses the old layout
     if (need > c->arena_bytes) {
-        if (c->caller_ws) {
+        if (c->caller_ws || c->no_alloc) {
             c->need = need;
             return fail(c, EAMFE_ENOMEM, "workspace of " + std::to_string(c->arena_bytes) + " bytes is too small: " +
                                              std::to_string(need) + " needed (eamfe_workspace_bytes)");
@@ -1052,6 +1078,10 @@ int eamfe_create(eamfe_ctx** out, int device, void* hip_stream, int precision, i
     c->stream = (hipStream_t)hip_stream;
     c->precision = precision;
     c->deterministic = deterministic;
+    if (scratch_setup(device) != EAMFE_OK) {
+        delete c;
+        return EAMFE_EDEVICE;
+    }
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
@@ -1605,6 +1635,28 @@ int eamfe_adjoint_theta(eamfe_ctx* c, const double* x, const double* w_host, int
     if (!x || !dtheta) return fail(c, EAMFE_EINVAL, "adjoint_theta: null argument");
     (void)hipSetDevice(c->device);
     return adjoint_theta_with(c, x, w_host, reduce, dtheta, nullptr, 0);
+}
+
+int eamfe_adjoint_theta_noalloc(eamfe_ctx* c, const double* x, const double* w_host, int reduce, double* dtheta)
+{
+    if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
+    if (!x || !dtheta) return fail(c, EAMFE_EINVAL, "adjoint_theta_noalloc: null argument");
+    if (c->device < 0 || c->device >= kMaxDevices || !g_scratch_ptr[c->device])
+        return fail(c, EAMFE_EDEVICE, "adjoint_theta_noalloc: no scratch address for this device");
+    const size_t nb = (size_t)std::max(c->n_r, c->n_rho) - 1;
+    const size_t bins = (size_t)c->n_rep * 3 * nb * 4 * sizeof(unsigned long long);
+    const size_t fin = (size_t)(reduce ? 1 : c->n_rep) * 3 * 2 * (nb + 1) * sizeof(double);
+    const size_t fin_off = (bins + 255) / 256 * 256;
+    if (fin_off + fin > kNoAllocScratchBytes)
+        return fail(c, EAMFE_EINVAL, "adjoint_theta_noalloc: needs " + std::to_string(fin_off + fin) +
+                                         " bytes of scratch, more than its fixed " +
+                                         std::to_string(kNoAllocScratchBytes) + " (fewer replicas or reduce = 1)");
+    (void)hipSetDevice(c->device);
+    char* base = (char*)g_scratch_ptr[c->device];
+    c->no_alloc = true;   // the arena must already hold the lists: report EAMFE_ENOMEM rather than grow it
+    const int rc = adjoint_theta_with(c, x, w_host, reduce, dtheta, base, fin_off);
+    c->no_alloc = false;
+    return rc;
 }
 
 int eamfe_set_adjoint_sampling(eamfe_ctx* c, int every, const double* w_host, int reduce, double* dtheta)
