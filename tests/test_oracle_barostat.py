@@ -114,3 +114,97 @@ def test_move_statistics_match_the_published_rescaling(oracle_lib, opot):
 _EV_J = 1.602176634e-19
 _MVV2E_SI = 1.66053906660e-27 * 1e-20 / 1e-24 / _EV_J
 _KB_SI = 1.380649e-23 / _EV_J
+
+
+def _hcp_zero_stress(opot, cells):
+    """(a, c/a) of the perfect hcp lattice at zero static stress: P_xx = 0 and
+    P_zz = 0 from the oracle's pressure tensor (P_yy = P_xx by the basal
+    plane's symmetry)."""
+    from scipy.optimize import fsolve
+
+    def P(a, q):
+        r = I.Replica("hcp", 0, a, 1.0, 0.0, 0, cells=cells, c_over_a=q)
+        return opot.pressure(r.sites(), r.box)
+    a, q = fsolve(lambda t: [P(*t)[0], P(*t)[2]], [1.78, 1.56], xtol=1e-12)
+    assert np.abs(P(a, q)).max() < 1e-10
+    return a, q
+
+
+def _virial_diag_by_strain(opot, x, L, h=1e-5):
+    """Pair virial W_aa of each axis from the energy alone: under the
+    uniaxial stretch x_a -> s x_a, L_a -> s L_a, dU/ds = -W_aa at s = 1."""
+    out = np.zeros(3)
+    for a in range(3):
+        e = np.ones(3)
+        e[a] = 1 + h
+        up = opot.eam(x * e, L * e)["U"]
+        e[a] = 1 - h
+        dn = opot.eam(x * e, L * e)["U"]
+        out[a] = -(up - dn) / (2 * h)
+    return out
+
+
+def test_orthorhombic_move_statistics(oracle_lib, opot):
+    """The orthorhombic move (each edge on its own, eps_a = ln L_a) at a
+    fixed configuration of a strained, displaced hcp cell: per axis, the
+    drift -(beta_T/(3 tau_p))(p0 - P_aa - kB T/V) dt and the variance
+    2 kB T beta_T dt / (3 V tau_p), with P_aa rebuilt from a uniaxial strain
+    derivative of the energy; move by move d eps_a - amp z_a is the drift, and
+    the sum over axes is the isotropic move's drift and variance."""
+    from oracle import barostat as OB
+    cells = (7, 4, 4)
+    a0, q0 = _hcp_zero_stress(opot, cells)
+    rep = I.Replica("hcp", 0, a0 * 1.01, 500.0, 0.0, 6, cells=cells, c_over_a=q0 * 0.98)
+    p = oracle_lib.RunParams(mode="rs", T=rep.T, k=0.0, seed=rep.seed)
+    x0 = I.displaced(rep.sites(), 0.04, seed=12)
+    v0 = oracle_lib.init_velocities(p, rep.natoms)
+    L = np.asarray(rep.box, dtype=np.float64)
+    V = float(np.prod(L))
+    w_eam, tau_p, beta_T, dt, mass = 0.9, 0.2, 0.3, 0.01, 55.845
+    Paa = (mass * _MVV2E_SI * np.sum(v0 * v0, axis=0) + w_eam * _virial_diag_by_strain(opot, x0, L)) / V
+    assert np.ptp(Paa) > 1e-3     # the strained cell's axes differ
+    kT = _KB_SI * rep.T
+    amp = np.sqrt(2 * kT * beta_T * dt / (3 * V * tau_p))
+    p0 = float(Paa.mean()) + 0.03
+    drift = -(beta_T / (3 * tau_p)) * (p0 - Paa - kT / V) * dt
+    deps, zs = [], []
+    for step in range(1, 401):
+        x, v = x0.copy(), v0.copy()
+        L1, mu, Pm = OB.move(opot, x, v, L, rep.T, mass, rep.seed, step, w_eam, p0, tau_p, beta_T, dt, aniso=True)
+        assert np.allclose(Pm, Paa, rtol=1e-7)
+        assert np.allclose(L1, L * mu) and np.allclose(x, x0 * mu) and np.allclose(v, v0 / mu)
+        deps.append(np.log(mu))
+        zs.append(oracle_lib.gauss3(rep.seed, 0, step, 3))
+    deps, zs = np.asarray(deps), np.asarray(zs)
+    n = len(deps)
+    assert np.all(np.abs(deps.mean(0) - drift) < 4 * amp / np.sqrt(n))
+    assert np.all(np.abs(deps.var(0, ddof=1) / amp ** 2 - 1) < 4 * np.sqrt(2.0 / (n - 1)))
+    assert np.abs(deps - amp * zs - drift).max() < 1e-3 * (beta_T / (3 * tau_p)) * (kT / V) * dt
+    # the volume: the isotropic drift and variance of ln V
+    dlnV = deps.sum(1)
+    assert abs(dlnV.mean() - drift.sum()) < 4 * np.sqrt(3) * amp / np.sqrt(n)
+    assert abs(dlnV.var(ddof=1) / (2 * kT * beta_T * dt / (V * tau_p)) - 1) < 4 * np.sqrt(2.0 / (n - 1))
+
+
+def test_orthorhombic_relaxes_hcp_to_the_zero_stress_cell(oracle_lib, opot):
+    """At 1 K and p0 = 0, hcp started at the ideal c/a = sqrt(8/3) and with
+    a 0.5 % too large relaxes under the orthorhombic move to the cell where
+    the static stress tensor of the perfect lattice vanishes (c/a = 1.560 for
+    this potential), keeping the basal plane's ratio; the isotropic move
+    cannot change c/a."""
+    from oracle import barostat as OB
+    cells = (7, 4, 4)
+    a0, q0 = _hcp_zero_stress(opot, cells)
+    rep = I.Replica("hcp", 0, a0 * 1.005, 1.0, 0.0, 3, cells=cells)
+    p = oracle_lib.RunParams(mode="rs", T=rep.T, k=0.0, seed=rep.seed)
+    lam = np.ones(1501)
+    x, v = rep.sites(), oracle_lib.init_velocities(p, rep.natoms)
+    boxes, mus, Ps, _ = OB.run_npt(opot, p, rep.sites(), rep.box, x, v, lam, 10, 0.0, 0.1, 1.0, aniso=True)
+    a = boxes[:, 0] / cells[0]
+    q = boxes[:, 2] / cells[2] / a
+    plane = boxes[:, 1] / (cells[1] * np.sqrt(3.0)) / a
+    late = slice(len(a) // 2, None)
+    assert abs(q[0] - np.sqrt(8.0 / 3.0)) < 1e-12 and abs(q0 - 1.56) < 1e-3
+    assert abs(q[late].mean() / q0 - 1) < 2e-4, (q[late].mean(), q0)
+    assert abs(a[late].mean() / a0 - 1) < 2e-4
+    assert abs(plane[late].mean() - 1) < 5e-4
