@@ -119,7 +119,8 @@ def measured_issue(kernel, workload, prec, launch, skin):
             "resident_waves_per_simd": float(kv["resident_waves_per_simd"])}
 
 
-def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None, stride=None, graph=0):
+def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None, stride=None, graph=0,
+            list_builder="auto"):
     """Run warmup + steps steps of a workload's protocol on the GPU; the
     last `steps` are timed with HIP events around one run_switching call on
     the library's stream (torch's current stream).  Inside the timed region
@@ -140,6 +141,8 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     reps = wl.replicas if only is None else [wl.replicas[i] for i in only]
     arrs = I.batch_arrays(reps)
     ctx = E.Context(0, E.FP32 if prec == "fp32" else E.FP64)
+    if list_builder != "auto":
+        ctx.set_list_builder(list_builder == "lds")
     if lanes:
         ctx.set_launch(lanes, block)
     ctx.eam_setup(I.synthetic_eam_knots())
@@ -176,12 +179,13 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     rebuilt_reps, rebuilt_atoms = ctx.list_rebuilds()
     end_nl, max_nl, cap = ctx.list_stats()
     launch = ctx.get_launch()
+    builder = ctx.get_list_builder()
     ctx.close()
     return {
         "natoms": natoms, "n_rep": len(reps), "steps": steps, "ms": ms, "wall_s": wall, "kt": kt,
         "stride": stride, "mean_nl": mean_nl, "passes": passes, "rebuilt_reps": rebuilt_reps,
         "rebuilt_atoms": rebuilt_atoms, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch,
-        "tuned": tuned, "desc": wl.description,
+        "tuned": tuned, "desc": wl.description, "list_builder": builder,
     }
 
 
@@ -319,6 +323,7 @@ def result_line(args, main_run, plain, cpu):
             "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
                        "autotuned": main_run["tuned"] is not None},
             "skin": args.skin,
+            "list_builder": main_run["list_builder"],
             "force_kernel_ms_sampled": round(kt["force"][0], 4),
             "force_launches_sampled": kt["force"][1],
         },
@@ -346,6 +351,9 @@ def main():
     ap.add_argument("--skin", type=float, default=0.65)   # fastest of a 0.35..1.2 sweep on the 64-replica batch
     ap.add_argument("--timing-stride", type=int, default=None,
                     help="iterations between event-timed force passes in the timed region (0: none)")
+    ap.add_argument("--list-builder", default="auto", choices=["auto", "lds", "global"],
+                    help="neighbour rows of small replicas built from LDS or all in global memory "
+                         "(auto: the autotuner's choice, else LDS)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -369,7 +377,7 @@ def main():
         sys.exit(2)
 
     main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup, args.lanes, args.block,
-                       not args.no_autotune, args.skin, stride=args.timing_stride)
+                       not args.no_autotune, args.skin, stride=args.timing_stride, list_builder=args.list_builder)
     plain = None
     if not args.no_fp64:
         pr = run_gpu("fl_mid", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0], stride=0)

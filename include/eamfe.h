@@ -11,8 +11,8 @@
  *                        RS lambda(tau) = 1/(1 + tau (1/l_f - 1)) (Sec. RS in LAMMPS)
  *   estimators           Eq. W12, Eq. Ediss, Eq. fl (+ Eq. cm), Eq. rs, Eq. jarz
  *   spring constants     Eq. msd (mean-squared displacement), per-atom springs
- *   constant pressure    pressure tensor; isotropic stochastic cell rescaling
- *                        between fixed-volume stretches (RS at p = 0 gives G(T))
+ *   constant pressure    pressure tensor; isotropic or orthorhombic stochastic cell
+ *                        rescaling between fixed-volume stretches (RS at p = 0 gives G(T))
  *
  * Conventions for every entry point:
  *   - Units are LAMMPS "metal": eV, Angstrom, ps, amu, K.
@@ -66,9 +66,13 @@ extern "C" {
 #define EAMFE_FP64 0   /* all arithmetic in float64                                    */
 #define EAMFE_FP32 1   /* pair terms, densities, tables in float32; positions, velocities,
                           energies and work in float64.  Per-atom sums are float32
-                          partials over fixed groups of four list slots, rounded to
-                          2^-32 and added exactly in fixed point: results are
-                          bitwise reproducible and independent of the launch shape */
+                          partials over groups of four consecutive list slots, rounded
+                          to 2^-32 and added exactly in fixed point; replica sums
+                          (energies, the noise mean) add values rounded to 2^-24 or
+                          2^-36 exactly.  Results are bitwise reproducible and the
+                          same for every launch shape and either list builder.  The
+                          slot groups follow the rows: rebuilding the lists at
+                          another step changes the rounding (the last bits). */
 
 /* Hamiltonian family (dH/dl in brackets) */
 #define EAMFE_MODE_FL      0   /* (1-l) U_EAM + l U_E(k)          [U_E - U_EAM]  Eq. interp/w_irr2 */
@@ -116,10 +120,10 @@ typedef struct eamfe_protocol {
  * (a hipStream_t; NULL = the legacy default stream).  precision is
  * EAMFE_FP64 or EAMFE_FP32.  deterministic (EAMFE_FP32 only; 0 or 1): 1
  * rounds every float32 partial sum of four list slots to the 2^-32 grid and
- * adds it exactly (results bitwise reproducible and independent of the
- * launch shape, the precision form the method's work integral is stated
- * for); 0 adds the float32 partials in float64 as they are (bitwise
- * reproducible run to run for one launch shape, not across shapes).
+ * every term of a replica sum to 2^-24 (energies, virials) or 2^-36 (the
+ * noise mean) and adds them exactly (results bitwise reproducible and
+ * independent of the launch shape); 0 adds them in float64 as they are
+ * (bitwise reproducible run to run for one launch shape, not across shapes).
  * No device memory is taken here.  *ctx is set on success. */
 int eamfe_create(eamfe_ctx** ctx, int device, void* hip_stream, int precision, int deterministic);
 
@@ -165,8 +169,12 @@ int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threa
 /* Autotuner: time `trial_steps` steps of protocol p from `step` at every
  * launch shape (lanes per atom x block threads x persistent grid) on copies
  * of the caller's state (x_dev, v_dev are not modified; the work carried by
- * the context is restored) and keep the fastest shape.  Outputs (may be
- * NULL): the chosen lanes and block threads, and its time per step in ms. */
+ * the context is restored) and keep the fastest shape; then, at that shape,
+ * keep the faster of the two list builders (eamfe_set_list_builder).  The
+ * lists are built again at the caller's positions by the next pass, so a
+ * deterministic EAMFE_FP32 run continues bitwise as one whose lists were
+ * rebuilt at `step`.  Outputs (may be NULL): the chosen lanes and block
+ * threads, and its time per step in ms. */
 int eamfe_autotune(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step, const double* x_dev,
                    const double* v_dev, int trial_steps, int* lanes_out, int* block_out, double* ms_per_step);
 
@@ -190,6 +198,17 @@ int eamfe_get_grid(const eamfe_ctx* ctx, int* blocks);
  * internal default-priority stream ordered after and before the context's
  * stream with events.  Kernel timing or adjoint sampling switch it off. */
 int eamfe_set_graph(eamfe_ctx* ctx, int iters);
+
+/* Neighbour-list builder.  lds = 1 (default): replicas of at most 4096 atoms
+ * and 4096 cells have their rows built by one kernel over one block per
+ * compute unit, which stages each flagged replica's positions in LDS, sorts
+ * its atoms into cells there and builds the rows from LDS; larger replicas
+ * use the global-memory binning and row kernels.  lds = 0: every replica
+ * through the global-memory kernels.  The rows are identical either way
+ * (the same cells, stencil order and member order).  The lists are built
+ * again by the next pass. */
+int eamfe_set_list_builder(eamfe_ctx* ctx, int lds);
+int eamfe_get_list_builder(const eamfe_ctx* ctx, int* lds);
 
 /* 1: bin the replicas into eight groups balanced by atom count; group x is
  * spread over the blocks on XCD x (workgroup id mod 8), so a replica's atoms
@@ -248,34 +267,41 @@ int eamfe_list_rebuilds(eamfe_ctx* ctx, int64_t* replica_rebuilds, int64_t* atom
  * a list or bin overflow enlarges the lists and evaluates again. */
 int eamfe_pressure(eamfe_ctx* ctx, const double* x_dev, const double* v_dev, double* P);
 
-/* Isotropic stochastic cell rescaling (Bernetti and Bussi, J. Chem. Phys.
- * 153, 114107, 2020), one coupling move per call, made between
- * fixed-volume runs of run_switching.  It holds the pressure the paper holds
- * with a barostat: at zero in its reversible-scaling runs (Sec. p_rs) and
- * while the lattice parameter of its Frenkel--Ladd runs is fixed (Sec. p_fl).
- * At positions x_dev and velocities v_dev (device SoA [3][N_tot] FP64, both
- * updated in place) each replica's internal pressure of H = w_eam U_EAM,
- *   P = (sum_i m v_i^2 + w_eam W) / (3 V),  W the trace of the pair virial,
- * moves eps = ln V by
- *   d eps = -(beta_T / tau_p) (p0 - P - kB T / V) dt
- *           + sqrt(2 kB T beta_T dt / (V tau_p)) z,
- * T the replica's temperature and z the first Box--Muller deviate of Philox
- * stream 3 under the replica's seed at counter (atom 0, step).  Positions and
- * box edges are then scaled by mu = exp(d eps / 3) and velocities by 1 / mu.
- * w_eam is the weight of U_EAM in the Hamiltonian at the step boundary
- * `step`: lambda_step of the schedule in reversible scaling (where, with
- * p0 = 0, this keeps the scaled system at the zero pressure of the real one
- * at T0 / lambda), 1 for plain dynamics of U_EAM.  The spring anchors x0 are not moved, so the
- * move suits runs without springs.  The lists are
- * planned again for the new boxes by the next pass.  mu_host[n_rep] and
- * P_host[n_rep] (host, may be NULL) return the factors and the pressures
- * used.  EAMFE_EBOX leaves everything unchanged if a box edge would fall to
+/* Stochastic cell rescaling (Bernetti and Bussi, J. Chem. Phys. 153,
+ * 114107, 2020), one coupling move per call, made between fixed-volume runs
+ * of run_switching.  It holds the pressure the paper holds with a barostat:
+ * at zero in its reversible-scaling runs (Sec. p_rs), while the lattice
+ * parameter of its Frenkel--Ladd runs is fixed (Sec. p_fl), and with each
+ * direction on its own for hcp (the per-direction barostat of the size
+ * study, Sec. on free-energy size dependence).  At positions x_dev and
+ * velocities v_dev (device SoA [3][N_tot] FP64, both updated in place)
+ * each replica's internal pressure of H = w_eam U_EAM along axis a,
+ *   P_aa = (sum_i m v_ia^2 + w_eam W_aa) / V,  W_aa the pair virial,
+ * moves the box.  Isotropic (aniso = 0): eps = ln V moves by
+ *   d eps = -(beta_T / tau_p) (p0 - P - kB T / V) dt + sqrt(2 kB T beta_T dt / (V tau_p)) z0,
+ * P the mean of the P_aa, and positions and edges scale by exp(d eps / 3).
+ * Orthorhombic (aniso = 1): each edge moves on its own, eps_a = ln L_a,
+ *   d eps_a = -(beta_T / (3 tau_p)) (p0 - P_aa - kB T / V) dt + sqrt(2 kB T beta_T dt / (3 V tau_p)) z_a,
+ * whose sum over the axes is the isotropic move of ln V; positions and edges
+ * along a scale by exp(d eps_a).  Velocities scale by the inverse factors.
+ * T is the replica's temperature and (z0, z1, z2) the three Box--Muller
+ * deviates of Philox stream 3 under the replica's seed at counter (atom 0,
+ * step).  w_eam is the weight of U_EAM in the Hamiltonian at the step
+ * boundary `step`: lambda_step of the schedule in reversible scaling (where,
+ * with p0 = 0, this keeps the scaled system at the zero pressure of the real
+ * one at T0 / lambda), 1 for plain dynamics of U_EAM.  The spring anchors x0
+ * are not moved, so the move suits runs without springs.  The lists are
+ * planned again for the new boxes by the next pass.  mu_host[n_rep][3] and
+ * P_host[n_rep][3] (host, may be NULL) return each axis's factor and P_aa.
+ * EAMFE_EBOX leaves everything unchanged if a box edge would fall to
  * 2 (r_cut + skin) or below.  Synchronises. */
 typedef struct eamfe_barostat {
     double p0;       /* target pressure, eV/A^3 */
     double tau_p;    /* coupling time, ps (> 0) */
     double beta_T;   /* compressibility, A^3/eV: sets the relaxation rate, not the sampled distribution */
     double dt;       /* time between moves (the coupling interval), ps */
+    int32_t aniso;   /* 0: isotropic; 1: each box edge on its own (orthorhombic) */
+    int32_t pad_;
 } eamfe_barostat;
 int eamfe_barostat_step(eamfe_ctx* ctx, const eamfe_barostat* b, int64_t step, double w_eam, double* x_dev,
                         double* v_dev, double* mu_host, double* P_host);

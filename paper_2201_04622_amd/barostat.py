@@ -1,6 +1,7 @@
 """Constant-pressure runs: fixed-volume stretches of the switching dynamics
-alternating with isotropic stochastic cell-rescaling moves (Bernetti and
-Bussi, J. Chem. Phys. 153, 114107, 2020; ``eamfe_barostat_step``).
+alternating with stochastic cell-rescaling moves (Bernetti and Bussi, J.
+Chem. Phys. 153, 114107, 2020; ``eamfe_barostat_step``), isotropic or with
+each box edge on its own (orthorhombic, for hcp's c/a).
 
 The paper holds the pressure at zero with a barostat in its reversible-
 scaling runs (Sec. p_rs) and while it fixes the lattice parameter of its
@@ -26,14 +27,15 @@ from . import eamfe as E
 class NptTrace:
     steps: np.ndarray     # [moves] step boundary of each move
     boxes: np.ndarray     # [moves + 1, n_rep, 3] box edges before the first move and after each
-    mu: np.ndarray        # [moves, n_rep] scale factors
-    pressure: np.ndarray  # [moves, n_rep] internal pressures the moves used, eV/A^3
+    mu: np.ndarray        # [moves, n_rep, 3] per-axis scale factors
+    pressure: np.ndarray  # [moves, n_rep, 3] diagonal internal pressures the moves used, eV/A^3
 
 
-def barostat(p0=0.0, tau_p=1.0, beta_T=1.0, dt=0.001, every=10) -> E.Barostat:
+def barostat(p0=0.0, tau_p=1.0, beta_T=1.0, dt=0.001, every=10, aniso=False) -> E.Barostat:
     """Parameters of the move made every ``every`` steps of length ``dt`` ps
-    (the coupling interval is every * dt)."""
-    return E.Barostat(float(p0), float(tau_p), float(beta_T), float(dt) * int(every))
+    (the coupling interval is every * dt); ``aniso`` moves each box edge on
+    its own."""
+    return E.Barostat(float(p0), float(tau_p), float(beta_T), float(dt) * int(every), int(bool(aniso)), 0)
 
 
 def run_npt(ctx, p: E.Protocol, x, v, step_begin, step_end, every, b: E.Barostat, dHdl_out=None,
@@ -61,4 +63,4 @@ def run_npt(ctx, p: E.Protocol, x, v, step_begin, step_end, every, b: E.Barostat
         s = e
     n = len(steps)
     return NptTrace(np.asarray(steps, dtype=np.int64), np.asarray(boxes),
-                    np.asarray(mus).reshape(n, -1), np.asarray(Ps).reshape(n, -1))
+                    np.asarray(mus).reshape(n, -1, 3), np.asarray(Ps).reshape(n, -1, 3))

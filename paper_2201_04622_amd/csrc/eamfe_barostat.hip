@@ -10,17 +10,18 @@
 
 namespace eamfe {
 
-// x <- mu x, v <- v / mu for the atoms of each replica (SoA [3][N] FP64; one
-// thread per atom; mu[n_rep] on the device)
+// x_a <- mu_a x_a, v_a <- v_a / mu_a for the atoms of each replica (SoA
+// [3][N] FP64; one thread per atom; mu[n_rep][3] on the device, one factor
+// per axis)
 __global__ void k_rescale(double* x, double* v, const int32_t* rep_of, const double* mu, int N)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const double m = mu[rep_of[i]];
-    const double im = 1.0 / m;
+    const int r = rep_of[i];
     for (int c = 0; c < 3; ++c) {
+        const double m = mu[3 * r + c];   // the factor of axis c
         x[(size_t)c * N + i] *= m;
-        v[(size_t)c * N + i] *= im;
+        v[(size_t)c * N + i] *= 1.0 / m;
     }
 }
 
@@ -54,13 +55,20 @@ static void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1)
 // The first Box--Muller deviate of the Philox block at counter (atom, step
 // low word, stream, step high word) under key (seed low word, seed high
 // word), from the uniforms (w + 1) 2^-32 of its first two words.
-double barostat_gauss(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream)
+// The three Box--Muller deviates of the Philox block at counter (atom, step
+// low word, stream, step high word) under key (seed low word, seed high
+// word): z0, z1 from the uniforms (w + 1) 2^-32 of its first two words, z2
+// from the last two.
+void barostat_gauss3(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream, double z[3])
 {
     uint32_t c[4] = {atom, (uint32_t)((uint64_t)step & 0xffffffffu), stream, (uint32_t)((uint64_t)step >> 32)};
     philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
-    const double u0 = ((double)c[0] + 1.0) * 2.3283064365386963e-10;
-    const double u1 = ((double)c[1] + 1.0) * 2.3283064365386963e-10;
-    return std::sqrt(-2.0 * std::log(u0)) * std::cos(2.0 * M_PI * u1);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = ((double)c[q] + 1.0) * 2.3283064365386963e-10;
+    const double r0 = std::sqrt(-2.0 * std::log(u[0])), r1 = std::sqrt(-2.0 * std::log(u[2]));
+    z[0] = r0 * std::cos(2.0 * M_PI * u[1]);
+    z[1] = r0 * std::sin(2.0 * M_PI * u[1]);
+    z[2] = r1 * std::cos(2.0 * M_PI * u[3]);
 }
 
 }  // namespace eamfe

@@ -45,7 +45,7 @@ static int scratch_setup(int device)
 namespace eamfe {
 // eamfe_barostat.hip
 hipError_t launch_rescale(double* x, double* v, const int32_t* rep_of, const double* mu, int N, hipStream_t s);
-double barostat_gauss(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream);
+void barostat_gauss3(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream, double z[3]);
 }  // namespace eamfe
 
 struct DevBuf {
@@ -105,7 +105,7 @@ struct eamfe_ctx {
     DevBuf slices_d;
     DevBuf reps_d, tiles_d, rep_of_d, x0_d, xref_d, Pa_d, Pb_d, Qa_d, Qb_d, e_emb_d, xi_d;
     DevBuf noise_part_d, energy_part_d, U_rep_d, W_state_d;
-    DevBuf iter_d, rebuild_d, flag_pre_d, pending_d, status_d, row_acc_d, msd_d, kscale_d, vir_d, mu_d;
+    DevBuf iter_d, rebuild_d, flag_pre_d, status_d, row_acc_d, msd_d, kscale_d, vir_d, mu_d;
     bool has_kscale = false;   // per-atom spring scales set
 
     // neighbour lists
@@ -113,6 +113,10 @@ struct eamfe_ctx {
     double skin = 0.3;
     int cap = 0, ccap = 0, n_cells = 0;
     DevBuf nbr_d, nnb_d, cell_cnt_d, cell_atoms_d, cell_rep_d;
+    // rows of replicas that fit one block's LDS come from k_rows_lds
+    int lds_rows = 1;                       // 0: every replica through k_bin / k_list
+    int n_lds = 0, n_global = 0, lds_atoms = 0, lds_cells = 0, lds_waves = 0;
+    DevBuf lds_list_d;                      // [n_rep] those replicas, in order
 
     // graph replay of the middle iterations (0 = eager launches)
     int graph_iters = 0;
@@ -214,7 +218,6 @@ void for_regions(eamfe_ctx* c, const Shape& s, F&& f)
     if (N || s.n_r) {
         f(c->status_d, G_CORE, sizeof(int32_t));
         f(c->iter_d, G_CORE, sizeof(int64_t));
-        f(c->pending_d, G_CORE, sizeof(int32_t));
         f(c->stats_d, G_CORE, 2 * sizeof(unsigned long long));
     }
     if (N) {
@@ -243,6 +246,7 @@ void for_regions(eamfe_ctx* c, const Shape& s, F&& f)
         f(c->msd_d, G_SYS, R * d);
         f(c->mu_d, G_SYS, 3 * R * d);
         f(c->adj_w_d, G_SYS, R * d);
+        f(c->lds_list_d, G_SYS, R * sizeof(int32_t));
         f(c->tune_x, G_SYS, 3 * N * d);
         f(c->tune_v, G_SYS, 3 * N * d);
         f(c->tune_w, G_SYS, R * d);
@@ -576,6 +580,13 @@ NeighArgs neigh_args(eamfe_ctx* c, const double4* P)
         a.rl2_f = (float)((c->r_cut + c->skin + margin) * (c->r_cut + c->skin + margin));
     }
     a.half_skin2 = 0.25 * c->skin * c->skin;
+    a.lds_list = (const int32_t*)c->lds_list_d.p;
+    a.n_lds = c->n_lds;
+    a.n_global = c->n_global;
+    a.lds_atoms = c->lds_atoms;
+    a.lds_cells = c->lds_cells;
+    a.lds_waves = c->lds_waves;
+    a.lds_grid = c->n_cu;
     return a;
 }
 
@@ -598,7 +609,6 @@ StepArgs step_args(eamfe_ctx* c)
     a.rebuild = (int32_t*)c->rebuild_d.p;
     a.cell_cnt = (int32_t*)c->cell_cnt_d.p;
     a.flag_pre = (int32_t*)c->flag_pre_d.p;
-    a.pending = (int32_t*)c->pending_d.p;
     a.row_acc = (double*)c->row_acc_d.p;
     a.status = (int32_t*)c->status_d.p;
     a.iter = (int64_t*)c->iter_d.p;
@@ -620,7 +630,7 @@ StepArgs step_args(eamfe_ctx* c)
                        ? (int)c->slices.size()
                        : 0;
     a.half_skin2 = 0.25 * c->skin * c->skin;
-    a.fix = c->deterministic;
+    a.fix = c->deterministic && c->precision == EAMFE_FP32;
     return a;
 }
 
@@ -637,34 +647,44 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
     std::vector<int32_t> cell_rep;
     std::vector<RepDesc> reps = c->reps;
     for (int r = 0; r < c->n_rep; ++r) {
-        RepDesc& R = reps[r];
-        double V = R.L[0] * R.L[1] * R.L[2];
+        const RepDesc& R = reps[r];
         for (int d = 0; d < 3; ++d)
             if (!(R.L[d] > 2.0 * rl))
                 return fail(c, EAMFE_EBOX, "box edge " + std::to_string(R.L[d]) + " of replica " +
                                                std::to_string(r) + " is not larger than 2 (r_cut + skin)");
-        dens_max = std::max(dens_max, R.n / V);
-        // cells of edge >= rl / 2: a 5 x 5 x 5 stencil holds every pair within
-        // rl, and five or more cells per edge keep its cells distinct
-        int nc[3];
-        bool cells = true;
-        for (int d = 0; d < 3; ++d) {
-            nc[d] = (int)std::floor(2.0 * R.L[d] / rl);
-            if (nc[d] < 5) cells = false;
-        }
-        R.cell_base = n_cells;
-        if (cells) {
-            for (int d = 0; d < 3; ++d) R.nc[d] = nc[d];
-            const int k = nc[0] * nc[1] * nc[2];
-            for (int q = 0; q < k; ++q) cell_rep.push_back(r);
-            n_cells += k;
-            cellvol_max = std::max(cellvol_max, V / k * (R.n / V));
-        } else {
-            R.nc[0] = R.nc[1] = R.nc[2] = 0;
-        }
     }
-    // mean occupancy of the fullest cells, with room for clustering
-    const int ccap = std::max({32, c->min_ccap, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32});
+    // cells of edge >= rl / 2: a 5 x 5 x 5 stencil holds every pair within rl,
+    // and five or more cells per edge keep its cells distinct; replicas small
+    // enough for one block's LDS (allow_lds) get their rows from k_rows_lds
+    // and no global cells
+    auto classify = [&](bool allow_lds) {
+        dens_max = cellvol_max = 0.0;
+        n_cells = 0;
+        cell_rep.clear();
+        for (int r = 0; r < c->n_rep; ++r) {
+            RepDesc& R = reps[r];
+            const double V = R.L[0] * R.L[1] * R.L[2];
+            dens_max = std::max(dens_max, R.n / V);
+            int nc[3];
+            bool cells = true;
+            for (int d = 0; d < 3; ++d) {
+                nc[d] = (int)std::floor(2.0 * R.L[d] / rl);
+                if (nc[d] < 5) cells = false;
+            }
+            for (int d = 0; d < 3; ++d) R.nc[d] = cells ? nc[d] : 0;
+            R.lds = allow_lds && R.n <= kRowsAtomsMax && (long)R.nc[0] * R.nc[1] * R.nc[2] <= kRowsCellsMax;
+            R.cell_base = n_cells;
+            if (cells && !R.lds) {
+                const int k = nc[0] * nc[1] * nc[2];
+                for (int q = 0; q < k; ++q) cell_rep.push_back(r);
+                n_cells += k;
+                cellvol_max = std::max(cellvol_max, V / k * (R.n / V));
+            }
+        }
+    };
+    classify(c->lds_rows != 0);
+    // mean occupancy of the fullest cells, with room for clustering (set below, after the builders are chosen)
+    int ccap = 0;
     int cap;
     if (max_neighbors > 0) {
         cap = (max_neighbors + 31) / 32 * 32;   // rows are read four slots at a time, 16-byte aligned
@@ -672,11 +692,41 @@ int plan_lists(eamfe_ctx* c, double skin, int max_neighbors)
         const double nmean = 4.0 / 3.0 * M_PI * rl * rl * rl * dens_max;
         cap = std::max((int)(std::ceil((nmean * 2.0 + 32.0) / 32.0) * 32.0), (int)c->cap_min);
     }
+    // the LDS builder's block: records, ids and cell starts of its largest
+    // replica and a row buffer per wavefront; as many wavefronts as fit
+    int lds_atoms = 0, lds_cells = 0, lds_waves = 0;
+    for (const RepDesc& R : reps)
+        if (R.lds) {
+            lds_atoms = std::max(lds_atoms, R.n);
+            lds_cells = std::max(lds_cells, R.nc[0] * R.nc[1] * R.nc[2]);
+        }
+    if (lds_atoms)
+        for (int wv : {16, 8, 4})
+            if (rows_lds_bytes(lds_atoms, lds_cells, cap, wv) + 1024 <= (size_t)c->max_lds) {   // + static shared words
+                lds_waves = wv;
+                break;
+            }
+    if (lds_atoms && !lds_waves) {   // not even four wavefronts fit: every replica through k_bin / k_list
+        classify(false);
+        lds_atoms = lds_cells = 0;
+    }
+    std::vector<int32_t> lds_list;
+    for (int r = 0; r < c->n_rep; ++r)
+        if (reps[r].lds) lds_list.push_back(r);
+    ccap = std::max({32, c->min_ccap, (int)(std::ceil(cellvol_max * 4.0 / 32.0) * 32.0) + 32});
     Shape s2 = c->shape;
     s2.cap = cap;
     s2.n_cells = n_cells;
     s2.ccap = ccap;
     OK(bind(c, s2));
+    c->n_lds = (int)lds_list.size();
+    c->n_global = c->n_rep - c->n_lds;
+    c->lds_atoms = lds_atoms;
+    c->lds_cells = lds_cells;
+    c->lds_waves = lds_waves;
+    if (!lds_list.empty())
+        HIPCHK(c, hipMemcpy(c->lds_list_d.p, lds_list.data(), lds_list.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
     c->reps = reps;
     c->ccap = ccap;
     c->cap = cap;
@@ -902,14 +952,15 @@ int mark(eamfe_ctx* c, int kind, int end)
 // the previous iteration's force pass), density pass, force pass.  Without
 // EAM there is no list pass and the force pass is finished at once; with it
 // the caller finishes the last iteration's force pass.
+// finish_prev: the density pass finishes the force pass before it (an extra
+// block, off the path of the list pass).
 int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool has_eam, hipStream_t st, bool sample,
-                  int64_t it)
+                  bool finish_prev)
 {
     // sampled: the first iteration after timing was switched on, then every
     // timing-th one, so any range of at least one iteration has a sample
     c->timing_now = c->timing > 0 && c->timing_seen % c->timing == 0;
     if (c->timing > 0) ++c->timing_seen;
-    (void)it;
     if (has_eam) {
         NeighArgs na = neigh_args(c, cur);
         OK(mark(c, 2, 0));
@@ -921,9 +972,11 @@ int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool ha
     a.Q = Q_of(c, cur);
     a.Qn = Q_of(c, nxt);
     a.rho_out = sample ? (double*)c->rho_d.p : nullptr;
+    a.finish_prev = finish_prev ? 1 : 0;
     OK(mark(c, 0, 0));
     LCHK(c, launch_density(a, c->precision, c->lanes, c->block, st));
     OK(mark(c, 0, 1));
+    a.finish_prev = 0;
     if (sample) {
         OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out,
                       (unsigned long long*)c->bins_d.p, (double*)c->adj_scratch_d.p));
@@ -959,9 +1012,11 @@ int capture_middle(eamfe_ctx* c, const StepArgs& a0, double4* start, bool has_ea
     double4* nxt = cur == PA(c) ? PB(c) : PA(c);
     int rc = EAMFE_OK;
     for (int k = 0; k < iters && rc == EAMFE_OK; ++k) {
-        rc = one_iteration(c, a, cur, nxt, has_eam, c->gstream, false, 1);
+        a.it_k = k;   // step = the counter at the replay's start + k
+        rc = one_iteration(c, a, cur, nxt, has_eam, c->gstream, false, has_eam);
         std::swap(cur, nxt);
     }
+    if (rc == EAMFE_OK) rc = launch_advance_iter((int64_t*)c->iter_d.p, iters, c->gstream) ? EAMFE_EDEVICE : EAMFE_OK;
     c->timing = timing;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->gstream, &g);
@@ -990,11 +1045,16 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
     a.step_kernel = 1;
     a.has_eam = has_eam ? 1 : 0;
     OK(set_iter(c, it_first));
+    int64_t base = it_first;   // the device step counter
     const bool graphs = c->graph_iters > 0 && !c->timing && c->adj_every == 0 && c->gstream;
     int64_t it = it_first;
     while (it <= it_last) {
         const bool middle = it > it_first && it < it_last;
         if (graphs && middle && it_last - it >= c->graph_iters) {
+            if (base != it) {   // a replay's steps count from the counter
+                OK(set_iter(c, it));
+                base = it;
+            }
             const int k = cur == PA(c) ? 0 : 1;
             if (!c->gexec[k]) OK(capture_middle(c, a, cur, has_eam, c->graph_iters, &c->gexec[k]));
             HIPCHK(c, hipEventRecord(c->ev_user, c->stream));
@@ -1004,15 +1064,20 @@ int iterate(eamfe_ctx* c, StepArgs a, double4** cur_io, bool has_eam, int64_t it
             HIPCHK(c, hipEventRecord(c->ev_graph, c->gstream));
             HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_graph, 0));
             it += reps * c->graph_iters;   // graph_iters is even: the buffers are back where they were
+            base += reps * c->graph_iters;   // each replay advanced the counter
             continue;
         }
         const bool sample = has_eam && c->adj_every > 0 && it < it_last && it % c->adj_every == 0 &&
                             c->lam_valid && c->lam_h[it] == c->lam_h[0];
-        OK(one_iteration(c, a, cur, nxt, has_eam, c->stream, sample, it));
+        a.it_k = it - base;
+        OK(one_iteration(c, a, cur, nxt, has_eam, c->stream, sample, has_eam && it > it_first));
         std::swap(cur, nxt);
         ++it;
     }
-    if (has_eam && it > it_first) LCHK(c, launch_finish(a, c->stream));   // the last force pass
+    if (has_eam && it > it_first) {   // the last force pass
+        a.it_k = (it - 1) - base;
+        LCHK(c, launch_finish(a, c->stream));
+    }
     *cur_io = cur;
     return EAMFE_OK;
 }
@@ -1222,6 +1287,23 @@ int eamfe_get_launch(const eamfe_ctx* c, int* lanes, int* block)
     return EAMFE_OK;
 }
 
+int eamfe_set_list_builder(eamfe_ctx* c, int lds)
+{
+    if (!c || (lds != 0 && lds != 1)) return EAMFE_EINVAL;
+    if (c->lds_rows != lds) {
+        c->lds_rows = lds;
+        c->have_list = false;   // planned and built again by the next pass
+    }
+    return EAMFE_OK;
+}
+
+int eamfe_get_list_builder(const eamfe_ctx* c, int* lds)
+{
+    if (!c || !lds) return EAMFE_EINVAL;
+    *lds = c->lds_rows;
+    return EAMFE_OK;
+}
+
 int eamfe_set_xcd_affinity(eamfe_ctx* c, int on)
 {
     if (!c) return EAMFE_EINVAL;
@@ -1336,7 +1418,6 @@ int eamfe_system_setup(eamfe_ctx* c, int n_rep, const eamfe_replica* in, const d
     HIPCHK(c, hipMemset(c->W_state_d.p, 0, (size_t)n_rep * sizeof(double)));
     HIPCHK(c, hipMemset(c->rebuild_d.p, 0, (size_t)n_rep * sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->flag_pre_d.p, 0, (size_t)(2 * n_rep + 2) * sizeof(int32_t)));
-    HIPCHK(c, hipMemset(c->pending_d.p, 0, sizeof(int32_t)));
     HIPCHK(c, hipMemset(c->row_acc_d.p, 0, (size_t)(n_rep + 3) * sizeof(double)));
     c->have_list = false;
     c->has_kscale = false;
@@ -1773,7 +1854,43 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
           }
         }
     }
+    // at the chosen shape, the list builder: rows from LDS or from global memory
+    // (identical rows; the faster depends on how many atoms a step rebuilds)
+    if (!rc && has_eam && step + 2 < s1) {
+        c->lanes = best_l;
+        c->block = best_b;
+        c->grid = best_g;
+        if ((rc = build_tiles(c))) goto done;
+        const int lds0 = c->lds_rows;
+        double t_b[2] = {1e300, 1e300};
+        for (int lds = 0; lds < 2; ++lds) {
+            c->lds_rows = lds;
+            c->have_list = false;
+            if (hipMemcpyAsync(c->tune_x.p, x, v3, hipMemcpyDeviceToDevice, c->stream) ||
+                hipMemcpyAsync(c->tune_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream)) {
+                rc = fail(c, EAMFE_EDEVICE, "autotune: copy failed");
+                break;
+            }
+            if ((rc = run_switching(c, p, step, step + 2, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr,
+                                    nullptr, nullptr, 0)))
+                break;
+            (void)hipEventRecord(e0, c->stream);
+            if ((rc = run_switching(c, p, step + 2, s1, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr, nullptr,
+                                    nullptr, 0)))
+                break;
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t_b[lds] = ms / (double)(s1 - step - 2);
+        }
+        c->lds_rows = rc ? lds0 : (t_b[1] <= t_b[0] ? 1 : 0);
+        if (!rc) best = std::min(t_b[0], t_b[1]);
+    }
 done:
+    // the lists now follow a trial's positions: the next pass plans and builds
+    // them again at the caller's
+    c->have_list = false;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->timing = timing;
@@ -1901,42 +2018,53 @@ int eamfe_barostat_step(eamfe_ctx* c, const eamfe_barostat* b, int64_t step, dou
     if (!ready(c, true)) return c ? EAMFE_ESTATE : EAMFE_EINVAL;
     if (!b || !x || !v) return fail(c, EAMFE_EINVAL, "barostat_step: null argument");
     if (!(b->tau_p > 0.0) || !(b->beta_T >= 0.0) || !(b->dt >= 0.0) || !std::isfinite(b->p0) ||
-        !std::isfinite(w_eam))
-        return fail(c, EAMFE_EINVAL, "barostat_step: need tau_p > 0, beta_T >= 0, dt >= 0, finite p0 and w_eam");
+        !std::isfinite(w_eam) || (b->aniso != 0 && b->aniso != 1))
+        return fail(c, EAMFE_EINVAL,
+                    "barostat_step: need tau_p > 0, beta_T >= 0, dt >= 0, finite p0 and w_eam, aniso 0 or 1");
     (void)hipSetDevice(c->device);
-    // configurational pressure of U_EAM at x (virial only), then the kinetic
-    // part from the velocities: P = (sum m v^2 + w_eam W) / (3 V) is the
-    // internal pressure of H = w_eam U_EAM
+    // configurational pressure tensor of U_EAM at x (virial only), then the
+    // kinetic part from the velocities: P_aa = (sum m v_a^2 + w_eam W_aa) / V
+    // is the internal pressure of H = w_eam U_EAM along axis a
     std::vector<double> Pc((size_t)c->n_rep * 3);
     OK(eamfe_pressure(c, x, nullptr, Pc.data()));
     std::vector<double> vh((size_t)3 * c->N);
     HIPCHK(c, hipMemcpy(vh.data(), v, vh.size() * sizeof(double), hipMemcpyDeviceToHost));
     const double rl = c->r_cut + c->skin;
-    std::vector<double> mu(c->n_rep), Pint(c->n_rep);
+    std::vector<double> mu((size_t)c->n_rep * 3), Pint((size_t)c->n_rep * 3);
     for (int r = 0; r < c->n_rep; ++r) {
         const RepDesc& R = c->reps[r];
         const double V = R.L[0] * R.L[1] * R.L[2];
-        double mv2 = 0.0;
-        for (int i = R.off; i < R.off + R.n; ++i)
-            for (int d = 0; d < 3; ++d) mv2 += vh[(size_t)d * c->N + i] * vh[(size_t)d * c->N + i];
-        mv2 *= R.mass * mvv2e;
-        const double W = (Pc[3 * r] + Pc[3 * r + 1] + Pc[3 * r + 2]) * V;   // trace of the virial
-        const double P = (mv2 + w_eam * W) / (3.0 * V);
         const double kT = kB * R.T;
-        const double z = barostat_gauss(R.seed, 0u, step, 3u);
-        const double deps = -(b->beta_T / b->tau_p) * (b->p0 - P - kT / V) * b->dt +
-                            std::sqrt(2.0 * kT * b->beta_T * b->dt / (V * b->tau_p)) * z;
-        mu[r] = std::exp(deps / 3.0);
-        Pint[r] = P;
+        double Paa[3];
+        for (int d = 0; d < 3; ++d) {
+            double mv2 = 0.0;
+            for (int i = R.off; i < R.off + R.n; ++i) mv2 += vh[(size_t)d * c->N + i] * vh[(size_t)d * c->N + i];
+            Paa[d] = (mv2 * R.mass * mvv2e + w_eam * Pc[3 * r + d] * V) / V;
+            Pint[3 * r + d] = Paa[d];
+        }
+        double z[3];
+        barostat_gauss3(R.seed, 0u, step, 3u, z);
+        if (b->aniso) {
+            // each edge on its own: eps_a = ln L_a with its own diagonal pressure
+            const double amp = std::sqrt(2.0 * kT * b->beta_T * b->dt / (3.0 * V * b->tau_p));
+            for (int d = 0; d < 3; ++d)
+                mu[3 * r + d] = std::exp(-(b->beta_T / (3.0 * b->tau_p)) * (b->p0 - Paa[d] - kT / V) * b->dt +
+                                         amp * z[d]);
+        } else {
+            const double P = (Paa[0] + Paa[1] + Paa[2]) / 3.0;
+            const double deps = -(b->beta_T / b->tau_p) * (b->p0 - P - kT / V) * b->dt +
+                                std::sqrt(2.0 * kT * b->beta_T * b->dt / (V * b->tau_p)) * z[0];
+            mu[3 * r] = mu[3 * r + 1] = mu[3 * r + 2] = std::exp(deps / 3.0);
+        }
         for (int d = 0; d < 3; ++d)
-            if (!(R.L[d] * mu[r] > 2.0 * rl))
+            if (!(R.L[d] * mu[3 * r + d] > 2.0 * rl))
                 return fail(c, EAMFE_EBOX, "barostat_step: box edge of replica " + std::to_string(r) +
                                                " would fall to 2 (r_cut + skin) or below");
     }
     for (int r = 0; r < c->n_rep; ++r) {
         RepDesc& R = c->reps[r];
         for (int d = 0; d < 3; ++d) {
-            R.L[d] *= mu[r];
+            R.L[d] *= mu[3 * r + d];
             R.invL[d] = 1.0 / R.L[d];
         }
     }

@@ -37,8 +37,10 @@ struct RepDesc {
     int32_t n;          // atoms
     int32_t tile_base;  // first slot of this replica in per-unit partial arrays
     int32_t n_tiles;    // work units of this replica
-    int32_t cell_base;  // first global cell
+    int32_t cell_base;  // first global cell (replicas whose lists are built in global memory)
     int32_t nc[3];      // cells per edge; nc[0] == 0 selects all-pairs lists
+    int32_t lds;        // 1: lists built from LDS by k_rows_lds (no global cells); 0: k_bin / k_list
+    int32_t pad_;
     double L[3];
     double invL[3];
     double T, k, k2, mass;
@@ -85,6 +87,13 @@ struct NeighArgs {
     int N, n_cells, ccap, cap;
     int chunk;                  // candidates staged per wavefront in the row builder (>= ccap)
     int n_rep;
+    const int32_t* lds_list;    // [n_lds] replicas whose lists k_rows_lds builds, in replica order
+    int n_lds;                  // their number (0: none)
+    int n_global;               // replicas whose lists k_bin / k_list build
+    int lds_atoms;              // the largest of them: atoms (records and sorted ids staged per block)
+    int lds_cells;              // and cells (cell starts staged per block)
+    int lds_waves;              // wavefronts per block of k_rows_lds
+    int lds_grid;               // row-building blocks of k_rows_lds (one more block finishes the force pass)
     double rl2;                 // (r_cut + skin)^2
     float rl2_f;                // (r_cut + skin + margin)^2 for the single-precision candidate test
     double half_skin2;          // (skin/2)^2
@@ -114,12 +123,13 @@ struct StepArgs {
     int32_t* rebuild;       // [n_rep]
     int32_t* cell_cnt;      // [n_cells] bin counters (cleared by the density pass after a rebuild)
     int32_t* flag_pre;      // [2 (n_rep + 1)] rebuild prefix (formed by the list pass's first kernel)
-    int32_t* pending;       // [1] 1 while a force pass of a step awaits its finish
     double* row_acc;        // [n_rep + 3] row lengths summed over the step force passes, their count, then
                             // the replicas and the atoms whose lists those passes rebuilt
     int32_t* status;
     const double* lam;      // lambda table [S+1]
-    int64_t* iter;          // device iteration counter (global step index)
+    int64_t* iter;          // device step counter: a pass's step is *iter + it_k
+    int64_t it_k;           // this pass's step offset from the counter (its iteration within a captured graph)
+    int finish_prev;        // density pass: an extra block finishes the force pass of the step before
     int64_t it_first;       // first iteration of this launch sequence: no closing kick
     int64_t it_last;        // last iteration: no new step (only the closing kick)
     double* dHdl_out;       // [n_rep][S] or null
@@ -146,7 +156,7 @@ struct StepArgs {
     int slice_grid;         // blocks of the staged FP32 pair launches (0: records gathered from global memory)
     int stage_atoms;        // records staged per block (atoms of the largest replica)
     int step_kernel;        // 1: integrate; 0: evaluate only (eam_forces)
-    int fix;                // FP32: 2^-32 fixed-point per-atom sums (1) or plain float64 sums of the partials (0)
+    int fix;                // FP32 only: fixed-point per-atom sums and exact replica sums (1), plain float64 sums (0)
     double dt;
     double c1;
     double half_skin2;
@@ -172,19 +182,39 @@ struct AdjointArgs {
     int n_units;                // total work units (replica-major)
 };
 
+// LDS of one block of the LDS row builder (k_rows_lds): the records and
+// sorted ids of up to `atoms` atoms, `cells` + 1 cell starts, and per
+// wavefront a row buffer of `cap` slots.
+constexpr int kRowsAtomsMax = 4096;    // replicas of at most this many atoms (16-bit ids, 64 KB of records)
+constexpr int kRowsCellsMax = 4096;    // and at most this many cells use it
+
+__host__ __device__ inline size_t rows_lds_wave_bytes(int cap)
+{
+    return (size_t)cap * 4;   // the row buffer
+}
+
+__host__ __device__ inline size_t rows_lds_bytes(int atoms, int cells, int cap, int waves)
+{
+    const size_t head = (size_t)atoms * 16 + (((size_t)atoms * 2 + 15) & ~(size_t)15) +
+                        (((size_t)(cells + 1) * 4 + 15) & ~(size_t)15);
+    return head + (size_t)waves * rows_lds_wave_bytes(cap);
+}
+
 // Launchers (eamfe_kernels.hip).  Each returns a hipError_t as int.
 int launch_pack(double4* P, uint4* Q, const double* x, const int32_t* rep_of, const RepDesc* reps, int N,
                 hipStream_t s);
 int launch_unpack(double* x, const double4* P, int N, hipStream_t s);
 int launch_check_displacement(const NeighArgs& a, hipStream_t s);
 // List pass.  Its first kernel also forms the prefix of the flagged replicas
-// and finishes the force pass before it when that is due (st.pending).
+// (the force pass before it is finished by the next density pass).
 int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int block, hipStream_t s);
 int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
 int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
-// per-replica energies, dH/dl, work and the iteration counter after a force
-// pass that no list pass follows
+// per-replica energies, dH/dl and work after a force pass that no density
+// pass of the same range follows
 int launch_finish(const StepArgs& a, hipStream_t s);
+// *iter += by on the stream (the step counter of a captured graph's iterations)
+int launch_advance_iter(int64_t* iter, int64_t by, hipStream_t s);
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s);
 // per-replica mean-squared displacement from x0 with the centre of mass removed -> out[n_rep] (device)
 int launch_msd(const double* x, const double* x0, const RepDesc* reps, int n_rep, int N, double* out, hipStream_t s);

@@ -350,6 +350,22 @@ __device__ __forceinline__ void unit_partial(const double (&vin)[K], double* par
         for (int k = 0; k < K; ++k) part[(size_t)(R.tile_base + idx) * K + k] = v[k];
 }
 
+// Exact replica sums of the fixed-point form: each lane's value is rounded to
+// a multiple of 2^-36 (noise, velocities) or 2^-24 (energies, virials) before
+// its unit partial, so every float64 add of partials and totals is exact while
+// a replica's total stays below 2^17 or 2^29 in magnitude.  The totals are
+// then the same for every grouping of atoms into units, i.e. for every number
+// of lanes per atom.
+constexpr double kGridZ = 68719476736.0, kGridZInv = 1.0 / 68719476736.0;
+constexpr double kGridE = 16777216.0, kGridEInv = 1.0 / 16777216.0;
+
+template <int M, int K>   // the first M of the K values
+__device__ __forceinline__ void on_grid(double (&v)[K], double g, double gi)
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = rint(v[k] * g) * gi;
+}
+
 // A replica's total of the partials written by an earlier kernel: lanes take
 // the units in a fixed stride, then a fixed butterfly; every lane gets it.
 template <int K>
@@ -366,13 +382,13 @@ __device__ __forceinline__ void replica_total(const double* part, const RepDesc&
 // Run body(u) for every unit of this wavefront's stride.  Uniform loop
 // bounds (scalar values) keep the whole body wave-uniform.
 template <typename Body>
-__device__ __forceinline__ void for_each_unit(const int* qoff, int nq, Body&& body)
+__device__ __forceinline__ void for_each_unit(const int* qoff, int nq, int grid, Body&& body)
 {
     const int wpb = (int)(blockDim.x >> 6);
     const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int x = nq > 1 ? (int)(blockIdx.x % (unsigned)nq) : 0;
     const int lb = (int)(blockIdx.x / (unsigned)nq);                 // block index among group x's blocks
-    const int nb = ((int)gridDim.x - x + nq - 1) / nq;             // blocks serving group x
+    const int nb = (grid - x + nq - 1) / nq;                       // blocks serving group x (of the grid's first `grid`)
     const int first = qoff[x], len = qoff[x + 1] - qoff[x];
     for (int u = lb * wpb + wib; u < len; u += nb * wpb) body(first + u);
 }
@@ -402,7 +418,7 @@ __device__ __forceinline__ void run_units(const StepArgs& a, uint4* st, Table&& 
             stage_table();
             __syncthreads();
         }
-        for_each_unit(a.qoff, a.nq, body);
+        for_each_unit(a.qoff, a.nq, (int)gridDim.x - a.finish_prev, body);   // a finish block is the last
     }
 }
 
@@ -463,7 +479,8 @@ __device__ __forceinline__ double3 sep(const RepDesc& R, const double4& a, const
 // in id order, of the members within r_cut + skin of the 5 x 5 x 5 cells
 // around the atom's own, so rows have a fixed order.
 // --------------------------------------------------------------------------
-// Prefix sums over the replicas of the atoms and of the cells to rebuild:
+// Prefix sums over the replicas of the global builder (not k_rows_lds) of
+// the atoms and of the cells to rebuild:
 // pre[r] (atoms of flagged replicas before r), pre[n_rep + 1 + r] (cells of
 // flagged replicas before r), totals at index n_rep and 2 n_rep + 1.  One
 // block (any size, multiple of 64); the list kernels take their work items
@@ -477,7 +494,7 @@ __device__ int flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_re
     for (int base = 0; base < n_rep; base += blockDim.x) {
         const int r = base + threadIdx.x;
         int va = 0, vc = 0;
-        if (r < n_rep && rebuild[r]) {
+        if (r < n_rep && rebuild[r] && !reps[r].lds) {   // replicas of the global builder only
             va = reps[r].n;
             vc = reps[r].nc[0] * reps[r].nc[1] * reps[r].nc[2];
         }
@@ -558,23 +575,18 @@ __device__ __forceinline__ int cell_coord(double x, double L, double invL, int n
     return c >= nc ? nc - 1 : c;
 }
 
-__device__ void finish_body(const StepArgs& a);   // below, with the force pass
+__device__ void finish_body(const StepArgs& a, int64_t it);   // below, with the force pass
 
-// First kernel of a list pass; its blocks take three independent jobs.
-// Block 0 finishes the force pass before it when that is due (replica
-// energies, work, the iteration counter); block 1 forms the prefix of the
-// flagged replicas' atoms and cells that the next two kernels take their
-// work items from; the other blocks bin the atoms of the flagged replicas,
-// one atom per thread with a flag test each (the prefix is not formed yet).
+// First kernel of the global list pass; its blocks take two independent
+// jobs.  Block 0 forms the prefix of the flagged replicas' atoms and cells
+// that the next two kernels take their work items from; the other blocks
+// bin the atoms of the flagged replicas, one atom per thread with a flag
+// test each (the prefix is not formed yet).
 constexpr int kBinBlock = 1024;
 
 __global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
 {
     if (blockIdx.x == 0) {
-        if (*s.pending) finish_body(s);
-        return;
-    }
-    if (blockIdx.x == 1) {
         const int flagged = flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
         if (s.step_kernel && threadIdx.x == 0) {   // rebuild history of the step passes
             s.row_acc[a.n_rep + 1] += (double)flagged;
@@ -582,12 +594,12 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
         }
         return;
     }
-    const int stride = (gridDim.x - 2) * blockDim.x;
-    for (int i = (blockIdx.x - 2) * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+    const int stride = (gridDim.x - 1) * blockDim.x;
+    for (int i = (blockIdx.x - 1) * blockDim.x + threadIdx.x; i < a.N; i += stride) {
         const int r = a.rep_of[i];
         if (!a.rebuild[r]) continue;
         const RepDesc& R = a.reps[r];
-        if (R.nc[0] == 0) continue;   // all-pairs rows: no cells
+        if (R.nc[0] == 0 || R.lds) continue;   // all-pairs rows, or rows built from LDS: no global cells
         const uint4 q = a.Q[i];
         const int c = R.cell_base + (box_cell(q.x, R.nc[0]) * R.nc[1] + box_cell(q.y, R.nc[1])) * R.nc[2] +
                       box_cell(q.z, R.nc[2]);
@@ -819,6 +831,282 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
 }
 
 // --------------------------------------------------------------------------
+// Rows of replicas small enough for one block's LDS (k_rows_lds).  The grid
+// is one block per CU; every block reads the rebuild flags of
+// these replicas, splits the flagged ones into `parts` slices of atoms so
+// that the items fill the grid, and takes items in a fixed stride.  For its
+// item a block stages the replica's records in LDS, sorts its atoms into
+// the cells of the global builder (counting sort by cell, then each cell's
+// members by id) and builds the rows of the item's atoms from LDS alone: the
+// same candidate stream (stencil cells by offset, members by id) and the
+// same test as k_list, so the rows are identical to that builder's.
+// LDS: records [atoms], sorted ids [atoms] (16 bit), cell starts [cells + 1],
+// then per wavefront a row buffer [cap], the stencil's inclusive ends and
+// starts [2][128] and a candidate chunk [kRowsChunk] (16 bit).
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
+{
+    extern __shared__ uint4 lds_rows[];
+    const int lw = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint4* st = lds_rows;
+    uint16_t* ids = (uint16_t*)(st + a.lds_atoms);
+    int* cst = (int*)((char*)ids + (((size_t)a.lds_atoms * 2 + 15) & ~(size_t)15));
+    int* row = (int*)((char*)cst + (((size_t)(a.lds_cells + 1) * 4 + 15) & ~(size_t)15) +
+                      (size_t)w * rows_lds_wave_bytes(a.cap));
+    __shared__ int sh_nf, sh_atoms, sh_rep, sh_part, sh_parts;
+    __shared__ int wsum[16];
+
+    // flagged replicas of this builder: their number and atoms
+    if (w == 0) {
+        int nf = 0, at = 0;
+        for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
+            const int k = k0 + lw;
+            const int r = k < a.n_lds ? a.lds_list[k] : 0;
+            const bool f = k < a.n_lds && a.rebuild[r] != 0;
+            nf += __popcll(__ballot(f));
+            int n = f ? a.reps[r].n : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+            at += n;
+        }
+        if (lw == 0) {
+            sh_nf = nf;
+            sh_atoms = at;
+        }
+    }
+    __syncthreads();
+    const int nf = sh_nf, atoms_f = sh_atoms;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && s.step_kernel) {   // rebuild history of the step passes
+        s.row_acc[a.n_rep + 1] += (double)nf;
+        s.row_acc[a.n_rep + 2] += (double)atoms_f;
+    }
+    if (nf == 0) return;
+    const int G = gridDim.x;
+    // items: each flagged replica cut into parts in proportion to its atoms,
+    // about G items in all; the items are numbered replica by replica
+    auto parts_of = [&](int n) { return max(1, (int)(((long long)n * G) / atoms_f)); };
+    int items = 0;
+    if (w == 0) {
+        for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
+            const int k = k0 + lw;
+            const int r = k < a.n_lds ? a.lds_list[k] : 0;
+            int pr = (k < a.n_lds && a.rebuild[r] != 0) ? parts_of(a.reps[r].n) : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o, 64);
+            items += pr;
+        }
+        if (lw == 0) wsum[0] = items;
+    }
+    __syncthreads();
+    items = wsum[0];
+    __syncthreads();
+    const uint64_t below = (1ull << lw) - 1ull;
+    const float rl2 = a.rl2_f;
+    for (int it = blockIdx.x; it < items; it += G) {
+        // the replica and part of item it
+        if (w == 0) {
+            int seen = 0;
+            for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
+                const int k = k0 + lw;
+                const int r = k < a.n_lds ? a.lds_list[k] : 0;
+                const int pr = (k < a.n_lds && a.rebuild[r] != 0) ? parts_of(a.reps[r].n) : 0;
+                int incl = pr;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o, 64);
+                    if (lw >= o) incl += y;
+                }
+                const int chunk_total = __builtin_amdgcn_readlane(incl, 63);
+                if (it < seen + chunk_total) {   // uniform: the lane whose parts hold it
+                    const bool mine = pr > 0 && it >= seen + incl - pr && it < seen + incl;
+                    const int src = (int)__ffsll((long long)__ballot(mine)) - 1;
+                    const int rsel = __shfl(r, src, 64);
+                    const int first = __shfl(seen + incl - pr, src, 64);
+                    const int psel = __shfl(pr, src, 64);
+                    if (lw == 0) {
+                        sh_rep = rsel;
+                        sh_part = it - first;
+                        sh_parts = psel;
+                    }
+                    break;
+                }
+                seen += chunk_total;
+            }
+        }
+        __syncthreads();
+        const int rr = sh_rep, part = sh_part, parts = sh_parts;
+        const RepDesc& R = a.reps[rr];
+        const int roff = R.off, rn = R.n;
+        const int nc0 = R.nc[0], nc1 = R.nc[1], nc2 = R.nc[2];
+        const int ncell = nc0 * nc1 * nc2;
+        for (int k = threadIdx.x; k < rn; k += blockDim.x) st[k] = a.Q[roff + k];
+        if (nc0 > 0)
+            for (int c = threadIdx.x; c <= ncell; c += blockDim.x) cst[c] = 0;
+        __syncthreads();
+        auto cell_of = [&](const uint4& q) {
+            return (box_cell(q.x, nc0) * nc1 + box_cell(q.y, nc1)) * nc2 + box_cell(q.z, nc2);
+        };
+        if (nc0 > 0) {
+            for (int k = threadIdx.x; k < rn; k += blockDim.x) atomicAdd(&cst[cell_of(st[k])], 1);
+            __syncthreads();
+            // inclusive scan of the counts over the cells: contiguous segments
+            // per thread, then the segment totals across the block
+            {
+                const int per = (ncell + (int)blockDim.x - 1) / (int)blockDim.x;
+                const int c0 = threadIdx.x * per, c1 = min(ncell, c0 + per);
+                int tot = 0;
+                for (int c = c0; c < c1; ++c) tot += cst[c];
+                int incl = tot;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o, 64);
+                    if (lw >= o) incl += y;
+                }
+                if (lw == 63) wsum[w] = incl;
+                __syncthreads();
+                int before = incl - tot;
+                for (int q = 0; q < w; ++q) before += wsum[q];
+                for (int c = c0; c < c1; ++c) {
+                    before += cst[c];
+                    cst[c] = before;
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) cst[ncell] = rn;
+            // scatter: each cell's end pointer walks down to its start
+            for (int k = threadIdx.x; k < rn; k += blockDim.x) {
+                const int pos = atomicSub(&cst[cell_of(st[k])], 1) - 1;
+                ids[pos] = (uint16_t)k;
+            }
+            __syncthreads();
+            // each cell's members in id order
+            for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+                const int b = cst[c], e = cst[c + 1];
+                for (int t = b + 1; t < e; ++t) {
+                    const uint16_t x = ids[t];
+                    int u = t;
+                    while (u > b && ids[u - 1] > x) {
+                        ids[u] = ids[u - 1];
+                        --u;
+                    }
+                    ids[u] = x;
+                }
+            }
+        }
+        __syncthreads();
+        // rows of this item's atoms, one wavefront per atom
+        const int a0 = (int)((long long)rn * part / parts), a1 = (int)((long long)rn * (part + 1) / parts);
+        const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
+                    sz = (float)(R.L[2] * 2.3283064365386963e-10);
+        for (int il = a0 + w; il < a1; il += nw) {
+            const int i = roff + il;
+            const uint4 qi = st[il];
+            auto close_to = [&](const uint4& qj) {
+                const float dx = (float)(int)(qi.x - qj.x) * sx, dy = (float)(int)(qi.y - qj.y) * sy,
+                            dz = (float)(int)(qi.z - qj.z) * sz;
+                return dx * dx + dy * dy + dz * dz < rl2;
+            };
+            int cnt = 0;
+            if (nc0 == 0) {   // all-pairs rows: every other atom in id order
+                for (int s0 = 0; s0 < rn; s0 += 64) {
+                    const int jl = s0 + lw;
+                    const bool acc = jl < rn && jl != il && close_to(st[jl < rn ? jl : il]);
+                    const uint64_t m = __ballot(acc);
+                    const int rank = __popcll(m & below);
+                    if (acc && cnt + rank < a.cap) row[cnt + rank] = roff + jl;
+                    cnt += __popcll(m);
+                }
+            } else {
+                // lane l tests stencil cells l and 64 + l (cells by offset, the
+                // 125 of a 5 x 5 x 5 block), keeping a mask of its members in
+                // range; a prefix sum of the accepted counts over the cells then
+                // gives every accepted member its slot, so the row is the stream
+                // of cells in offset order, members in id order
+                const int cx = box_cell(qi.x, nc0), cy = box_cell(qi.y, nc1), cz = box_cell(qi.z, nc2);
+                int cb[2], cn[2];
+                uint64_t mask[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int q = 64 * h + lw;
+                    cb[h] = 0;
+                    cn[h] = 0;
+                    mask[h] = 0ull;
+                    if (q < kStencil) {
+                        const int ux = (cx + q / 25 - 2 + nc0) % nc0;
+                        const int uy = (cy + (q / 5) % 5 - 2 + nc1) % nc1;
+                        const int uz = (cz + q % 5 - 2 + nc2) % nc2;
+                        const int c = (ux * nc1 + uy) * nc2 + uz;
+                        cb[h] = cst[c];
+                        cn[h] = cst[c + 1] - cb[h];
+                        if (cn[h] > 64) {   // a mask holds 64 members (only overlapping atoms crowd a cell so)
+                            atomicOr(a.status, ST_CELL_OVERFLOW);
+                            cn[h] = 64;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    for (int t0 = 0; t0 < cn[h]; t0 += 4) {   // four members' loads in flight together
+                        int jl[4];
+                        uint4 qj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) jl[u] = t0 + u < cn[h] ? (int)ids[cb[h] + t0 + u] : il;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) qj[u] = st[jl[u]];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (jl[u] != il && close_to(qj[u])) mask[h] |= 1ull << (t0 + u);
+                    }
+                }
+                int base = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int n_acc = __popcll(mask[h]);
+                    int incl = n_acc;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int y = __shfl_up(incl, o, 64);
+                        if (lw >= o) incl += y;
+                    }
+                    int slot = base + incl - n_acc;
+                    for (uint64_t m = mask[h]; m; m &= m - 1ull) {
+                        const int t = (int)__ffsll((long long)m) - 1;
+                        if (slot < a.cap) row[slot] = roff + (int)ids[cb[h] + t];
+                        ++slot;
+                    }
+                    base += __builtin_amdgcn_readlane(incl, 63);
+                }
+                cnt = base;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // pad the last slab with the atom itself (cap is a multiple of 32), then
+            // write the row as whole slabs
+            const int used = cnt < a.cap ? cnt : a.cap;
+            const int pad_end = min((used + 3) & ~3, a.cap);
+            if (used + lw < pad_end) row[used + lw] = i;
+            __builtin_amdgcn_wave_barrier();
+            for (int b = lw; 4 * b < pad_end; b += 64)
+                *(int4*)(a.nbr + ((size_t)b * (size_t)a.N + (size_t)i) * 4) =
+                    make_int4(row[4 * b], row[4 * b + 1], row[4 * b + 2], row[4 * b + 3]);
+            if (lw == 0) {
+                if (cnt > a.cap) {
+                    atomicOr(a.status, ST_NEIGH_OVERFLOW);
+                    cnt = a.cap;
+                }
+                a.nnb[i] = cnt;
+                const double4 pi = a.P[i];
+                a.xref[i] = pi.x;
+                a.xref[a.N + i] = pi.y;
+                a.xref[2 * a.N + i] = pi.z;
+            }
+            __builtin_amdgcn_wave_barrier();   // the row buffer is reused by the next atom
+        }
+        __syncthreads();   // the staged replica is replaced by the next item's
+    }
+}
+
+// --------------------------------------------------------------------------
 // Density pass.  FP32 tables are staged in LDS (32 KB for rho).
 // --------------------------------------------------------------------------
 template <typename real, int T, bool kStage = false, bool kFix = true>
@@ -828,7 +1116,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     constexpr bool kLds = sizeof(real) == 4;
     constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
     const int N = a.N;
-    const int64_t it = a.step_kernel ? *a.iter : 0;
+    const int64_t it = a.step_kernel ? *a.iter + a.it_k : 0;
+    if (a.finish_prev && blockIdx.x == gridDim.x - 1) {   // the extra block: finish the force pass of step it - 1
+        finish_body(a, it - 1);
+        return;
+    }
     const int nr = a.tab.n_r;
     auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
         if constexpr (kLds) {
@@ -948,11 +1240,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 a.xi[2 * N + i] = za;
             }
         }
-        if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
+        if (a.fix_com) {
+            if constexpr (sizeof(real) == 4 && kFix) on_grid<3>(z, kGridZ, kGridZInv);
+            unit_partial<3>(z, a.noise_part, R, tl.idx);
+        }
     }
     // a replica rebuilt in this step: the list pass has read its cell counters,
     // which are cleared here for its next binning
-    if (a.cell_cnt && R.nc[0] > 0 && a.flag_pre[tl.rep + 1] > a.flag_pre[tl.rep]) {
+    if (a.cell_cnt && R.nc[0] > 0 && !R.lds && a.flag_pre[tl.rep + 1] > a.flag_pre[tl.rep]) {
         const int ncell = R.nc[0] * R.nc[1] * R.nc[2];
         for (int c = tl.idx * 64 + wave_lane(); c < ncell; c += R.n_tiles * 64) a.cell_cnt[R.cell_base + c] = 0;
     }
@@ -984,7 +1279,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     constexpr bool kLds = sizeof(real) == 4;
     constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
     const int N = a.N;
-    const int64_t it = a.step_kernel ? *a.iter : 0;
+    const int64_t it = a.step_kernel ? *a.iter + a.it_k : 0;
     const int nr = a.tab.n_r;
     auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
         if constexpr (kLds) {
@@ -997,7 +1292,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
             }
         }
     };
-    if (a.step_kernel && blockIdx.x == 0 && threadIdx.x == 0) *a.pending = 1;   // finish due before the next pass
     // this step's lambda values, read once per block
     const double lam_it = a.step_kernel ? a.lam[it] : 0.0;
     const double lam_next = a.step_kernel && it < a.it_last ? a.lam[it + 1] : 0.0;
@@ -1201,7 +1495,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         }
     }
 
-    unit_partial<3>(e, a.energy_part, R, tl.idx);
+    if constexpr (sizeof(real) == 4 && kFix) on_grid<2>(e, kGridE, kGridEInv);
+    unit_partial<3>(e, a.energy_part, R, tl.idx);   // e[2], a row length, is an integer
     if constexpr (kVir) {   // pressure evaluation: (1/2) pair virial plus m v_a^2 of the atom, per unit
         double pv[3] = {0.0, 0.0, 0.0};
         if (valid && lane == 0) {
@@ -1212,6 +1507,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 pv[c] = 0.5 * wv[c] + vc * vc / R.inv_m;
             }
         }
+        if constexpr (sizeof(real) == 4 && kFix) on_grid<3>(pv, kGridE, kGridEInv);
         unit_partial<3>(pv, a.vir_part, R, tl.idx);
     }
     };   // unit
@@ -1223,9 +1519,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 // iteration counter.  Run by one block of any size (multiple of 64), every
 // thread of which calls it: g lanes per replica (the largest power of two up
 // to 64 that fits the block), so the replicas load in parallel.
-__device__ void finish_body(const StepArgs& a)
+__device__ void finish_body(const StepArgs& a, int64_t it)
 {
-    const int64_t it = a.step_kernel ? *a.iter : 0;
     int g = 64;
     while (g > 1 && g * a.n_rep > (int)blockDim.x) g >>= 1;
     const int grp = (int)threadIdx.x / g, sub = (int)threadIdx.x % g, ngrp = (int)blockDim.x / g;
@@ -1238,9 +1533,24 @@ __device__ void finish_body(const StepArgs& a)
         double tot[3] = {0.0, 0.0, 0.0};
         if (r < a.n_rep) {
             const RepDesc& R = a.reps[r];
-            for (int t = sub; t < R.n_tiles; t += g)
+            // the lane's units t = sub, sub + g, ... in batches of eight: every load of
+            // a batch is issued before the first add, the adds keep the unit order
+            constexpr int kB = 8;
+            for (int t0 = sub; t0 < R.n_tiles; t0 += kB * g) {
+                double p[kB][3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) tot[k] += a.energy_part[(size_t)(R.tile_base + t) * 3 + k];
+                for (int b = 0; b < kB; ++b) {
+                    const int t = t0 + b * g;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        p[b][k] = t < R.n_tiles ? a.energy_part[(size_t)(R.tile_base + t) * 3 + k] : 0.0;
+                }
+#pragma unroll
+                for (int b = 0; b < kB; ++b)
+                    if (t0 + b * g < R.n_tiles)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) tot[k] += p[b][k];
+            }
         }
         for (int o = g / 2; o > 0; o >>= 1)
 #pragma unroll
@@ -1267,19 +1577,28 @@ __device__ void finish_body(const StepArgs& a)
             }
         }
     }
-    __syncthreads();   // every thread has read the counter
-    if (threadIdx.x == 0) {
-        if (a.step_kernel) {
-            *a.iter = it + 1;
-            a.row_acc[a.n_rep] += 1.0;
-        }
-        *a.pending = 0;
-    }
+    if (threadIdx.x == 0 && a.step_kernel) a.row_acc[a.n_rep] += 1.0;   // one more force pass in the history
 }
 
-// Finish of a force pass that no list pass follows: evaluation-only passes,
-// the last pass of a range, and the modes without EAM.
-__global__ __launch_bounds__(1024) void k_finish(StepArgs a) { finish_body(a); }
+// Finish of a force pass that no density pass of the same range follows:
+// evaluation-only passes, the last pass of a range, and the modes without
+// EAM (the other step passes are finished by an extra block of the next
+// density pass, off the path of the list pass).
+__global__ __launch_bounds__(1024) void k_finish(StepArgs a)
+{
+    finish_body(a, a.step_kernel ? *a.iter + a.it_k : 0);
+}
+
+// The device step counter of a captured graph's iterations, advanced once
+// per replay (the graph's kernels read the step as the counter plus their
+// iteration's offset).
+__global__ void k_advance_iter(int64_t* iter, int64_t by) { *iter += by; }
+
+int launch_advance_iter(int64_t* iter, int64_t by, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_iter, dim3(1), dim3(1), 0, s, iter, by);
+    return (int)hipGetLastError();
+}
 
 // --------------------------------------------------------------------------
 // Initial velocities: v = sqrt(kT/m) z(stream 1, step 0), centre of mass removed
@@ -1300,7 +1619,10 @@ __global__ void k_init_v(StepArgs a, int fix_com)
             a.v[c * a.N + i] = z[c];
         }
     }
-    if (fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
+    if (fix_com) {
+        if (a.fix) on_grid<3>(z, kGridZ, kGridZInv);   // the mean only; v keeps its full value
+        unit_partial<3>(z, a.noise_part, R, tl.idx);
+    }
 }
 
 __global__ void k_sub_mean_v(StepArgs a)
@@ -1343,17 +1665,27 @@ int launch_check_displacement(const NeighArgs& a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
+static void allow_lds(const void* f, size_t bytes);
+
 int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int block, hipStream_t s)
 {
     if (a.N <= 0) return 0;
-    const int bin_blocks = 2 + std::min(1024, (a.N + kBinBlock - 1) / kBinBlock);
-    hipLaunchKernelGGL(k_bin, dim3(bin_blocks), dim3(kBinBlock), 0, s, a, st);
     (void)lanes;
     (void)block;
-    // one row buffer and one candidate chunk per wavefront
-    const size_t lds = (size_t)((kListBlock / 64) * (a.cap + a.chunk)) * sizeof(int);
-    if (lds > 64 * 1024) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_list, dim3(kListGrid), dim3(kListBlock), lds, s, a, a.n_rep);
+    if (a.n_global > 0) {
+        const int bin_blocks = 1 + std::min(1024, (a.N + kBinBlock - 1) / kBinBlock);
+        hipLaunchKernelGGL(k_bin, dim3(bin_blocks), dim3(kBinBlock), 0, s, a, st);
+        // one row buffer and one candidate chunk per wavefront
+        const size_t lds = (size_t)((kListBlock / 64) * (a.cap + a.chunk)) * sizeof(int);
+        if (lds > 64 * 1024) return (int)hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_list, dim3(kListGrid), dim3(kListBlock), lds, s, a, a.n_rep);
+    }
+    if (a.n_lds > 0) {
+        const size_t lds = rows_lds_bytes(a.lds_atoms, a.lds_cells, a.cap, a.lds_waves);
+        const void* f = reinterpret_cast<const void*>(&k_rows_lds);
+        allow_lds(f, lds);
+        hipLaunchKernelGGL(k_rows_lds, dim3(a.lds_grid), dim3(64 * a.lds_waves), lds, s, a, st);
+    }
     return (int)hipGetLastError();
 }
 
@@ -1457,13 +1789,15 @@ static void density_one(const StepArgs& a, int block, hipStream_t s)
             const size_t sh = lds_bytes<real>(a, 1) + (size_t)a.stage_atoms * sizeof(uint4);
             const void* f = reinterpret_cast<const void*>(&k_density<real, T, true, kFix>);
             allow_lds(f, sh);
-            hipLaunchKernelGGL((k_density<real, T, true, kFix>), dim3(a.slice_grid), dim3(block), sh, s, a);
+            hipLaunchKernelGGL((k_density<real, T, true, kFix>), dim3(a.slice_grid + a.finish_prev), dim3(block), sh,
+                               s, a);
             return;
         }
     }
     const size_t sh = lds_bytes<real>(a, 1);
     const void* f = reinterpret_cast<const void*>(&k_density<real, T, false, kFix>);
-    hipLaunchKernelGGL((k_density<real, T, false, kFix>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, a);
+    hipLaunchKernelGGL((k_density<real, T, false, kFix>), dim3(pair_grid(a, f, block, sh) + a.finish_prev),
+                       dim3(block), sh, s, a);
 }
 
 template <typename real, int T, bool kFix>

@@ -43,7 +43,8 @@ class Protocol(C.Structure):
 
 
 class Barostat(C.Structure):
-    _fields_ = [("p0", C.c_double), ("tau_p", C.c_double), ("beta_T", C.c_double), ("dt", C.c_double)]
+    _fields_ = [("p0", C.c_double), ("tau_p", C.c_double), ("beta_T", C.c_double), ("dt", C.c_double),
+                ("aniso", C.c_int32), ("pad_", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -74,6 +75,8 @@ def lib():
         "eamfe_set_graph": (i32, [vp, i32]),
         "eamfe_get_grid": (i32, [vp, C.POINTER(i32)]),
         "eamfe_set_xcd_affinity": (i32, [vp, i32]),
+        "eamfe_set_list_builder": (i32, [vp, i32]),
+        "eamfe_get_list_builder": (i32, [vp, C.POINTER(i32)]),
         "eamfe_check": (i32, [vp]),
         "eamfe_set_kernel_timing": (i32, [vp, i32, i32]),
         "eamfe_autotune": (i32, [vp, C.POINTER(Protocol), i64, vp, vp, i32, C.POINTER(i32), C.POINTER(i32), _dp]),
@@ -333,6 +336,16 @@ class Context:
         self._c(self._lib.eamfe_get_grid(self._h, C.byref(g)))
         return g.value
 
+    def set_list_builder(self, lds: bool):
+        """True: rows of replicas that fit one block's LDS built from LDS (default); False: all in global memory."""
+        self._c(self._lib.eamfe_set_list_builder(self._h, int(bool(lds))))
+
+    def get_list_builder(self):
+        """"lds" or "global": the builder of the neighbour rows."""
+        v = C.c_int()
+        self._c(self._lib.eamfe_get_list_builder(self._h, C.byref(v)))
+        return "lds" if v.value else "global"
+
     def set_xcd_affinity(self, on: bool):
         self._c(self._lib.eamfe_set_xcd_affinity(self._h, int(bool(on))))
 
@@ -377,11 +390,11 @@ class Context:
     def barostat_step(self, b: Barostat, step, w_eam, x, v):
         """One stochastic cell-rescaling move at the step boundary ``step``
         (``w_eam``: weight of U_EAM in the Hamiltonian there): scales x,
-        v and the boxes in place; returns (mu[n_rep], P[n_rep] internal
-        pressures, eV/A^3)."""
-        mu, P = np.zeros(self.n_rep), np.zeros(self.n_rep)
+        v and the boxes in place; returns (mu[n_rep, 3] per-axis factors,
+        P[n_rep, 3] diagonal internal pressures, eV/A^3)."""
+        mu, P = np.zeros((self.n_rep, 3)), np.zeros((self.n_rep, 3))
         self._r(self._lib.eamfe_barostat_step, C.byref(b), int(step), float(w_eam), _ptr(x), _ptr(v),
-                                              mu.ctypes.data_as(_dp), P.ctypes.data_as(_dp))
+                mu.ctypes.data_as(_dp), P.ctypes.data_as(_dp))
         return mu, P
 
     def boxes(self):

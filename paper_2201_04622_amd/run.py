@@ -85,7 +85,7 @@ def fl_results(reps, p, W):
         jf, jfe = E.jarzynski(Wf[rows], r0.T)
         jb, jbe = E.jarzynski(Wb[rows], r0.T)
         out.append({"kind": r0.kind, "cells": list(r0.dims), "a": r0.a, "T": r0.T, "k": r0.k, "atoms": N,
-                    "vacuum": r0.vacuum, "realizations": len(rows), "F0_per_atom": F0 / N,
+                    "vacuum": r0.vacuum, "realizations": len(rows), "F0": F0, "F0_per_atom": F0 / N,
                     "F0_err_per_atom": err / N, "E_diss_per_atom": Ed / N,
                     "F0_jarzynski_fwd_per_atom": (FE + cm - jf) / N, "F0_jarzynski_fwd_err": jfe / N,
                     "F0_jarzynski_bwd_per_atom": (FE + cm + jb) / N, "F0_jarzynski_bwd_err": jbe / N,
@@ -159,7 +159,7 @@ def run_workload(name, stable=False, precision=E.FP32, skin=0.3, fl_companion=(2
         Wfl, fstats = _run(ctx, pf, x, v, n_eq + 2 * n_sw + n_hold)
         ctx.close()
         fl_sys, _ = fl_results(creps, pf, Wfl)
-        F0_T0 = fl_sys[0]["F0_per_atom"] * reps[0].natoms if len(fl_sys) == 1 else None
+        F0_T0 = fl_sys[0]["F0"] if len(fl_sys) == 1 else None   # the system's F0 itself, not per atom times N
         if F0_T0 is None:
             raise ValueError("run: the replicas of an RS scan must be realizations of one system")
         ctx, x, v = _context(reps, precision, skin)

@@ -86,7 +86,7 @@ def _fake_run(force_ms, force_n, steps=20):
             "kt": {"density": (0.0, 0), "force": (force_ms, force_n), "lists": (0.0, 0)},
             "stride": 10, "mean_nl": 70.0, "passes": steps, "rebuilt_reps": 3, "rebuilt_atoms": 5000,
             "end_nl": 71.0, "max_nl": 80, "cap": 160, "launch": (2, 1024), "tuned": (2, 1024, 0.08),
-            "desc": "64 replicas"}
+            "desc": "64 replicas", "list_builder": "global"}
 
 
 class _Args:
@@ -104,6 +104,7 @@ def test_timing_stride_samples_every_short_run(bench):
 def test_result_line_with_the_driver_step_counts(bench):
     out = bench.result_line(_Args, _fake_run(0.066, 2), None, None)
     assert out["steps"] == 20 and out["warmup"] == 5
+    assert out["config"]["list_builder"] == "global"
     assert out["ms_per_step"] == pytest.approx(1.6 / 20)
     assert out["value"] == pytest.approx(113090 * 20 / 1.6e-3)
     rf = out["roofline"]

@@ -56,8 +56,10 @@ def test_npt_trajectory_matches_oracle(oracle_lib, opot, prec):
         say(f"replica {r}: box {tr.boxes[-1, r]} vs {boxes[-1]}, |dx| {np.abs(xr - xo).max():.1e}")
         assert len(mus) == len(tr.mu) == (S - 1) // every
         assert np.abs(tr.boxes[:, r] / boxes - 1).max() < (1e-12 if prec == FP64 else 1e-6)
-        assert np.abs(tr.mu[:, r] / mus - 1).max() < (1e-12 if prec == FP64 else 1e-6)
-        assert np.abs(tr.pressure[:, r] - Ps).max() < (1e-9 if prec == FP64 else 1e-3) * np.abs(Ps).max()
+        assert np.all(tr.mu[:, r, 0] == tr.mu[:, r, 1]) and np.all(tr.mu[:, r, 0] == tr.mu[:, r, 2])
+        assert np.abs(tr.mu[:, r, 0] / mus - 1).max() < (1e-12 if prec == FP64 else 1e-6)
+        Pg = tr.pressure[:, r].mean(axis=-1)
+        assert np.abs(Pg - Ps).max() < (1e-9 if prec == FP64 else 1e-3) * np.abs(Ps).max()
         assert np.abs(xr - xo).max() < tol, r
         assert np.abs(vr - vo).max() < tol * 100, r
         assert np.abs(Wg[r] - Wo).max() < tol * max(1.0, np.abs(Wo).max()), r
@@ -203,3 +205,86 @@ def test_barostat_rejects_bad_input_and_too_small_boxes():
     assert np.array_equal(ctx.boxes(), L)
     assert torch.equal(x, xs) and torch.equal(v, vs)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_orthorhombic_npt_trajectory_matches_oracle(oracle_lib, opot, prec):
+    """The orthorhombic move (each edge on its own) on an hcp cell started at
+    the ideal c/a and a strained bcc cell, reversible scaling from 1 to 0.8
+    and back with a move every 10 steps: per-axis boxes, factors and
+    pressures, positions, velocities and work agree with the oracle on the
+    same noise."""
+    import torch
+
+    import paper_2201_04622_amd.barostat as B
+    import paper_2201_04622_amd.eamfe as E
+    from oracle import barostat as OB
+    say(f"orthorhombic npt trajectory prec={prec}")
+    reps = [I.Replica("hcp", 0, 1.80, 400.0, 0.0, 21, cells=(7, 4, 4)),
+            I.Replica("bcc", 0, I.A_BCC_STABLE * 1.01, 300.0, 0.0, 22, cells=(6, 7, 6))]
+    ctx, x0, arrs = make_ctx(reps, prec, 2, 256)
+    n_eq, n_sw, n_hold = 10, 40, 10
+    p = E.protocol("rs", n_eq, n_sw, n_hold, 0, lambda_f=0.8, skin=0.3)
+    S = n_eq + 2 * n_sw + n_hold
+    every, p0, tau_p, beta_T = 10, 0.0, 0.1, 1.0
+    b = B.barostat(p0, tau_p, beta_T, 0.001, every, aniso=True)
+    x = x0.clone()
+    v = torch.zeros_like(x)
+    ctx.init_velocities(v, True)
+    v_init = E.from_soa(v)
+    W = torch.zeros(len(reps), S, dtype=torch.float64, device="cuda")
+    tr = B.run_npt(ctx, p, x, v, 0, S, every, b, W_out=W)
+    ctx.close()
+    lam = oracle_lib.schedule("rs", n_eq, n_sw, n_hold, 0, lambda_f=0.8)
+    xg, vg, Wg = E.from_soa(x), E.from_soa(v), W.cpu().numpy()
+    tol = 1e-9 if prec == FP64 else 2e-3
+    for r, (rep, xr, vr, vi) in enumerate(zip(reps, split(xg, ctx.offsets), split(vg, ctx.offsets),
+                                               split(v_init, ctx.offsets))):
+        po = oracle_lib.RunParams(mode="rs", T=rep.T, k=0.0, seed=rep.seed, mass=rep.mass)
+        xo, vo = rep.sites(), vi.copy()
+        boxes, mus, Ps, Wo = OB.run_npt(opot, po, rep.sites(), rep.box, xo, vo, lam, every, p0, tau_p, beta_T,
+                                        aniso=True)
+        say(f"replica {r}: box {tr.boxes[-1, r]} vs {boxes[-1]}, |dx| {np.abs(xr - xo).max():.1e}")
+        assert tr.mu.shape[1:] == (len(reps), 3) and mus.shape == (len(tr.mu), 3)
+        assert np.abs(tr.boxes[:, r] / boxes - 1).max() < (1e-12 if prec == FP64 else 1e-6)
+        assert np.abs(tr.mu[:, r] / mus - 1).max() < (1e-12 if prec == FP64 else 1e-6)
+        assert np.abs(tr.pressure[:, r] - Ps).max() < (1e-9 if prec == FP64 else 1e-3) * np.abs(Ps).max()
+        assert np.abs(xr - xo).max() < tol, r
+        assert np.abs(vr - vo).max() < tol * 100, r
+        assert np.abs(Wg[r] - Wo).max() < tol * max(1.0, np.abs(Wo).max()), r
+        # the edges moved by different factors
+        assert np.ptp(np.log(tr.boxes[-1, r] / rep.box)) > 1e-4
+
+
+def test_orthorhombic_barostat_relaxes_hcp_c_over_a():
+    """hcp at 10 K and p0 = 0, started at the ideal c/a = sqrt(8/3): under the
+    orthorhombic move c/a relaxes to that of lattice.zero_stress_hcp (the
+    zero-stress cell from fixed-volume runs) within 1e-3, and a to its a;
+    the isotropic move keeps the ideal c/a."""
+    import torch
+
+    import paper_2201_04622_amd.barostat as B
+    import paper_2201_04622_amd.eamfe as E
+    import paper_2201_04622_amd.lattice as LT
+    T, cells = 10.0, (7, 4, 5)   # every edge above 2 (r_c + skin) at the trial cells too
+    zs = LT.zero_stress_hcp(cells, T, 1.801, 1.56)
+    a_zs = zs.a
+    res = {}
+    for aniso in (True, False):
+        reps = [I.Replica("hcp", 0, a_zs * 1.003, T, 0.0, 40 + s, cells=cells) for s in range(4)]
+        ctx, x0, _ = make_ctx(reps, FP32, 2, 256)
+        p = E.protocol("rs", 6000, 1, 0, 0, lambda_f=1.0, skin=0.3)
+        x = x0.clone()
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        tr = B.run_npt(ctx, p, x, v, 0, 6000, 10, B.barostat(0.0, 0.1, 1.0, 0.001, 10, aniso=aniso))
+        ctx.close()
+        late = tr.boxes[len(tr.boxes) // 2:]
+        a = late[:, :, 0] / cells[0]
+        q = late[:, :, 2] / cells[2] / a
+        res[aniso] = (a.mean(), q.mean())
+    say(f"zero-stress cell: a {a_zs:.5f} c/a {zs.c_over_a:.5f}; orthorhombic barostat: a {res[True][0]:.5f} "
+        f"c/a {res[True][1]:.5f}; isotropic: c/a {res[False][1]:.5f}")
+    assert abs(res[True][1] - zs.c_over_a) < 1e-3
+    assert abs(res[True][0] / a_zs - 1) < 1e-3
+    assert abs(res[False][1] - np.sqrt(8.0 / 3.0)) < 1e-9
