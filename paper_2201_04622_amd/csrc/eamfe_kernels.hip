@@ -1281,14 +1281,22 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter + a.it_k : 0;
     const int nr = a.tab.n_r;
-    auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
+    // FP32: the table in LDS once per block; its wavefronts then take units.
+    // In LDS the two 16-byte halves of an interval's record (phi's
+    // coefficients, rho's slope coefficients) sit in two arrays of nr entries,
+    // so the random reads of each half spread over every bank, not over the
+    // even or the odd 16-byte bank groups only.
+    auto stage_table = [&]() {
         if constexpr (kLds) {
             const float4* g = (const float4*)a.tab.pair;
-            for (int k = threadIdx.x; k < 2 * (nr - 1); k += blockDim.x) lds_tab[k] = g[k];
+            for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) {
+                lds_tab[k] = g[2 * k];
+                lds_tab[nr + k] = g[2 * k + 1];
+            }
             if (threadIdx.x == 0) {   // padding interval: phi(r_cut), zero slopes
                 const float4 c = g[2 * (nr - 2)];
-                lds_tab[2 * (nr - 1)] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
-                lds_tab[2 * (nr - 1) + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
+                lds_tab[2 * nr - 1] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
     };
@@ -1352,7 +1360,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
             for (int s = 0; s < SB; ++s) {
                 real ua, ub, uc, ud, wb, wc, wd;
                 if constexpr (kLds) {
-                    const float4 u = lds_tab[2 * m[s]], w = lds_tab[2 * m[s] + 1];
+                    const float4 u = lds_tab[m[s]], w = lds_tab[nr + m[s]];
                     ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
                 } else {
                     decltype(Tab<real>::ld4(a.tab.rho, 0)) u, w;
