@@ -120,7 +120,7 @@ def measured_issue(kernel, workload, prec, launch, skin):
 
 
 def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None, stride=None, graph=0,
-            list_builder="auto"):
+            list_builder="auto", stable=False):
     """Run warmup + steps steps of a workload's protocol on the GPU; the
     last `steps` are timed with HIP events around one run_switching call on
     the library's stream (torch's current stream).  Inside the timed region
@@ -131,7 +131,7 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     import paper_2201_04622_amd.eamfe as E
     from paper_2201_04622_amd import inputs as I
 
-    wl = I.workload(workload)
+    wl = I.workload(workload, stable=stable)
     sch = wl.schedule
     # extend the trailing hold so the protocol covers warm-up + timed steps
     need = warmup + steps
@@ -290,7 +290,51 @@ def cpu_baseline(target_s=8.0):
     }
 
 
-def result_line(args, main_run, plain, cpu):
+# The other workloads, each a bounded run of its own protocol from the lattice
+# start (warm-up untimed): name, workload, stable lattice, precision, timed
+# steps, warm-up steps, graph iterations (0: eager), skin (None: the bench's;
+# the stable lattice's smallest boxes, 11.79 A, take at most 0.59 A).  The
+# graph/eager pair times without sampled kernel events, which a captured step
+# does not take.
+CONFIGS = (
+    ("batch64_stable_fp32", "batch64", True, "fp32", 4000, 2000, 0, 0.45),
+    ("batch64_fp64", "batch64", False, "fp64", 1000, 500, 0, None),
+    ("batch64_fp32_eager", "batch64", False, "fp32", 4000, 2000, 0, None),
+    ("batch64_fp32_graph", "batch64", False, "fp32", 4000, 2000, 64, None),
+    ("rs_scan_fp32", "rs_scan", False, "fp32", 2000, 1000, 0, None),
+    ("fl_large_fp32", "fl_large", False, "fp32", 400, 200, 0, None),
+)
+
+
+def config_record(name, run, prec, workload, skin, graph):
+    """Summary of one extra configuration's run_gpu record."""
+    rf = None if graph or name.endswith("_eager") else roofline(run, prec, workload, skin)
+    return {
+        "workload": f"{name}: {run['desc']}", "replicas": run["n_rep"], "atoms": run["natoms"],
+        "value": run["natoms"] * run["steps"] / (run["ms"] / 1e3), "unit": "atom-steps/s",
+        "steps": run["steps"], "ms_per_step": run["ms"] / run["steps"],
+        "mean_neighbour_row": round(run["mean_nl"], 2),
+        "launch": {"lanes_per_atom": run["launch"][0], "block_threads": run["launch"][1]},
+        "list_builder": run["list_builder"], "graph_iterations": graph, "skin": skin,
+        "force_roofline_frac": None if rf is None else rf["frac"],
+        "force_avg_launch_us": None if rf is None else rf["avg_launch_us"],
+    }
+
+
+def run_configs(skin):
+    out = {}
+    for name, wl, stable, prec, steps, warmup, graph, sk in CONFIGS:
+        sk = skin if sk is None else sk
+        plain = graph or name.endswith("_eager")
+        run = run_gpu(wl, prec, steps, warmup, 0, 0, True, sk, stride=0 if plain else None, graph=graph,
+                      stable=stable)
+        out[name] = config_record(name, run, prec, wl, sk, graph)
+    g, e = out["batch64_fp32_graph"], out["batch64_fp32_eager"]
+    out["graph_over_eager"] = g["value"] / e["value"]
+    return out
+
+
+def result_line(args, main_run, plain, cpu, configs=None):
     """The bench's one JSON line from the measured legs (no GPU calls here)."""
     value = main_run["natoms"] * main_run["steps"] / (main_run["ms"] / 1e3)
     kt = main_run["kt"]
@@ -330,6 +374,7 @@ def result_line(args, main_run, plain, cpu):
         "roofline": roofline(main_run, args.precision, args.workload, args.skin),
         "fp64_plain_single_replica": plain,
         "cpu_baseline": cpu,
+        "other_configs": configs,
     }
     if plain:
         out["batched_fp32_over_plain_fp64"] = value / plain["value"]
@@ -356,6 +401,7 @@ def main():
                          "(auto: the autotuner's choice, else LDS)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' bounded runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -386,8 +432,9 @@ def main():
             "workload": "one FL replica, bcc 10^3 (2000 atoms), T=1400 K, k=3, FP64, autotuned launch",
             "ms_per_step": pr["ms"] / 2000,
         }
+    configs = None if args.no_configs else run_configs(args.skin)
     cpu = None if args.no_cpu else cpu_baseline()
-    print(json.dumps(result_line(args, main_run, plain, cpu)), flush=True)
+    print(json.dumps(result_line(args, main_run, plain, cpu, configs)), flush=True)
 
 
 if __name__ == "__main__":

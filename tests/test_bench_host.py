@@ -129,3 +129,16 @@ def test_cpu_baseline_reports_threads_model_and_both_legs(bench):
     assert 1 <= cpu["cores"] <= bench.CPU_THREADS_MAX
     assert cpu["value"] > 0 and cpu["single_core"]["value"] > 0 and cpu["single_core"]["cores"] == 1
     assert cpu["host"]["threads_available"] >= 1 and isinstance(cpu["host"]["model"], str)
+
+
+def test_config_records_and_graph_ratio(bench):
+    run = _fake_run(0.066, 2)
+    rec = bench.config_record("batch64_fp32_graph", run, "fp32", "batch64", 0.65, 64)
+    assert rec["force_roofline_frac"] is None and rec["graph_iterations"] == 64   # no kernel events in a graph
+    rec = bench.config_record("rs_scan_fp32", run, "fp32", "rs_scan", 0.65, 0)
+    assert rec["force_roofline_frac"] > 0 and rec["value"] == pytest.approx(113090 * 20 / 1.6e-3)
+    names = [c[0] for c in bench.CONFIGS]
+    assert "batch64_fp32_graph" in names and "batch64_fp32_eager" in names
+    out = bench.result_line(_Args, run, None, None, {"x": rec})
+    assert out["other_configs"]["x"]["workload"].startswith("rs_scan_fp32")
+    json.dumps(out)
