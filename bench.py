@@ -125,7 +125,7 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     last `steps` are timed with HIP events around one run_switching call on
     the library's stream (torch's current stream).  Inside the timed region
     the force pass of the first timed iteration and then of every
-    stride-th one is bracketed by its own event pair (stride 0: none)."""
+    stride-th one is stamped with its own start and end (stride 0: none)."""
     import torch
 
     import paper_2201_04622_amd.eamfe as E

@@ -219,15 +219,16 @@ int eamfe_set_xcd_affinity(eamfe_ctx* ctx, int on);
  * (EAMFE_ENEIGH_OVERFLOW ...), clearing it. */
 int eamfe_check(eamfe_ctx* ctx);
 
-/* Time kernel launches with HIP events recorded around them on the context's
- * stream: the first iteration run after this call and then every
- * `stride`-th iteration (counted over the iterations the stepping calls run,
- * so any range of at least one iteration is sampled); stride 0 stops.
- * `kinds` selects the kernels timed: bit 0 the density pass, bit 1 the force
- * pass, bit 2 the neighbour-list rebuild sequence (0 = all three).  An event
- * pair adds a few microseconds of stream time, so a stride of tens and one
- * kind keep the timed work essentially unperturbed.  Each call resets the
- * accumulators. */
+/* Time kernel launches with HIP events: the first iteration run after this
+ * call and then every `stride`-th iteration (counted over the iterations the
+ * stepping calls run, so any range of at least one iteration is sampled);
+ * stride 0 stops.  `kinds` selects the kernels timed: bit 0 the density
+ * pass, bit 1 the force pass (each stamped with the kernel's own start and
+ * end by HIP's extended launch), bit 2 the neighbour-list rebuild sequence
+ * (events recorded around its kernels on the context's stream; 0 = all
+ * three).  A sampled launch costs the stream a few microseconds, so a stride
+ * of tens and one kind keep the timed work essentially unperturbed.  Each
+ * call resets the accumulators. */
 int eamfe_set_kernel_timing(eamfe_ctx* ctx, int stride, int kinds);
 
 /* Synchronise and return the summed event times (ms) and launch counts of

@@ -931,18 +931,43 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
     return EAMFE_OK;
 }
 
-// Record a timing event (kind: 0 density, 1 force, 2 lists; end = 0 start, 1 stop).
+// Timing events of a sampled launch (kind: 0 density, 1 force, 2 lists).
+// mark records one on the stream (end = 0 start, 1 stop), around the list
+// pass's kernels; stamps hands out a pair for a pair kernel to stamp with
+// its own start and end (null pair: this launch is not sampled).
+int next_event(eamfe_ctx* c, hipEvent_t* e)
+{
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t n;
+        HIPCHK(c, hipEventCreate(&n));
+        c->ev_pool.push_back(n);
+    }
+    *e = c->ev_pool[c->ev_used++];
+    return EAMFE_OK;
+}
+
+bool sampled(const eamfe_ctx* c, int kind)
+{
+    return c->timing && c->timing_now && (c->timing_kinds & (1 << kind));
+}
+
 int mark(eamfe_ctx* c, int kind, int end)
 {
-    if (!c->timing || !c->timing_now || !(c->timing_kinds & (1 << kind))) return EAMFE_OK;
-    if (c->ev_used == c->ev_pool.size()) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->ev_pool.push_back(e);
-    }
+    if (!sampled(c, kind)) return EAMFE_OK;
     if (!end) c->ev_kind.push_back(kind);
-    HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used++], c->stream));
+    hipEvent_t e;
+    OK(next_event(c, &e));
+    HIPCHK(c, hipEventRecord(e, c->stream));
     return EAMFE_OK;
+}
+
+int stamps(eamfe_ctx* c, int kind, hipEvent_t* t0, hipEvent_t* t1)
+{
+    *t0 = *t1 = nullptr;
+    if (!sampled(c, kind)) return EAMFE_OK;
+    c->ev_kind.push_back(kind);
+    OK(next_event(c, t0));
+    return next_event(c, t1);
 }
 
 // Iterations it_first .. it_last of a protocol starting from packed
@@ -973,19 +998,18 @@ int one_iteration(eamfe_ctx* c, StepArgs& a, double4* cur, double4* nxt, bool ha
     a.Qn = Q_of(c, nxt);
     a.rho_out = sample ? (double*)c->rho_d.p : nullptr;
     a.finish_prev = finish_prev ? 1 : 0;
-    OK(mark(c, 0, 0));
-    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, st));
-    OK(mark(c, 0, 1));
+    hipEvent_t t0, t1;
+    OK(stamps(c, 0, &t0, &t1));
+    LCHK(c, launch_density(a, c->precision, c->lanes, c->block, st, t0, t1));
     a.finish_prev = 0;
     if (sample) {
         OK(adjoint_at(c, cur, c->adj_w.empty() ? nullptr : c->adj_w.data(), c->adj_reduce, c->adj_out,
                       (unsigned long long*)c->bins_d.p, (double*)c->adj_scratch_d.p));
         ++c->adj_samples;
     }
-    OK(mark(c, 1, 0));
-    LCHK(c, launch_force(a, c->precision, c->lanes, c->block, st));
+    OK(stamps(c, 1, &t0, &t1));
+    LCHK(c, launch_force(a, c->precision, c->lanes, c->block, st, t0, t1));
     if (!has_eam) LCHK(c, launch_finish(a, st));
-    OK(mark(c, 1, 1));
     return EAMFE_OK;
 }
 

@@ -208,8 +208,11 @@ int launch_check_displacement(const NeighArgs& a, hipStream_t s);
 // List pass.  Its first kernel also forms the prefix of the flagged replicas
 // (the force pass before it is finished by the next density pass).
 int launch_neigh_rebuild(const NeighArgs& a, const StepArgs& st, int lanes, int block, hipStream_t s);
-int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
-int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s);
+// t0, t1 (optional): events stamped with the pair kernel's own start and end
+int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
+int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s, hipEvent_t t0 = nullptr,
+                 hipEvent_t t1 = nullptr);
 // per-replica energies, dH/dl and work after a force pass that no density
 // pass of the same range follows
 int launch_finish(const StepArgs& a, hipStream_t s);

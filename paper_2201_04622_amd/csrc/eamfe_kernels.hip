@@ -26,6 +26,8 @@
 // partials in a fixed order, so runs are bitwise reproducible.
 #include "eamfe_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <vector>
 
 namespace eamfe {
@@ -1789,33 +1791,49 @@ static bool staged(const StepArgs& a)
     return sizeof(real) == 4 && a.has_eam && a.slice_grid > 0;
 }
 
+// Events stamped with a pair kernel's own start and end (HIP's extended
+// launch), for sampled timing; null events: a plain launch.
+struct Stamp {
+    hipEvent_t t0, t1;
+};
+
+template <typename K>
+static void launch_pair(K kernel, dim3 grid, dim3 block, size_t sh, hipStream_t s, const Stamp& ts,
+                        const StepArgs& a)
+{
+    if (ts.t0)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)sh, s, ts.t0, ts.t1, 0u, a);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, sh, s, a);
+}
+
 template <typename real, int T, bool kFix>
-static void density_one(const StepArgs& a, int block, hipStream_t s)
+static void density_one(const StepArgs& a, int block, hipStream_t s, const Stamp& ts)
 {
     if constexpr (sizeof(real) == 4) {
         if (staged<real>(a)) {
             const size_t sh = lds_bytes<real>(a, 1) + (size_t)a.stage_atoms * sizeof(uint4);
             const void* f = reinterpret_cast<const void*>(&k_density<real, T, true, kFix>);
             allow_lds(f, sh);
-            hipLaunchKernelGGL((k_density<real, T, true, kFix>), dim3(a.slice_grid + a.finish_prev), dim3(block), sh,
-                               s, a);
+            launch_pair(k_density<real, T, true, kFix>, dim3(a.slice_grid + a.finish_prev), dim3(block), sh, s, ts,
+                        a);
             return;
         }
     }
     const size_t sh = lds_bytes<real>(a, 1);
     const void* f = reinterpret_cast<const void*>(&k_density<real, T, false, kFix>);
-    hipLaunchKernelGGL((k_density<real, T, false, kFix>), dim3(pair_grid(a, f, block, sh) + a.finish_prev),
-                       dim3(block), sh, s, a);
+    launch_pair(k_density<real, T, false, kFix>, dim3(pair_grid(a, f, block, sh) + a.finish_prev), dim3(block), sh,
+                s, ts, a);
 }
 
 template <typename real, int T, bool kFix>
-static void force_one(const StepArgs& a, int block, hipStream_t s)
+static void force_one(const StepArgs& a, int block, hipStream_t s, const Stamp& ts)
 {
     if (a.vir_part) {   // pressure evaluation (not a step): the persistent form with the virial
         const size_t sh = lds_bytes<real>(a, 2);
         const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, true, kFix>);
-        hipLaunchKernelGGL((k_force<real, T, false, true, kFix>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh,
-                           s, a);
+        launch_pair(k_force<real, T, false, true, kFix>, dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, ts,
+                    a);
         return;
     }
     if constexpr (sizeof(real) == 4) {
@@ -1823,61 +1841,60 @@ static void force_one(const StepArgs& a, int block, hipStream_t s)
             const size_t sh = lds_bytes<real>(a, 2) + (size_t)a.stage_atoms * sizeof(uint4);
             const void* f = reinterpret_cast<const void*>(&k_force<real, T, true, false, kFix>);
             allow_lds(f, sh);
-            hipLaunchKernelGGL((k_force<real, T, true, false, kFix>), dim3(a.slice_grid), dim3(block), sh, s, a);
+            launch_pair(k_force<real, T, true, false, kFix>, dim3(a.slice_grid), dim3(block), sh, s, ts, a);
             return;
         }
     }
     const size_t sh = lds_bytes<real>(a, 2);
     const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, false, kFix>);
-    hipLaunchKernelGGL((k_force<real, T, false, false, kFix>), dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s,
-                       a);
+    launch_pair(k_force<real, T, false, false, kFix>, dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, ts, a);
 }
 
 // lanes per atom and, in FP32, the accumulation form as template arguments
 template <typename real, bool kFix>
-static int density_lanes(const StepArgs& a, int lanes, int block, hipStream_t s)
+static int density_lanes(const StepArgs& a, int lanes, int block, hipStream_t s, const Stamp& ts)
 {
     switch (lanes) {
-    case 1: density_one<real, 1, kFix>(a, block, s); break;
-    case 2: density_one<real, 2, kFix>(a, block, s); break;
-    case 4: density_one<real, 4, kFix>(a, block, s); break;
-    case 8: density_one<real, 8, kFix>(a, block, s); break;
-    case 16: density_one<real, 16, kFix>(a, block, s); break;
+    case 1: density_one<real, 1, kFix>(a, block, s, ts); break;
+    case 2: density_one<real, 2, kFix>(a, block, s, ts); break;
+    case 4: density_one<real, 4, kFix>(a, block, s, ts); break;
+    case 8: density_one<real, 8, kFix>(a, block, s, ts); break;
+    case 16: density_one<real, 16, kFix>(a, block, s, ts); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
 template <typename real, bool kFix>
-static int force_lanes(const StepArgs& a, int lanes, int block, hipStream_t s)
+static int force_lanes(const StepArgs& a, int lanes, int block, hipStream_t s, const Stamp& ts)
 {
     switch (lanes) {
-    case 1: force_one<real, 1, kFix>(a, block, s); break;
-    case 2: force_one<real, 2, kFix>(a, block, s); break;
-    case 4: force_one<real, 4, kFix>(a, block, s); break;
-    case 8: force_one<real, 8, kFix>(a, block, s); break;
-    case 16: force_one<real, 16, kFix>(a, block, s); break;
+    case 1: force_one<real, 1, kFix>(a, block, s, ts); break;
+    case 2: force_one<real, 2, kFix>(a, block, s, ts); break;
+    case 4: force_one<real, 4, kFix>(a, block, s, ts); break;
+    case 8: force_one<real, 8, kFix>(a, block, s, ts); break;
+    case 16: force_one<real, 16, kFix>(a, block, s, ts); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
 template <typename real>
-static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t s)
+static int launch_density_t(const StepArgs& a, int lanes, int block, hipStream_t s, const Stamp& ts)
 {
     if (a.n_tiles <= 0) return 0;
     if (block < 64 || block > kMaxBlock || block % 64) return (int)hipErrorInvalidValue;
-    if (sizeof(real) == 4 && !a.fix) return density_lanes<real, false>(a, lanes, block, s);
-    return density_lanes<real, true>(a, lanes, block, s);
+    if (sizeof(real) == 4 && !a.fix) return density_lanes<real, false>(a, lanes, block, s, ts);
+    return density_lanes<real, true>(a, lanes, block, s, ts);
 }
 
 template <typename real>
-static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s)
+static int launch_force_t(const StepArgs& a, int lanes, int block, hipStream_t s, const Stamp& ts)
 {
     if (a.n_tiles <= 0) return 0;
     if (block < 64 || block > kMaxBlock || block % 64) return (int)hipErrorInvalidValue;
-    if (sizeof(real) == 4 && !a.fix) return force_lanes<real, false>(a, lanes, block, s);
-    return force_lanes<real, true>(a, lanes, block, s);
+    if (sizeof(real) == 4 && !a.fix) return force_lanes<real, false>(a, lanes, block, s, ts);
+    return force_lanes<real, true>(a, lanes, block, s, ts);
 }
 
 // --------------------------------------------------------------------------
@@ -1931,14 +1948,18 @@ int launch_finish(const StepArgs& a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
-int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s)
+int launch_density(const StepArgs& a, int precision, int lanes, int block, hipStream_t s, hipEvent_t t0,
+                   hipEvent_t t1)
 {
-    return precision ? launch_density_t<float>(a, lanes, block, s) : launch_density_t<double>(a, lanes, block, s);
+    const Stamp ts{t0, t1};
+    return precision ? launch_density_t<float>(a, lanes, block, s, ts)
+                     : launch_density_t<double>(a, lanes, block, s, ts);
 }
 
-int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s)
+int launch_force(const StepArgs& a, int precision, int lanes, int block, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return precision ? launch_force_t<float>(a, lanes, block, s) : launch_force_t<double>(a, lanes, block, s);
+    const Stamp ts{t0, t1};
+    return precision ? launch_force_t<float>(a, lanes, block, s, ts) : launch_force_t<double>(a, lanes, block, s, ts);
 }
 
 int launch_init_velocities(const StepArgs& a, int n_rep, int fix_com, hipStream_t s)
