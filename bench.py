@@ -156,6 +156,8 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
         ctx.run_switching(p, x, v, 0, warmup, sync=True)
     if autotune and not lanes:
         tuned = ctx.autotune(p, warmup, x, v, trial_steps=20)
+        if list_builder != "auto":   # the tuner times both builders; an explicit choice stands
+            ctx.set_list_builder(list_builder == "lds")
     if graph:
         ctx.set_graph(graph)
     natoms = int(arrs["x0"].shape[0])

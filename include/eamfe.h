@@ -170,7 +170,8 @@ int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threa
  * launch shape (lanes per atom x block threads x persistent grid) on copies
  * of the caller's state (x_dev, v_dev are not modified; the work carried by
  * the context is restored) and keep the fastest shape; then, at that shape,
- * keep the faster of the two list builders (eamfe_set_list_builder).  The
+ * keep the faster of the two list builders (eamfe_set_list_builder), timed
+ * over at least 100 steps (at most to the protocol's end).  The
  * lists are built again at the caller's positions by the next pass, so a
  * deterministic EAMFE_FP32 run continues bitwise as one whose lists were
  * rebuilt at `step`.  Outputs (may be NULL): the chosen lanes and block

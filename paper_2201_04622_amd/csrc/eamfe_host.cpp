@@ -1827,6 +1827,7 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
     OK(ensure_lambda(c, p, &S));
     if (step < 0 || step >= S) return fail(c, EAMFE_EINVAL, "autotune: step out of range");
     const int64_t s1 = std::min<int64_t>(S, step + 2 + trial_steps);
+    const int64_t s2 = std::min<int64_t>(S, step + 2 + std::max<int64_t>(trial_steps, 100));
     const size_t v3 = 3 * (size_t)c->N * sizeof(double);
     HIPCHK(c, hipMemcpyAsync(c->tune_w.p, c->W_state_d.p, (size_t)c->n_rep * sizeof(double),
                              hipMemcpyDeviceToDevice, c->stream));
@@ -1879,8 +1880,9 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
         }
     }
     // at the chosen shape, the list builder: rows from LDS or from global memory
-    // (identical rows; the faster depends on how many atoms a step rebuilds)
-    if (!rc && has_eam && step + 2 < s1) {
+    // (identical rows; the faster depends on how many atoms a step rebuilds, so
+    // this trial spans at least 100 steps, to s2)
+    if (!rc && has_eam && step + 2 < s2) {
         c->lanes = best_l;
         c->block = best_b;
         c->grid = best_g;
@@ -1899,17 +1901,16 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
                                     nullptr, nullptr, 0)))
                 break;
             (void)hipEventRecord(e0, c->stream);
-            if ((rc = run_switching(c, p, step + 2, s1, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr, nullptr,
+            if ((rc = run_switching(c, p, step + 2, s2, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr, nullptr,
                                     nullptr, 0)))
                 break;
             (void)hipEventRecord(e1, c->stream);
             (void)hipEventSynchronize(e1);
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            t_b[lds] = ms / (double)(s1 - step - 2);
+            t_b[lds] = ms / (double)(s2 - step - 2);
         }
         c->lds_rows = rc ? lds0 : (t_b[1] <= t_b[0] ? 1 : 0);
-        if (!rc) best = std::min(t_b[0], t_b[1]);
     }
 done:
     // the lists now follow a trial's positions: the next pass plans and builds
