@@ -241,6 +241,100 @@ def test_same_noise_trajectory(oracle_lib, opot, prec, mode):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", ["fl", "rs"])
+def test_fp32_one_step_error_is_the_force_error(oracle_lib, opot, mode):
+    """One FP32 step from the oracle's own state, at points across a
+    protocol, differs from the oracle's step by no more than the FP32 force
+    and energy errors measured at that state imply: with eps_f the largest
+    force-component error and eps_u the energy error (GPU FP32 against the
+    oracle at x_s, and eps_f' at the oracle's x_{s+1}), one B-A-O-A-B step
+    gives |dx| <= (dt^2/2m) eps_f (the first half kick, carried through both
+    drifts), |dv| <= (dt/2m)(eps_f + eps_f') plus the first-order change of
+    the closing kick's force, |d dH/dl| <= eps_u (plus the grid of the
+    replica sum of the spring energies in FL) and |dW| <= |dlambda| times
+    that, each with a factor 2 for the rows' rounding groups, above a float64
+    floor.  Unlike a whole-trajectory cap, a per-step bound this tight fails
+    on any slip in the integration or the work sum."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    say(f"fp32 one-step error mode={mode}")
+    reps = _mixed_batch()[:4]
+    n_eq, n_sw, n_hold, n_hold2 = 10, 30, 5, 5
+    S = n_eq + 2 * n_sw + n_hold + n_hold2
+    p = E.protocol(mode, n_eq, n_sw, n_hold, n_hold2, function=2, lambda_f=0.5)
+    lam = oracle_lib.schedule(mode, n_eq, n_sw, n_hold, n_hold2, function=2, lambda_f=0.5)
+    ctx, x0, arrs = make_ctx(reps, FP32, 2, 256)
+    v0 = torch.zeros_like(x0)
+    ctx.init_velocities(v0, True)
+    v_init = split(E.from_soa(v0), ctx.offsets)
+    m = reps[0].mass * 1.0364269e-4   # eV ps^2 / A^2
+    dt = 0.001
+    checks = (0, 12, 25, 40, 55, 70)
+    # the oracle's trajectory, its states at the checked steps
+    params = [oracle_lib.RunParams(mode=mode, T=r.T, k=r.k, seed=r.seed, fix_com=True, mass=r.mass) for r in reps]
+    xs = [r.sites().copy() for r in reps]
+    vs = [vi.copy() for vi in v_init]
+    states, prev = {}, 0
+    for s in checks:
+        if s > prev:
+            for q, r in enumerate(reps):
+                oracle_lib.run(opot if mode in ("fl", "rs") else None, params[q], r.sites(), r.box, xs[q], vs[q],
+                               lam[prev: s + 1], step0=prev)
+        states[s] = ([a.copy() for a in xs], [a.copy() for a in vs])
+        prev = s
+
+    def fp32_errors(xl):
+        x = E.to_soa(np.concatenate(xl))
+        ctx.neigh_build(x, 0.3, 0)
+        f = torch.zeros_like(x)
+        U = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+        ctx.eam_forces(x, f, U)
+        fg = split(E.from_soa(f), ctx.offsets)
+        out = []
+        for q, r in enumerate(reps):
+            o = opot.eam(xl[q], r.box)
+            out.append((float(np.abs(fg[q] - o["f"]).max()), abs(float(U[q]) - o["U"])))
+        return out
+
+    worst = 0.0
+    for s in checks:
+        xl, vl = states[s]
+        err0 = fp32_errors(xl)
+        x = E.to_soa(np.concatenate(xl))
+        v = E.to_soa(np.concatenate(vl))
+        W = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+        dH = torch.zeros(len(reps), dtype=torch.float64, device="cuda")
+        ctx.switch_step(p, s, x, v, W, dH)
+        xg, vg = split(E.from_soa(x), ctx.offsets), split(E.from_soa(v), ctx.offsets)
+        x1, v1, dH1, W1 = [], [], [], []
+        for q, r in enumerate(reps):
+            xo, vo = xl[q].copy(), vl[q].copy()
+            dHo, Wo, _, _ = oracle_lib.run(opot, params[q], r.sites(), r.box, xo, vo, lam[s: s + 2], step0=s)
+            x1.append(xo); v1.append(vo); dH1.append(float(dHo[0])); W1.append(float(Wo[0]))
+        err1 = fp32_errors(x1)
+        dlam = abs(lam[s + 1] - lam[s])
+        for q, r in enumerate(reps):
+            ef0, eu0 = err0[q]
+            ef1, _ = err1[q]
+            bx = 2.0 * dt * dt / (2.0 * m) * ef0 + 1e-11
+            bv = 2.0 * dt / (2.0 * m) * (ef0 + ef1) + 1e-9
+            # FL: the spring energies enter the replica sum on the 2^-24 grid (in A^2, times k/2)
+            grid = 0.5 * r.k * r.natoms * 2.0 ** -25 if mode == "fl" else 0.0
+            bh = 2.0 * eu0 + grid + 1e-9 * max(1.0, abs(dH1[q]))
+            bw = dlam * bh + 1e-12
+            dx = float(np.abs(xg[q] - x1[q]).max())
+            dv = float(np.abs(vg[q] - v1[q]).max())
+            dh = abs(float(dH[q]) - dH1[q])
+            dw = abs(float(W[q]) - W1[q])
+            say(f"step {s} rep {q}: eps_f {ef0:.1e} eps_u {eu0:.1e} | dx {dx:.1e}/{bx:.1e} dv {dv:.1e}/{bv:.1e} "
+                f"dH {dh:.1e}/{bh:.1e} dW {dw:.1e}/{bw:.1e}")
+            assert dx <= bx and dv <= bv and dh <= bh and dw <= bw, (s, q)
+            worst = max(worst, dx / bx, dv / bv, dh / bh)
+    say(f"largest share of a bound used: {worst:.2f}")
+    ctx.close()
+
+
 def test_switch_step_matches_run_switching():
     import torch
 
