@@ -68,8 +68,9 @@ extern "C" {
                           energies and work in float64.  Per-atom sums are float32
                           partials over groups of four consecutive list slots, rounded
                           to 2^-32 and added exactly in fixed point; replica sums
-                          (energies, the noise mean) add values rounded to 2^-24 or
-                          2^-36 exactly.  Results are bitwise reproducible and the
+                          add energies rounded to 2^-24 and, with the centre of mass
+                          held, thermostat deviates and initial velocities that are
+                          themselves on the 2^-36 grid, exactly.  Results are bitwise reproducible and the
                           same for every launch shape and either list builder.  The
                           slot groups follow the rows: rebuilding the lists at
                           another step changes the rounding (the last bits). */
@@ -119,11 +120,13 @@ typedef struct eamfe_protocol {
 /* Create a context on HIP device `device`, issuing work on `hip_stream`
  * (a hipStream_t; NULL = the legacy default stream).  precision is
  * EAMFE_FP64 or EAMFE_FP32.  deterministic (EAMFE_FP32 only; 0 or 1): 1
- * rounds every float32 partial sum of four list slots to the 2^-32 grid and
- * every term of a replica sum to 2^-24 (energies, virials) or 2^-36 (the
- * noise mean) and adds them exactly (results bitwise reproducible and
- * independent of the launch shape); 0 adds them in float64 as they are
- * (bitwise reproducible run to run for one launch shape, not across shapes).
+ * rounds every float32 partial sum of four list slots to the 2^-32 grid,
+ * every energy or virial term of a replica sum to 2^-24, and (centre of mass
+ * held) the thermostat deviates and initial velocities themselves to 2^-36,
+ * and adds them exactly (results bitwise reproducible and independent of the
+ * launch shape; the removed mean is the exact mean of the applied values);
+ * 0 adds them in float64 as they are (bitwise reproducible run to run for
+ * one launch shape, not across shapes).
  * No device memory is taken here.  *ctx is set on success. */
 int eamfe_create(eamfe_ctx** ctx, int device, void* hip_stream, int precision, int deterministic);
 

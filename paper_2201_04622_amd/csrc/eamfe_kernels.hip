@@ -1219,12 +1219,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     }
     if (tl.idx == 0 && wave_lane() == 0) a.rebuild[tl.rep] = 0;   // lists are current now
 
-    // thermostat noise of step `it` and (fixed centre of mass) its replica sum
+    // thermostat noise of step `it` and (fixed centre of mass) its replica sum.
+    // In the exact-sum form the deviates themselves go on the 2^-36 grid, so
+    // the mean the step removes is the exact mean of the values it applies
+    // (a lone atom stays put bit for bit)
     if (a.step_kernel && it < a.it_last) {
+        constexpr bool kGrid = sizeof(real) == 4 && kFix;
         double z[3] = {0.0, 0.0, 0.0};
         if constexpr (T == 1) {
             if (valid) {
                 gauss3(R.seed, (uint32_t)(i - R.off), it, 0u, z[0], z[1], z[2]);
+                if (kGrid && a.fix_com) on_grid<3>(z, kGridZ, kGridZInv);
                 a.xi[i] = z[0];
                 a.xi[N + i] = z[1];
                 a.xi[2 * N + i] = z[2];
@@ -1232,6 +1237,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         } else if (valid && lane < 2) {   // lane 0: x and y components, lane 1: z
             double za, zb;
             gauss3_half(R.seed, (uint32_t)(i - R.off), it, 0u, lane, za, zb);
+            if (kGrid && a.fix_com) {
+                za = rint(za * kGridZ) * kGridZInv;
+                zb = rint(zb * kGridZ) * kGridZInv;
+            }
             if (lane == 0) {
                 z[0] = za;
                 z[1] = zb;
@@ -1242,10 +1251,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 a.xi[2 * N + i] = za;
             }
         }
-        if (a.fix_com) {
-            if constexpr (sizeof(real) == 4 && kFix) on_grid<3>(z, kGridZ, kGridZInv);
-            unit_partial<3>(z, a.noise_part, R, tl.idx);
-        }
+        if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
     }
     // a replica rebuilt in this step: the list pass has read its cell counters,
     // which are cleared here for its next binning
@@ -1624,15 +1630,13 @@ __global__ void k_init_v(StepArgs a, int fix_com)
     if (valid) {
         gauss3(R.seed, (uint32_t)(i - R.off), 0, 1u, z[0], z[1], z[2]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            z[c] *= R.sig_v;
-            a.v[c * a.N + i] = z[c];
-        }
+        for (int c = 0; c < 3; ++c) z[c] *= R.sig_v;
+        // exact-sum form: the velocities on the 2^-36 grid, their mean an exact sum
+        if (fix_com && a.fix) on_grid<3>(z, kGridZ, kGridZInv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.v[c * a.N + i] = z[c];
     }
-    if (fix_com) {
-        if (a.fix) on_grid<3>(z, kGridZ, kGridZInv);   // the mean only; v keeps its full value
-        unit_partial<3>(z, a.noise_part, R, tl.idx);
-    }
+    if (fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
 }
 
 __global__ void k_sub_mean_v(StepArgs a)

@@ -206,11 +206,17 @@ def _chk(ctx, code, what=""):
         raise EamfeError(code, msg or what)
 
 
-def _ptr(t):
+def _ptr(t, n=None, what="tensor"):
+    """Device address of a contiguous float64 tensor on the GPU holding at
+    least n elements (the library's kernels read or write that many; a
+    shorter buffer is refused here, since the C ABI takes a bare pointer)."""
     if t is None:
         return None
     import torch
-    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "device float64 contiguous tensor expected"
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{what}: a contiguous float64 tensor on the GPU is expected")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} elements, the call needs {n}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -354,7 +360,8 @@ class Context:
 
     def autotune(self, p: Protocol, step, x, v, trial_steps=20):
         a, b, ms = C.c_int(), C.c_int(), C.c_double()
-        self._r(self._lib.eamfe_autotune, C.byref(p), int(step), _ptr(x), _ptr(v), int(trial_steps),
+        self._r(self._lib.eamfe_autotune, C.byref(p), int(step), _ptr(x, 3 * self.N, "x"), _ptr(v, 3 * self.N, "v"),
+                int(trial_steps),
                                          C.byref(a), C.byref(b), C.byref(ms))
         return a.value, b.value, ms.value
 
@@ -384,7 +391,8 @@ class Context:
         """Per-replica diagonal pressure tensor [n_rep, 3] (eV/A^3) at x (and
         velocities v, or the configurational part only)."""
         out = np.zeros((self.n_rep, 3))
-        self._r(self._lib.eamfe_pressure, _ptr(x), _ptr(v), out.ctypes.data_as(_dp))
+        self._r(self._lib.eamfe_pressure, _ptr(x, 3 * self.N, "x"), _ptr(v, 3 * self.N, "v"),
+                out.ctypes.data_as(_dp))
         return out
 
     def barostat_step(self, b: Barostat, step, w_eam, x, v):
@@ -393,7 +401,8 @@ class Context:
         v and the boxes in place; returns (mu[n_rep, 3] per-axis factors,
         P[n_rep, 3] diagonal internal pressures, eV/A^3)."""
         mu, P = np.zeros((self.n_rep, 3)), np.zeros((self.n_rep, 3))
-        self._r(self._lib.eamfe_barostat_step, C.byref(b), int(step), float(w_eam), _ptr(x), _ptr(v),
+        self._r(self._lib.eamfe_barostat_step, C.byref(b), int(step), float(w_eam), _ptr(x, 3 * self.N, "x"),
+                _ptr(v, 3 * self.N, "v"),
                 mu.ctypes.data_as(_dp), P.ctypes.data_as(_dp))
         return mu, P
 
@@ -406,13 +415,13 @@ class Context:
     def set_spring_scale(self, s=None):
         """Per-atom spring scales s_i (device float64 [N_tot]; atom i's spring
         is k s_i) or None for uniform springs."""
-        self._c(self._lib.eamfe_set_spring_scale(self._h, _ptr(s)))
+        self._c(self._lib.eamfe_set_spring_scale(self._h, _ptr(s, self.N, "spring scales")))
 
     def msd(self, x):
         """Per-replica mean-squared displacement (A^2) of x from the lattice
         sites, centre of mass removed (Eq. msd)."""
         out = np.zeros(self.n_rep)
-        self._c(self._lib.eamfe_msd(self._h, _ptr(x), out.ctypes.data_as(_dp)))
+        self._c(self._lib.eamfe_msd(self._h, _ptr(x, 3 * self.N, "x"), out.ctypes.data_as(_dp)))
         return out
 
     def row_history(self, reset=False):
@@ -446,6 +455,9 @@ class Context:
 
     def system_setup(self, replicas: Sequence, x0_soa):
         """replicas: inputs.Replica list; x0_soa: device float64 [3, N_tot]."""
+        n_tot = sum(int(r.natoms) for r in replicas)
+        if tuple(x0_soa.shape) != (3, n_tot):
+            raise ValueError(f"system_setup: x0 has shape {tuple(x0_soa.shape)}, the replicas hold (3, {n_tot})")
         arr = (Replica * len(replicas))()
         for q, r in zip(arr, replicas):
             q.n_atoms = r.natoms
@@ -458,13 +470,14 @@ class Context:
         self.offsets = np.concatenate([[0], np.cumsum([r.natoms for r in replicas])])
 
     def neigh_build(self, x, skin=0.3, max_neighbors=0):
-        self._r(self._lib.neigh_build, _ptr(x), float(skin), int(max_neighbors))
+        self._r(self._lib.neigh_build, _ptr(x, 3 * self.N, "x"), float(skin), int(max_neighbors))
 
     def eam_forces(self, x, f=None, U=None, e_atom=None):
-        self._r(self._lib.eam_forces, _ptr(x), _ptr(f), _ptr(U), _ptr(e_atom))
+        self._r(self._lib.eam_forces, _ptr(x, 3 * self.N, "x"), _ptr(f, 3 * self.N, "f"), _ptr(U, self.n_rep, "U"),
+                _ptr(e_atom, self.N, "e_atom"))
 
     def init_velocities(self, v, fix_com=True):
-        self._c(self._lib.eamfe_init_velocities(self._h, _ptr(v), int(bool(fix_com))))
+        self._c(self._lib.eamfe_init_velocities(self._h, _ptr(v, 3 * self.N, "v"), int(bool(fix_com))))
 
     def run_switching(self, p: Protocol, x, v, step_begin=0, step_end=None, lam_out=None, dHdl_out=None, W_out=None,
                       sync=True):
@@ -472,10 +485,13 @@ class Context:
             S = C.c_int64()
             _chk(None, self._lib.eamfe_lambda_schedule(C.byref(p), None, C.byref(S)))
             step_end = S.value
+        S = C.c_int64()
+        _chk(None, self._lib.eamfe_lambda_schedule(C.byref(p), None, C.byref(S)))
+        args = (_ptr(x, 3 * self.N, "x"), _ptr(v, 3 * self.N, "v"), _ptr(lam_out, S.value + 1, "lam_out"),
+                _ptr(dHdl_out, self.n_rep * S.value, "dHdl_out"), _ptr(W_out, self.n_rep * S.value, "W_out"))
         s0 = int(step_begin)
         while True:
-            code = self._lib.run_switching(self._h, C.byref(p), s0, int(step_end), _ptr(x), _ptr(v), _ptr(lam_out),
-                                           _ptr(dHdl_out), _ptr(W_out), int(bool(sync)))
+            code = self._lib.run_switching(self._h, C.byref(p), s0, int(step_end), *args, int(bool(sync)))
             if code == ENOMEM and self._grow():
                 r = C.c_int64()
                 self._c(self._lib.eamfe_resume_step(self._h, C.byref(r)))
@@ -485,7 +501,8 @@ class Context:
             return self._c(code)
 
     def switch_step(self, p: Protocol, step, x, v, W, dHdl=None):
-        self._r(self._lib.switch_step, C.byref(p), int(step), _ptr(x), _ptr(v), _ptr(W), _ptr(dHdl))
+        self._r(self._lib.switch_step, C.byref(p), int(step), _ptr(x, 3 * self.N, "x"), _ptr(v, 3 * self.N, "v"),
+                _ptr(W, self.n_rep, "W"), _ptr(dHdl, self.n_rep, "dHdl"))
 
     def set_chunk(self, steps):
         self._c(self._lib.eamfe_set_chunk(self._h, int(steps)))
@@ -512,19 +529,33 @@ class Context:
     def set_state(self, W, xref, skin):
         """Load a saved work vector and build the lists at the saved reference positions."""
         Wc = np.ascontiguousarray(W, dtype=np.float64)
-        self._r(self._lib.eamfe_set_state, Wc.ctypes.data_as(_dp), _ptr(xref), float(skin))
+        if Wc.size < self.n_rep:
+            raise ValueError(f"set_state: {Wc.size} work values for {self.n_rep} replicas")
+        self._r(self._lib.eamfe_set_state, Wc.ctypes.data_as(_dp), _ptr(xref, 3 * self.N, "xref"), float(skin))
 
     def adjoint_theta(self, x, dtheta, weights=None, reduce=False):
         """dtheta (device float64, [n_rep, 3, n] or [3, n] with reduce) += w_r dU_r/dtheta."""
+        w = self._adjoint_weights(weights)
+        self._r(self._lib.eamfe_adjoint_theta, _ptr(x, 3 * self.N, "x"), None if w is None else w.ctypes.data_as(_dp),
+                int(bool(reduce)), _ptr(dtheta, self._dtheta_size(reduce), "dtheta"))
+
+    def _adjoint_weights(self, weights):
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
-        self._r(self._lib.eamfe_adjoint_theta, _ptr(x), None if w is None else w.ctypes.data_as(_dp),
-                                              int(bool(reduce)), _ptr(dtheta))
+        if w is not None and w.size < self.n_rep:
+            raise ValueError(f"adjoint: {w.size} weights for {self.n_rep} replicas")
+        return w
+
+    def _dtheta_size(self, reduce):
+        """Elements of dU/dtheta: 3 functions x n knots, per replica unless reduced."""
+        n = len(self.knots.phi) if getattr(self, "knots", None) is not None else 0
+        return 3 * n * (1 if reduce else self.n_rep)
 
     def set_adjoint_sampling(self, every, dtheta=None, weights=None, reduce=False):
-        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        w = self._adjoint_weights(weights)
         self._adj_keep = (dtheta, w)
         self._c(self._lib.eamfe_set_adjoint_sampling(self._h, int(every), None if w is None else w.ctypes.data_as(_dp),
-                                                     int(bool(reduce)), _ptr(dtheta)))
+                                                     int(bool(reduce)),
+                                                     _ptr(dtheta, self._dtheta_size(reduce), "dtheta")))
 
     def adjoint_samples(self):
         n = C.c_int64()
