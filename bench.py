@@ -28,7 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2201_04622_amd/csrc/eamfe_kernels.hip", "paper_2201_04622_amd/csrc/eamfe_internal.h")
+KERNEL_SOURCES = ("paper_2201_04622_amd/csrc/eamfe_kernels.hip", "paper_2201_04622_amd/csrc/eamfe_internal.h",
+                  "paper_2201_04622_amd/build.py")   # the build flags shape the code too
 # worker threads of the all-core oracle leg: at most the host share of one GPU
 CPU_THREADS_MAX = 16
 

@@ -16,6 +16,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression: the same
+    # expression then compiles to the same rounding wherever it is inlined
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 
