@@ -334,6 +334,11 @@ int eamfe_set_spring_scale(eamfe_ctx* ctx, const double* s_dev);
  * A^2.  Synchronises. */
 int eamfe_msd(eamfe_ctx* ctx, const double* x_dev, double* msd);
 
+/* Spring constant from a mean-squared displacement by equipartition
+ * (Eq. msd): k = 3 kB T / msd, msd in A^2 (eamfe_msd, averaged), T in K;
+ * returns eV/A^2, or 0 for msd <= 0. */
+double eamfe_spring_constant(double msd, double T);
+
 /* Copy the current Verlet rows (for inspection): nnb_dev[N_tot] row lengths,
  * nbr_dev[N_tot][cap] global atom ids in row order, -1 past each row's end
  * (may be NULL; cap >= the row capacity reported by eamfe_list_stats).

@@ -2157,6 +2157,11 @@ int eamfe_list_stats(eamfe_ctx* c, double* mean_len, int* max_len, int* capacity
 }
 
 // ---- estimators -------------------------------------------------------------
+double eamfe_spring_constant(double msd, double T)
+{
+    return msd > 0.0 ? 3.0 * kB * T / msd : 0.0;
+}
+
 double eamfe_einstein_free_energy(double n_eff, double T, double k, double mass)
 {
     const double omega = std::sqrt(k / (mass * mvv2e));

@@ -107,6 +107,7 @@ def lib():
         "eamfe_set_adjoint_sampling": (i32, [vp, i32, _dp, i32, vp]),
         "eamfe_adjoint_samples": (i32, [vp, C.POINTER(i64)]),
         "eamfe_einstein_free_energy": (dbl, [dbl, dbl, dbl, dbl]),
+        "eamfe_spring_constant": (dbl, [dbl, dbl]),
         "eamfe_fixed_cm_correction": (dbl, [dbl, dbl, dbl, dbl]),
         "eamfe_fl_free_energy": (i32, [i32, _dp, _dp, dbl, dbl, dbl, dbl, dbl, dbl, i32, _dp, _dp, _dp]),
         "eamfe_rs_free_energy": (i32, [C.POINTER(Protocol), _dp, dbl, dbl, dbl, i32, _dp, _dp]),
@@ -141,6 +142,11 @@ def lambda_schedule(p: Protocol) -> np.ndarray:
     lam = np.zeros(S.value + 1)
     _chk(None, lib().eamfe_lambda_schedule(C.byref(p), lam.ctypes.data_as(_dp), C.byref(S)))
     return lam
+
+
+def spring_constant(msd, T):
+    """k = 3 kB T / msd (Eq. msd), eV/A^2."""
+    return lib().eamfe_spring_constant(float(msd), float(T))
 
 
 def einstein_free_energy(n_eff, T, k, mass):

@@ -4,18 +4,16 @@ displacements taken from the lattice sites and the centre-of-mass
 displacement removed, averaged over an equilibrium run of the real system
 (H0, lambda = 0) at the size and temperature of the switching runs.
 
-The dynamics and the displacement sums run in the library (run_switching over
-the equilibration stretch of a protocol, eamfe_msd after each stretch); this
-module sequences the stretches and forms the averages.
+The dynamics, the displacement sums and k run in the library (run_switching
+over the equilibration stretch of a protocol, eamfe_msd after each stretch,
+eamfe_spring_constant); this module sequences the stretches and forms the
+averages.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import eamfe as E
-
-KB = 8.617333262e-5   # Boltzmann constant, eV/K (the library's value)
-
 
 def spring_constants(ctx, replicas, x, v, n_steps, every, mode="fl", skin=0.3, dt=0.001, damp=0.1,
                      discard=0):
@@ -35,5 +33,5 @@ def spring_constants(ctx, replicas, x, v, n_steps, every, mode="fl", skin=0.3, d
             acc += ctx.msd(x)
             samples += 1
     msd = acc / max(samples, 1)
-    T = np.array([r.T for r in replicas], dtype=np.float64)
-    return 3.0 * KB * T / msd, msd, samples
+    k = np.array([E.spring_constant(m, r.T) for m, r in zip(msd, replicas)])
+    return k, msd, samples

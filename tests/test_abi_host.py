@@ -219,3 +219,11 @@ def test_transition_temperature_of_crossing_curves():
     assert TR.transition_temperature(a, b) == pytest.approx(487.25, abs=1e-9)
     c = TR.GibbsCurve("hcp", 1.0, 1.0, T, z + 0.01, z, 0.0, 0.0)
     assert TR.transition_temperature(c, b) is None
+
+
+def test_spring_constant_matches_the_oracle():
+    import paper_2201_04622_amd.eamfe as E
+    from oracle import estimators as OE
+    for msd, T in ((0.0123, 300.0), (0.45, 100.0), (2.5e-3, 1600.0)):
+        assert E.spring_constant(msd, T) == pytest.approx(OE.spring_constant(msd, T), rel=1e-15)
+    assert E.spring_constant(0.0, 300.0) == 0.0 and E.spring_constant(-1.0, 300.0) == 0.0
