@@ -68,60 +68,75 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload, prec, launch, skin):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the factor the same
-    counter reads for a plain copy), or None when there is no summary for this
-    kernel, workload, precision, launch shape and skin, or the kernel sources
-    have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_hbm_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    if kv.get("launch") != f"lanes {launch[0]} block {launch[1]}":
-        return None
-    if kv.get("skin") is None or float(kv["skin"]) != float(skin):
-        return None
-    return float(kv["traffic_bytes_per_launch"])
-
-
-def measured_issue(kernel, workload, prec, launch, skin):
-    """VALU issue and LDS bank-conflict shares of ``kernel``'s cycles over the
-    timed dispatches, from the committed SQ counter summary, or None when it
-    does not cover this kernel, workload, precision, launch and skin, or the
-    kernel sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_force_k_density_{workload}_{prec}_issue_utilisation.txt")
-    if not os.path.exists(path) or launch != (2, 1024):
-        return None
-    kv, name, src = {}, None, None
+def _summary_fields(path, sectioned=False):
+    """The "name: value" fields of a committed profile summary.  Sectioned:
+    the header fields before the first "kernel:" line, and the fields of
+    each per-kernel section, keyed by its kernel."""
+    head, sections, cur = {}, {}, None
     with open(path) as fh:
         for line in fh:
             if line.startswith("#") or ":" not in line:
                 continue
             k, v = (t.strip() for t in line.split(":", 1))
-            if k == "kernel_source_sha256":
-                src = v
-            elif k == "skin":
-                kv["skin"] = v
-            elif k == "kernel":
-                name = v
-            elif name and name.startswith(kernel + "<"):
-                kv[k] = v
-    if src != kernel_source_hash() or "valu_issue" not in kv or float(kv.get("skin", "nan")) != float(skin):
-        return None
-    return {"valu_issue": float(kv["valu_issue"]), "lds_conflict": float(kv["lds_conflict"]),
-            "resident_waves_per_simd": float(kv["resident_waves_per_simd"])}
+            v = v.split("#", 1)[0].strip()
+            if sectioned and k == "kernel":
+                cur = sections.setdefault(v, {})
+            elif cur is not None:
+                cur[k] = v
+            else:
+                head.setdefault(k, v)
+    return head, sections
+
+
+def _summary_covers(head, workload, prec, launch, skin, steps, warmup):
+    """True when a summary was taken with the current kernel sources on this
+    run: the same workload, precision, launch shape, skin and run length
+    (timed steps and warm-up steps: the neighbour rows, and so the bytes a
+    launch moves, follow the state the crystal has reached)."""
+    try:
+        return (head.get("kernel_source_sha256") == kernel_source_hash()
+                and head.get("workload") == workload and head.get("precision") == prec
+                and head.get("launch") == f"lanes {launch[0]} block {launch[1]} grid {launch[2]}"
+                and float(head["skin"]) == float(skin)
+                and int(head["steps"]) == int(steps) and int(head["warmup"]) == int(warmup))
+    except (KeyError, ValueError, TypeError):
+        return False
+
+
+def measured_traffic(kernel, workload, prec, launch, skin, steps, warmup):
+    """HBM bytes per launch of ``kernel`` from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the factor the same
+    counter reads for a plain copy), or None when no summary covers this
+    kernel, workload, precision, launch shape, skin and run length, or the
+    kernel sources have changed since the counters were taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_hbm_traffic.txt"))):
+        head, _ = _summary_fields(path)
+        if head.get("kernel", "").split("<")[0] == kernel and \
+                _summary_covers(head, workload, prec, launch, skin, steps, warmup):
+            return float(head["traffic_bytes_per_launch"])
+    return None
+
+
+def measured_issue(kernel, workload, prec, launch, skin, steps, warmup):
+    """VALU issue and LDS bank-conflict shares of ``kernel``'s cycles over the
+    timed dispatches, from a committed SQ counter summary, or None when none
+    covers this kernel, workload, precision, launch, skin and run length, or
+    the kernel sources have changed since the counters were taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_force_k_density_*_issue_utilisation.txt"))):
+        head, sections = _summary_fields(path, sectioned=True)
+        if not _summary_covers(head, workload, prec, launch, skin, steps, warmup):
+            continue
+        for name, kv in sections.items():
+            if name.split("<")[0] == kernel and "valu_issue" in kv:
+                return {"valu_issue": float(kv["valu_issue"]), "lds_conflict": float(kv["lds_conflict"]),
+                        "resident_waves_per_simd": float(kv["resident_waves_per_simd"])}
+    return None
 
 
 def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=None, stride=None, graph=0,
-            list_builder="auto", stable=False):
+            list_builder="auto", stable=False, grid=-1):
     """Run warmup + steps steps of a workload's protocol on the GPU; the
     last `steps` are timed with HIP events around one run_switching call on
     the library's stream (torch's current stream).  Inside the timed region
@@ -146,6 +161,8 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
         ctx.set_list_builder(list_builder == "lds")
     if lanes:
         ctx.set_launch(lanes, block)
+    if grid >= 0:
+        ctx.set_grid(grid)
     ctx.eam_setup(I.synthetic_eam_knots())
     x = E.to_soa(arrs["x0"])
     ctx.system_setup(reps, x)
@@ -181,11 +198,11 @@ def run_gpu(workload, prec, steps, warmup, lanes, block, autotune, skin, only=No
     mean_nl, passes = ctx.row_history()   # time average over the timed force passes
     rebuilt_reps, rebuilt_atoms = ctx.list_rebuilds()
     end_nl, max_nl, cap = ctx.list_stats()
-    launch = ctx.get_launch()
+    launch = (*ctx.get_launch(), ctx.get_grid())   # lanes per atom, block threads, grid blocks (0: one per slice)
     builder = ctx.get_list_builder()
     ctx.close()
     return {
-        "natoms": natoms, "n_rep": len(reps), "steps": steps, "ms": ms, "wall_s": wall, "kt": kt,
+        "natoms": natoms, "n_rep": len(reps), "steps": steps, "warmup": warmup, "ms": ms, "wall_s": wall, "kt": kt,
         "stride": stride, "mean_nl": mean_nl, "passes": passes, "rebuilt_reps": rebuilt_reps,
         "rebuilt_atoms": rebuilt_atoms, "end_nl": end_nl, "max_nl": max_nl, "cap": cap, "launch": launch,
         "tuned": tuned, "desc": wl.description, "list_builder": builder,
@@ -208,10 +225,10 @@ def roofline(run, prec, workload, skin):
     return {
         "bound": "hbm", "kernel": "k_force",
         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-        "traffic": measured_traffic("k_force", workload, prec, run["launch"], skin),
+        "traffic": measured_traffic("k_force", workload, prec, run["launch"], skin, run["steps"], run["warmup"]),
         "algorithmic_bytes": bytes_launch, "bytes_per_atom": bpa,
         # the same kernel's VALU issue and LDS-conflict shares from SQ counters (what bounds it)
-        "issue": measured_issue("k_force", workload, prec, tuple(run["launch"]), skin),
+        "issue": measured_issue("k_force", workload, prec, run["launch"], skin, run["steps"], run["warmup"]),
         "avg_launch_us": avg_ms * 1e3, "launches_timed": n, "timing_stride": run["stride"],
     }
 
@@ -317,7 +334,8 @@ def config_record(name, run, prec, workload, skin, graph):
         "value": run["natoms"] * run["steps"] / (run["ms"] / 1e3), "unit": "atom-steps/s",
         "steps": run["steps"], "ms_per_step": run["ms"] / run["steps"],
         "mean_neighbour_row": round(run["mean_nl"], 2),
-        "launch": {"lanes_per_atom": run["launch"][0], "block_threads": run["launch"][1]},
+        "launch": {"lanes_per_atom": run["launch"][0], "block_threads": run["launch"][1],
+                   "grid_blocks": run["launch"][2]},
         "list_builder": run["list_builder"], "graph_iterations": graph, "skin": skin,
         "force_roofline_frac": None if rf is None else rf["frac"],
         "force_avg_launch_us": None if rf is None else rf["avg_launch_us"],
@@ -368,6 +386,7 @@ def result_line(args, main_run, plain, cpu, configs=None):
             "list_rebuilds_per_step": round(main_run["rebuilt_reps"] / main_run["steps"], 3),
             "atoms_rebuilt_per_step": round(main_run["rebuilt_atoms"] / main_run["steps"], 1),
             "launch": {"lanes_per_atom": main_run["launch"][0], "block_threads": main_run["launch"][1],
+                       "grid_blocks": main_run["launch"][2],
                        "autotuned": main_run["tuned"] is not None},
             "skin": args.skin,
             "list_builder": main_run["list_builder"],
@@ -396,6 +415,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--grid", type=int, default=-1,
+                    help="pair-pass grid in blocks (0: one block per staged slice; -1: the library's default), "
+                         "with --lanes and --no-autotune to repeat a tuned launch")
     ap.add_argument("--skin", type=float, default=0.65)   # fastest of a 0.35..1.2 sweep on the 64-replica batch
     ap.add_argument("--timing-stride", type=int, default=None,
                     help="iterations between event-timed force passes in the timed region (0: none)")
@@ -426,7 +448,8 @@ def main():
         sys.exit(2)
 
     main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup, args.lanes, args.block,
-                       not args.no_autotune, args.skin, stride=args.timing_stride, list_builder=args.list_builder)
+                       not args.no_autotune, args.skin, stride=args.timing_stride, list_builder=args.list_builder,
+                       grid=args.grid)
     plain = None
     if not args.no_fp64:
         pr = run_gpu("fl_mid", "fp64", 2000, 500, 0, 0, True, args.skin, only=[0], stride=0)

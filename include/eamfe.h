@@ -174,11 +174,13 @@ int eamfe_get_launch(const eamfe_ctx* ctx, int* lanes_per_atom, int* block_threa
  * of the caller's state (x_dev, v_dev are not modified; the work carried by
  * the context is restored) and keep the fastest shape; then, at that shape,
  * keep the faster of the two list builders (eamfe_set_list_builder), timed
- * over at least 100 steps (at most to the protocol's end).  The
- * lists are built again at the caller's positions by the next pass, so a
+ * over at least 100 steps (at most to the protocol's end).  Before it
+ * returns it builds the lists again at the caller's positions x_dev (as
+ * eamfe_neigh_build with the protocol's skin and automatic capacity), so a
  * deterministic EAMFE_FP32 run continues bitwise as one whose lists were
- * rebuilt at `step`.  Outputs (may be NULL): the chosen lanes and block
- * threads, and its time per step in ms. */
+ * rebuilt at `step`, and the next pass starts from valid lists.  Outputs
+ * (may be NULL): the chosen lanes and block threads, and its time per step
+ * in ms. */
 int eamfe_autotune(eamfe_ctx* ctx, const eamfe_protocol* p, int64_t step, const double* x_dev,
                    const double* v_dev, int trial_steps, int* lanes_out, int* block_out, double* ms_per_step);
 

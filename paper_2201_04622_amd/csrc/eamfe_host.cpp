@@ -1913,8 +1913,9 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
         c->lds_rows = rc ? lds0 : (t_b[1] <= t_b[0] ? 1 : 0);
     }
 done:
-    // the lists now follow a trial's positions: the next pass plans and builds
-    // them again at the caller's
+    // the lists now follow a trial's positions: plan and build them again at
+    // the caller's (at the chosen shape and builder), as a pass would on
+    // finding none, so the caller's next pass starts from valid lists
     c->have_list = false;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1926,6 +1927,7 @@ done:
         const int r2 = build_tiles(c);
         if (!rc) rc = r2;
     }
+    if (!rc && has_eam) rc = neigh_build(c, x, p->skin, 0);
     (void)hipMemcpyAsync(c->W_state_d.p, c->tune_w.p, (size_t)c->n_rep * sizeof(double), hipMemcpyDeviceToDevice,
                          c->stream);
     (void)hipStreamSynchronize(c->stream);

@@ -1,6 +1,7 @@
 """Host logic of bench.py: the one-GPU guard, the algorithmic byte counts and
 the checks that keep a committed counter summary from being reported for a
-kernel, launch or list skin it was not taken at."""
+kernel, launch, list skin or run length it was not taken at."""
+import glob
 import importlib.util
 import json
 import os
@@ -48,44 +49,65 @@ def test_algorithmic_bytes_per_atom(bench):
     assert bench.density_bytes_per_atom(10, "fp64") == 24 + 4 + 40 + 8 + 8
 
 
-def test_traffic_summary_only_for_the_shape_it_was_taken_at(bench):
-    path = os.path.join(ROOT, "profiles", "k_force_batch64_fp32_hbm_traffic.txt")
-    kv = _profile_kv(path)
+def _run_of(kv):
+    """The run a summary was taken on: launch (lanes, block, grid), skin,
+    timed steps, warm-up steps."""
     launch = tuple(int(t) for t in kv["launch"].split()[1::2])
-    skin = float(kv["skin"])
-    got = bench.measured_traffic("k_force", "batch64", "fp32", launch, skin)
-    if kv["kernel_source_sha256"] != bench.kernel_source_hash():
-        assert got is None     # kernel changed since the counters were taken
-        return
-    assert got == float(kv["traffic_bytes_per_launch"])
-    assert bench.measured_traffic("k_force", "batch64", "fp32", launch, skin + 0.1) is None
-    assert bench.measured_traffic("k_force", "batch64", "fp32", (launch[0] * 2, launch[1]), skin) is None
-    assert bench.measured_traffic("k_force", "batch64", "fp64", launch, skin) is None
-    assert bench.measured_traffic("k_force", "no_such_workload", "fp32", launch, skin) is None
+    return launch, float(kv["skin"]), int(kv["steps"]), int(kv["warmup"])
 
 
-def test_issue_summary_only_for_the_skin_it_was_taken_at(bench):
-    path = os.path.join(ROOT, "profiles", "k_force_k_density_batch64_fp32_issue_utilisation.txt")
-    kv = _profile_kv(path)
-    skin = float(kv["skin"])
-    got = bench.measured_issue("k_force", "batch64", "fp32", (2, 1024), skin)
-    if kv["kernel_source_sha256"] != bench.kernel_source_hash():
-        assert got is None
-        return
-    assert set(got) == {"valu_issue", "lds_conflict", "resident_waves_per_simd"}
-    assert 0.0 < got["valu_issue"] < 1.0 and 0.0 <= got["lds_conflict"] < 1.0
-    assert 0.0 < got["resident_waves_per_simd"] <= 8.0
-    dens = bench.measured_issue("k_density", "batch64", "fp32", (2, 1024), skin)
-    assert dens is not None and dens != got
-    assert bench.measured_issue("k_force", "batch64", "fp32", (2, 1024), skin - 0.15) is None
-    assert bench.measured_issue("k_force", "batch64", "fp32", (4, 1024), skin) is None
+def _others(launch, skin, steps, warmup):
+    """Runs that differ from the given one in one respect each."""
+    lanes, block, grid = launch
+    return [((lanes * 2, block, grid), skin, steps, warmup), ((lanes, block // 2, grid), skin, steps, warmup),
+            ((lanes, block, grid + 256), skin, steps, warmup), (launch, skin + 0.1, steps, warmup),
+            (launch, skin, steps + 1, warmup), (launch, skin, steps, warmup + 1)]
+
+
+def test_traffic_summary_only_for_the_run_it_was_taken_on(bench):
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_force_*_hbm_traffic.txt")))
+    assert paths
+    runs = [_run_of(_profile_kv(p)) for p in paths]
+    for path, run in zip(paths, runs):
+        kv = _profile_kv(path)
+        got = bench.measured_traffic("k_force", kv["workload"], kv["precision"], *run)
+        if kv["kernel_source_sha256"] != bench.kernel_source_hash():
+            assert got is None     # kernel changed since the counters were taken
+            continue
+        assert got == float(kv["traffic_bytes_per_launch"])
+        for other in _others(*run):
+            if other not in runs:
+                assert bench.measured_traffic("k_force", kv["workload"], kv["precision"], *other) is None
+        other_prec = "fp64" if kv["precision"] == "fp32" else "fp32"
+        assert bench.measured_traffic("k_force", kv["workload"], other_prec, *run) is None
+        assert bench.measured_traffic("k_force", "no_such_workload", kv["precision"], *run) is None
+
+
+def test_issue_summary_only_for_the_run_it_was_taken_on(bench):
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_force_k_density_*_issue_utilisation.txt")))
+    assert paths
+    runs = [_run_of(_profile_kv(p)) for p in paths]
+    for path, run in zip(paths, runs):
+        kv = _profile_kv(path)
+        got = bench.measured_issue("k_force", kv["workload"], kv["precision"], *run)
+        if kv["kernel_source_sha256"] != bench.kernel_source_hash():
+            assert got is None
+            continue
+        assert set(got) == {"valu_issue", "lds_conflict", "resident_waves_per_simd"}
+        assert 0.0 < got["valu_issue"] < 1.0 and 0.0 <= got["lds_conflict"] < 1.0
+        assert 0.0 < got["resident_waves_per_simd"] <= 8.0
+        dens = bench.measured_issue("k_density", kv["workload"], kv["precision"], *run)
+        assert dens is not None and dens != got
+        for other in _others(*run):
+            if other not in runs:
+                assert bench.measured_issue("k_force", kv["workload"], kv["precision"], *other) is None
 
 
 def _fake_run(force_ms, force_n, steps=20):
-    return {"natoms": 113090, "n_rep": 64, "steps": steps, "ms": 1.6, "wall_s": 0.002,
+    return {"natoms": 113090, "n_rep": 64, "steps": steps, "warmup": 5, "ms": 1.6, "wall_s": 0.002,
             "kt": {"density": (0.0, 0), "force": (force_ms, force_n), "lists": (0.0, 0)},
             "stride": 10, "mean_nl": 70.0, "passes": steps, "rebuilt_reps": 3, "rebuilt_atoms": 5000,
-            "end_nl": 71.0, "max_nl": 80, "cap": 160, "launch": (2, 1024), "tuned": (2, 1024, 0.08),
+            "end_nl": 71.0, "max_nl": 80, "cap": 160, "launch": (2, 1024, 0), "tuned": (2, 1024, 0.08),
             "desc": "64 replicas", "list_builder": "global"}
 
 

@@ -73,10 +73,11 @@ def test_builders_give_bitwise_the_same_run():
 
 def test_autotune_keeps_the_trajectory():
     # the tuner times launch shapes and both builders on copies of the state and
-    # leaves the lists to be built again at the caller's positions; the
+    # builds the lists again at the caller's positions before it returns; the
     # deterministic FP32 form gives the same bits for every shape and builder,
     # so the tuned run is bitwise the untuned one with its lists rebuilt at the
-    # same step (the float32 slot groups follow the rows)
+    # same step (the float32 slot groups follow the rows), and the tuned
+    # context's first pass rebuilds no list
     import torch
 
     import paper_2201_04622_amd.eamfe as E
@@ -100,7 +101,11 @@ def test_autotune_keeps_the_trajectory():
             assert ctx.get_list_builder() in ("lds", "global")
         else:
             ctx.neigh_build(x, 0.65, 0)
-        ctx.run_switching(p, x, v, 300, 600, W_out=W)
+        ctx.row_history(reset=True)
+        ctx.run_switching(p, x, v, 300, 301)
+        # one step from freshly built lists: no replica moved half a skin
+        assert ctx.list_rebuilds()[0] == 0
+        ctx.run_switching(p, x, v, 301, 600, W_out=W)
         out.append((x.cpu().numpy(), v.cpu().numpy(), W.cpu().numpy()))
         ctx.close()
     for qa, qb in zip(out[0], out[1]):
