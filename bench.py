@@ -355,7 +355,75 @@ def run_configs(skin):
     return out
 
 
-def result_line(args, main_run, plain, cpu, configs=None):
+def free_energy_check(skin=0.45, n_eq=500, n_sw=2000, n_hold=500, t_max=1200.0):
+    """The metric's accuracy gate, measured: the replicas of the stable
+    64-replica batch at up to t_max kelvin run one bounded Frenkel--Ladd
+    protocol (n_eq steps at lambda = 0, n_sw forward, n_hold at lambda = 1,
+    n_sw backward) in FP32 and in FP64, from the same lattice and with the
+    same noise (each replica's seed).  In the hottest replicas the atoms,
+    free oscillators on k = 5 eV/A^2 springs at lambda = 1, come close enough
+    that a density passes the table's end (ETABLE_RANGE at 1600 K), so they
+    are left out with a margin.  Per
+    replica the switching estimate (W_fwd - W_bwd)/2 of Eq. fl is taken per
+    atom in both precisions; the Einstein term and the centre-of-mass
+    correction are the same closed forms in both and cancel in the
+    difference.  Returns the mean, standard error and largest magnitude of
+    FP32 - FP64 over the replicas in meV/atom, the replicas' temperature at
+    that largest one, and the 0.5 meV/atom gate."""
+    import numpy as np
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    from paper_2201_04622_amd import inputs as I
+    wl = I.workload("batch64", stable=True)
+    reps = [r for r in wl.replicas if r.T <= t_max]
+    arrs = I.batch_arrays(reps)
+    p = E.protocol("fl", n_eq, n_sw, n_hold, 0, skin=skin)
+    S = len(E.lambda_schedule(p)) - 1
+    natoms = np.array([r.natoms for r in reps], dtype=np.float64)
+    t0 = time.perf_counter()
+    est = {}
+    for prec in (E.FP32, E.FP64):
+        ctx = E.Context(0, prec)
+        ctx.eam_setup(I.synthetic_eam_knots())
+        x = E.to_soa(arrs["x0"])
+        ctx.system_setup(reps, x)
+        v = torch.zeros_like(x)
+        ctx.init_velocities(v, True)
+        ctx.neigh_build(x, skin, 0)
+        W = torch.zeros(len(reps), S, dtype=torch.float64, device="cuda")
+        ctx.run_switching(p, x, v, 0, S, W_out=W)
+        torch.cuda.synchronize()
+        Wf, Wb = E.switch_works(p, W.cpu().numpy())
+        ctx.check()
+        ctx.close()
+        est[prec] = (Wf - Wb) / 2.0 / natoms
+    return free_energy_summary(est[E.FP32], est[E.FP64], [r.T for r in reps],
+                               f"{wl.description}, stable lattice, the replicas at T <= {t_max:g} K",
+                               (n_eq, n_sw, n_hold),
+                               time.perf_counter() - t0)
+
+
+def free_energy_summary(d32, d64, temps, workload, legs, wall_s, gate_mev=0.5):
+    """The free_energy_check record from per-replica per-atom estimates (eV)."""
+    import numpy as np
+    d = (np.asarray(d32, dtype=np.float64) - np.asarray(d64, dtype=np.float64)) * 1e3   # meV/atom
+    if d.size == 0 or not np.all(np.isfinite(d)):
+        raise ValueError("free_energy_check: no finite per-replica estimates")
+    i = int(np.argmax(np.abs(d)))
+    mean = float(d.mean())
+    se = float(d.std(ddof=1) / np.sqrt(d.size)) if d.size > 1 else 0.0
+    return {
+        "workload": workload, "replicas": int(d.size),
+        "protocol": f"FL, {legs[0]} steps at lambda 0, {legs[1]} forward, {legs[2]} at lambda 1, {legs[1]} backward",
+        "quantity": "(W_fwd - W_bwd) / 2 per atom, Eq. fl, FP32 minus FP64, same noise",
+        "mean_meV_per_atom": mean, "se_meV_per_atom": se, "max_abs_meV_per_atom": float(abs(d[i])),
+        "T_at_max_K": float(temps[i]), "gate_meV_per_atom": gate_mev,
+        "within_gate": bool(abs(mean) <= gate_mev), "wall_s": round(wall_s, 2),
+    }
+
+
+def result_line(args, main_run, plain, cpu, configs=None, dF=None):
     """The bench's one JSON line from the measured legs (no GPU calls here)."""
     value = main_run["natoms"] * main_run["steps"] / (main_run["ms"] / 1e3)
     kt = main_run["kt"]
@@ -397,6 +465,7 @@ def result_line(args, main_run, plain, cpu, configs=None):
         "fp64_plain_single_replica": plain,
         "cpu_baseline": cpu,
         "other_configs": configs,
+        "fp32_free_energy_check": dF,
     }
     if plain:
         out["batched_fp32_over_plain_fp64"] = value / plain["value"]
@@ -427,6 +496,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' bounded runs")
+    ap.add_argument("--no-dF", action="store_true",
+                    help="skip the FP32 against FP64 free-energy check on the stable batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -459,8 +530,9 @@ def main():
             "ms_per_step": pr["ms"] / 2000,
         }
     configs = None if args.no_configs else run_configs(args.skin)
+    dF = None if args.no_dF else free_energy_check()
     cpu = None if args.no_cpu else cpu_baseline()
-    print(json.dumps(result_line(args, main_run, plain, cpu, configs)), flush=True)
+    print(json.dumps(result_line(args, main_run, plain, cpu, configs, dF)), flush=True)
 
 
 if __name__ == "__main__":

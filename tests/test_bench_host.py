@@ -164,3 +164,23 @@ def test_config_records_and_graph_ratio(bench):
     out = bench.result_line(_Args, run, None, None, {"x": rec})
     assert out["other_configs"]["x"]["workload"].startswith("rs_scan_fp32")
     json.dumps(out)
+
+
+def test_free_energy_summary(bench):
+    d64 = [-4.0, -4.1, -3.9, -4.2]
+    off = [1e-4, -2e-4, 3e-4, 0.0]          # eV/atom
+    r = bench.free_energy_summary([a + b for a, b in zip(d64, off)], d64, [100.0, 200.0, 300.0, 400.0],
+                                  "four replicas", (5, 20, 5), 1.0)
+    import numpy as np
+    d = np.array(off) * 1e3
+    assert r["mean_meV_per_atom"] == pytest.approx(d.mean(), abs=1e-9)
+    assert r["se_meV_per_atom"] == pytest.approx(d.std(ddof=1) / 2.0, abs=1e-9)
+    assert r["max_abs_meV_per_atom"] == pytest.approx(0.3, abs=1e-9) and r["T_at_max_K"] == 300.0
+    assert r["replicas"] == 4 and r["within_gate"]
+    assert "5 steps at lambda 0, 20 forward" in r["protocol"]
+    far = bench.free_energy_summary([a + 6e-4 for a in d64], d64, [100.0] * 4, "w", (5, 20, 5), 1.0)
+    assert not far["within_gate"] and far["mean_meV_per_atom"] == pytest.approx(0.6, abs=1e-9)
+    with pytest.raises(ValueError):
+        bench.free_energy_summary([], [], [], "w", (5, 20, 5), 1.0)
+    with pytest.raises(ValueError):
+        bench.free_energy_summary([float("nan")], [0.0], [100.0], "w", (5, 20, 5), 1.0)
