@@ -12,11 +12,18 @@ pass, force pass with the fused spring/blend/BAOAB update and the work
 increment.  The metric is atom-steps/s over the K timed steps (inputs
 resident on the device, protocol continued from the W warm-up steps).
 
-Also reported: the plain single-replica FP64 path (bcc 10^3, 2000 atoms),
-the dominant kernel's roofline figure from HIP events recorded on its
-stream, and the FP64 CPU oracle timed on a bounded sample on the host.
+Also reported, in the same JSON line:
+  * the dominant kernel's (the force pass's) roofline figure, its sampled
+    launches stamped with their own start and end by HIP's extended launch
+    on the library's stream, with counter traffic and issue shares from a
+    committed summary of the same run;
+  * the plain single-replica FP64 path (bcc 10^3, 2000 atoms);
+  * bounded runs of the other workloads (stable lattice, FP64 batch, eager
+    against hipGraph, RS scan, large FL batch);
+  * an FP32 against FP64 free-energy check on the stable batch;
+  * the FP64 CPU oracle timed on a bounded sample on the host cores.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-fp64] [--no-configs] [--no-dF]
 """
 import argparse
 import json
