@@ -339,9 +339,10 @@ __device__ __forceinline__ void wave_sum(double (&v)[K])
         for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], o, 64);
 }
 
-// Store the wavefront's sum of K per-lane values as unit `idx`'s partial.
+// Store the wavefront's sum of K per-lane values as unit `idx`'s partial
+// (tile_base: the replica's first unit slot).
 template <int K>
-__device__ __forceinline__ void unit_partial(const double (&vin)[K], double* part, const RepDesc& R, int idx)
+__device__ __forceinline__ void unit_partial(const double (&vin)[K], double* part, int tile_base, int idx)
 {
     double v[K];
 #pragma unroll
@@ -349,7 +350,13 @@ __device__ __forceinline__ void unit_partial(const double (&vin)[K], double* par
     wave_sum<K>(v);
     if (wave_lane() == 0)
 #pragma unroll
-        for (int k = 0; k < K; ++k) part[(size_t)(R.tile_base + idx) * K + k] = v[k];
+        for (int k = 0; k < K; ++k) part[(size_t)(tile_base + idx) * K + k] = v[k];
+}
+
+template <int K>
+__device__ __forceinline__ void unit_partial(const double (&vin)[K], double* part, const RepDesc& R, int idx)
+{
+    unit_partial<K>(vin, part, R.tile_base, idx);
 }
 
 // Exact replica sums of the fixed-point form: each lane's value is rounded to
@@ -381,6 +388,48 @@ __device__ __forceinline__ void replica_total(const double* part, const RepDesc&
     wave_sum<K>(out);
 }
 
+// The same total in two halves, so that its loads can go out with other
+// loads: replica_loads issues the partials of the lane's first two units
+// (t = lane, lane + 64; a unit past the replica's last reads unit 0 and is
+// dropped), replica_finish adds them and any further units in the order of
+// replica_total and takes the butterfly, so the result is the same bits.
+// tb, nt: the replica's first unit slot and its number of units.
+template <int K>
+struct PartPair {
+    double p[2][K];
+};
+
+template <int K>
+__device__ __forceinline__ PartPair<K> replica_loads(const double* part, int tb, int nt)
+{
+    PartPair<K> q;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = wave_lane() + 64 * h;
+        const size_t o = (size_t)(tb + (t < nt ? t : 0)) * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) q.p[h][k] = part[o + k];
+    }
+    return q;
+}
+
+template <int K>
+__device__ __forceinline__ void replica_finish(const PartPair<K>& q, const double* part, int tb, int nt,
+                                               double (&out)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (wave_lane() + 64 * h < nt)
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[k] += q.p[h][k];
+    for (int t = wave_lane() + 128; t < nt; t += 64)
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] += part[(size_t)(tb + t) * K + k];
+    wave_sum<K>(out);
+}
+
 // Run body(u) for every unit of this wavefront's stride.  Uniform loop
 // bounds (scalar values) keep the whole body wave-uniform.
 template <typename Body>
@@ -395,6 +444,26 @@ __device__ __forceinline__ void for_each_unit(const int* qoff, int nq, int grid,
     for (int u = lb * wpb + wib; u < len; u += nb * wpb) body(first + u);
 }
 
+// Block-wide copy of n 16-byte items, U per thread per round: a round's
+// loads all go out before its first store, so the copy waits on memory once
+// per round rather than once per item.  Past the end a lane reads item n - 1
+// again (in bounds, not stored): loads without a condition cannot be moved
+// behind the stores.
+template <int U, typename V, typename Ld, typename St>
+__device__ __forceinline__ void copy_rounds(int n, Ld&& ld, St&& st)
+{
+    const int bs = (int)blockDim.x;
+    for (int k0 = threadIdx.x; k0 < n; k0 += U * bs) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld(min(k0 + u * bs, n - 1));
+        __builtin_amdgcn_sched_barrier(0);   // every load of the round issued before the stores
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * bs < n) st(k0 + u * bs, v[u]);
+    }
+}
+
 // Units of a pair launch.  Persistent form: for_each_unit over the unit
 // groups.  Staged form: block b serves slice b (a run of units of one
 // replica): it copies that replica's records into LDS at st and its
@@ -402,25 +471,30 @@ __device__ __forceinline__ void for_each_unit(const int* qoff, int nq, int grid,
 // stage_table() copies the pair kernel's table into LDS; in the staged
 // form the records are copied in the same phase, behind one barrier (the
 // slice carries its replica's first atom and size, so nothing waits on
-// further descriptor loads).
+// further descriptor loads), and each wavefront's first unit descriptor is
+// read before the copy, so its latency hides under the copy's.
+// body(tile) runs one unit.
 template <bool kStage, typename Table, typename Body>
 __device__ __forceinline__ void run_units(const StepArgs& a, uint4* st, Table&& stage_table, Body&& body)
 {
     if constexpr (kStage) {
         const int4 sl = a.slices[blockIdx.x];   // first unit, units, replica's first atom, atoms
         if (sl.y <= 0) return;                  // uniform over the block
-        stage_table();
-        for (int k = threadIdx.x; k < sl.w; k += blockDim.x) st[k] = a.Q[sl.z + k];
-        __syncthreads();
         const int wpb = (int)(blockDim.x >> 6);
         const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        for (int u = wib; u < sl.y; u += wpb) body(sl.x + u);
+        Tile first{};
+        if (wib < sl.y) first = a.tiles[sl.x + wib];
+        stage_table();
+        copy_rounds<4, uint4>(sl.w, [&](int k) { return a.Q[sl.z + k]; }, [&](int k, const uint4& q) { st[k] = q; });
+        __syncthreads();
+        for (int u = wib; u < sl.y; u += wpb) body(u == wib ? first : a.tiles[sl.x + u]);
     } else {
         if (a.has_eam) {
             stage_table();
             __syncthreads();
         }
-        for_each_unit(a.qoff, a.nq, (int)gridDim.x - a.finish_prev, body);   // a finish block is the last
+        for_each_unit(a.qoff, a.nq, (int)gridDim.x - a.finish_prev,
+                      [&](int tix) { body(a.tiles[tix]); });   // a finish block is the last
     }
 }
 
@@ -1127,7 +1201,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
         if constexpr (kLds) {
             const float4* g = (const float4*)a.tab.rho;
-            for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) lds_tab[k] = g[k];
+            copy_rounds<2, float4>(nr - 1, [&](int k) { return g[k]; }, [&](int k, const float4& c) { lds_tab[k] = c; });
             if (threadIdx.x == 0) {   // padding interval: the value at r_cut
                 const float4 c = g[nr - 2];
                 lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
@@ -1135,8 +1209,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         }
     };
     uint4* const st = (uint4*)(lds_tab + nr);   // staged form: the block's replica records, after the table
-    auto unit = [&](int tix) {
-    const Tile tl = a.tiles[tix];
+    auto unit = [&](const Tile& tl) {
     const RepDesc& R = a.reps[tl.rep];
     const int lane = wave_lane() % T;
     const int la = wave_lane() / T;
@@ -1203,21 +1276,34 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
     }
 #pragma unroll
     for (int o = T / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, T);
-    if (valid && lane == 0 && a.has_eam) {
-        const double rho = Acc<real, kFix>::fin(acc);
-        real t;
-        const int m = interval<real>((real)rho, (real)a.tab.inv_h_rho, a.tab.n_rho, t);
-        const auto c = Tab<real>::ld4(a.tab.F, m);
-        const real F = c.x + t * (c.y + t * (c.z + t * c.w));
-        const real Fp = (c.y + t * ((real)2 * c.z + (real)3 * t * c.w)) * (real)a.tab.inv_h_rho;
-        if constexpr (kQ) a.Q[i].w = __float_as_uint((float)Fp);
-        else a.P[i].w = (double)Fp;
-        a.e_emb[i] = (double)F;
-        if (a.rho_out) a.rho_out[i] = rho;
-        if (rho > a.tab.rho_max) atomicOr(a.status, ST_TABLE_RANGE);
-        if (!isfinite(rho)) atomicOr(a.status, ST_NONFINITE);
+    // one memory round trip for the epilogue: the embedding table's interval
+    // and what the epilogue needs of the replica go out together, ahead of
+    // the unit's stores (after a store every descriptor read would be a round
+    // trip of its own)
+    const bool emb = valid && lane == 0 && a.has_eam;
+    double rho = 0.0;
+    real tF = (real)0;
+    decltype(Tab<real>::ld4(a.tab.F, 0)) cF{};
+    if (emb) {
+        rho = Acc<real, kFix>::fin(acc);
+        const int m = interval<real>((real)rho, (real)a.tab.inv_h_rho, a.tab.n_rho, tF);
+        cF = Tab<real>::ld4(a.tab.F, m);
     }
-    if (tl.idx == 0 && wave_lane() == 0) a.rebuild[tl.rep] = 0;   // lists are current now
+    const uint64_t seed_raw = R.seed;
+    const int roff_raw = R.off, tbase_raw = R.tile_base, ntile_raw = R.n_tiles, cbase_raw = R.cell_base;
+    // a replica rebuilt in this step: the list pass has read its cell
+    // counters, which the unit clears for its next binning (every operand
+    // read at once, no chain of conditional reads)
+    const int nc0 = R.nc[0], nc1 = R.nc[1], nc2 = R.nc[2], rlds = R.lds;
+    const int fp0 = a.flag_pre[tl.rep], fp1 = a.flag_pre[tl.rep + 1];
+    const uint64_t seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(seed_raw >> 32)) << 32) |
+                          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)seed_raw);
+    const int roff = __builtin_amdgcn_readfirstlane(roff_raw);
+    const int tbase = __builtin_amdgcn_readfirstlane(tbase_raw);
+    const int ntile = __builtin_amdgcn_readfirstlane(ntile_raw);
+    const int cbase = __builtin_amdgcn_readfirstlane(cbase_raw);
+    const bool clear = (a.cell_cnt != nullptr) & (nc0 > 0) & (rlds == 0) & (fp1 > fp0);
+    const int ncell_clear = __builtin_amdgcn_readfirstlane(clear ? nc0 * nc1 * nc2 : 0);
 
     // thermostat noise of step `it` and (fixed centre of mass) its replica sum.
     // In the exact-sum form the deviates themselves go on the 2^-36 grid, so
@@ -1228,7 +1314,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         double z[3] = {0.0, 0.0, 0.0};
         if constexpr (T == 1) {
             if (valid) {
-                gauss3(R.seed, (uint32_t)(i - R.off), it, 0u, z[0], z[1], z[2]);
+                gauss3(seed, (uint32_t)(i - roff), it, 0u, z[0], z[1], z[2]);
                 if (kGrid && a.fix_com) on_grid<3>(z, kGridZ, kGridZInv);
                 a.xi[i] = z[0];
                 a.xi[N + i] = z[1];
@@ -1236,7 +1322,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
             }
         } else if (valid && lane < 2) {   // lane 0: x and y components, lane 1: z
             double za, zb;
-            gauss3_half(R.seed, (uint32_t)(i - R.off), it, 0u, lane, za, zb);
+            gauss3_half(seed, (uint32_t)(i - roff), it, 0u, lane, za, zb);
             if (kGrid && a.fix_com) {
                 za = rint(za * kGridZ) * kGridZInv;
                 zb = rint(zb * kGridZ) * kGridZInv;
@@ -1251,14 +1337,22 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
                 a.xi[2 * N + i] = za;
             }
         }
-        if (a.fix_com) unit_partial<3>(z, a.noise_part, R, tl.idx);
+        if (a.fix_com) unit_partial<3>(z, a.noise_part, tbase, tl.idx);
     }
-    // a replica rebuilt in this step: the list pass has read its cell counters,
-    // which are cleared here for its next binning
-    if (a.cell_cnt && R.nc[0] > 0 && !R.lds && a.flag_pre[tl.rep + 1] > a.flag_pre[tl.rep]) {
-        const int ncell = R.nc[0] * R.nc[1] * R.nc[2];
-        for (int c = tl.idx * 64 + wave_lane(); c < ncell; c += R.n_tiles * 64) a.cell_cnt[R.cell_base + c] = 0;
+    if (emb) {
+        const auto& c = cF;
+        const real t = tF;
+        const real F = c.x + t * (c.y + t * (c.z + t * c.w));
+        const real Fp = (c.y + t * ((real)2 * c.z + (real)3 * t * c.w)) * (real)a.tab.inv_h_rho;
+        if constexpr (kQ) a.Q[i].w = __float_as_uint((float)Fp);
+        else a.P[i].w = (double)Fp;
+        a.e_emb[i] = (double)F;
+        if (a.rho_out) a.rho_out[i] = rho;
+        if (rho > a.tab.rho_max) atomicOr(a.status, ST_TABLE_RANGE);
+        if (!isfinite(rho)) atomicOr(a.status, ST_NONFINITE);
     }
+    if (tl.idx == 0 && wave_lane() == 0) a.rebuild[tl.rep] = 0;   // lists are current now
+    for (int c = tl.idx * 64 + wave_lane(); c < ncell_clear; c += ntile * 64) a.cell_cnt[cbase + c] = 0;
     };   // unit
     run_units<kStage>(a, st, stage_table, unit);
 }
@@ -1297,10 +1391,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     auto stage_table = [&]() {
         if constexpr (kLds) {
             const float4* g = (const float4*)a.tab.pair;
-            for (int k = threadIdx.x; k < nr - 1; k += blockDim.x) {
-                lds_tab[k] = g[2 * k];
-                lds_tab[nr + k] = g[2 * k + 1];
-            }
+            // the two halves as 2 (nr - 1) items: item k is half k % 2 of interval k / 2
+            copy_rounds<4, float4>(2 * (nr - 1), [&](int k) { return g[k]; },
+                                   [&](int k, const float4& c) { lds_tab[(k & 1) * nr + (k >> 1)] = c; });
             if (threadIdx.x == 0) {   // padding interval: phi(r_cut), zero slopes
                 const float4 c = g[2 * (nr - 2)];
                 lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
@@ -1312,8 +1405,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     const double lam_it = a.step_kernel ? a.lam[it] : 0.0;
     const double lam_next = a.step_kernel && it < a.it_last ? a.lam[it + 1] : 0.0;
     uint4* const st = (uint4*)(lds_tab + 2 * nr);   // staged form: the block's replica records, after the table
-    auto unit = [&](int tix) {
-    const Tile tl = a.tiles[tix];
+    auto unit = [&](const Tile& tl) {
     const RepDesc& R = a.reps[tl.rep];
     const int lane = wave_lane() % T;
     const int la = wave_lane() / T;
@@ -1322,12 +1414,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 
     const double4 pi = a.P[i];
     const uint4 qi = kQ ? a.Q[i] : make_uint4(0u, 0u, 0u, 0u);
+    const int nrow = a.has_eam ? a.nnb[i] : 0;   // row length: the walk, then the list work of the pass
+    // the replica's unit slots, held in scalar registers across the walk so
+    // that the noise partials' loads need no descriptor read after it
+    const int tbase = __builtin_amdgcn_readfirstlane(R.tile_base);
+    const int ntile = __builtin_amdgcn_readfirstlane(R.n_tiles);
     const float qsx = (float)(R.L[0] * 2.3283064365386963e-10), qsy = (float)(R.L[1] * 2.3283064365386963e-10),
                 qsz = (float)(R.L[2] * 2.3283064365386963e-10);
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, ep = 0.0;
     double w0 = 0.0, w1 = 0.0, w2 = 0.0;   // virial (kVir): sum_j (x_i - x_j)_a f_ij,a per axis
     if (valid && a.has_eam) {
-        const int n = a.nnb[i];
+        const int n = nrow;
         const real Fpi = kQ ? (real)__uint_as_float(qi.w) : (real)pi.w;
         const real rc2 = (real)a.tab.rc2, inv_h = (real)a.tab.inv_h_r;
         const uint32_t rc2m1 = __float_as_uint((float)a.tab.rc2) - 1u;   // FP32 form's cutoff test
@@ -1437,31 +1534,39 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         }
     }
 
-    // the atom's operands of the integration, issued before the replica's
-    // noise total so that the two latencies overlap (i is in range on every lane)
+    // the atom's operands of the integration and the replica's noise
+    // partials go out together, one memory round trip after the walk (i is in
+    // range on every lane; arrays a pass does not use are stood in for by x0,
+    // which every pass has, and their values are not used)
     const bool stepping = a.step_kernel != 0, opening = stepping && it < a.it_last;
+    const bool noise_total = opening && a.fix_com;
+    // the replica's constants of the integration (after the first store below
+    // each would be a round trip of its own)
+    const double r_inv_m = R.inv_m, r_k = R.k, r_k2 = R.k2, r_c2 = R.c2, r_n = (double)R.n;
+    const double r_invL[3] = {R.invL[0], R.invL[1], R.invL[2]};
+    const double* vsrc = stepping ? a.v : a.x0;
+    const double* xisrc = opening ? a.xi : a.x0;
+    const double* xrsrc = opening ? a.xref : a.x0;
     const double x0i[3] = {a.x0[i], a.x0[N + i], a.x0[2 * N + i]};
-    const double ks = a.kscale ? a.kscale[i] : 1.0;   // this atom's spring is k ks
-    const double eemb = a.has_eam ? a.e_emb[i] : 0.0;
-    const int nrow = a.has_eam ? a.nnb[i] : 0;
+    const double ks_raw = a.kscale ? a.kscale[i] : 1.0;   // this atom's spring is k ks
+    const double eemb_raw = a.has_eam ? a.e_emb[i] : 0.0;
+    const double vraw[3] = {vsrc[i], vsrc[N + i], vsrc[2 * N + i]};
+    const double xiraw[3] = {xisrc[i], xisrc[N + i], xisrc[2 * N + i]};
+    const double xrraw[3] = {xrsrc[i], xrsrc[N + i], xrsrc[2 * N + i]};
+    PartPair<3> zp;
+    if (noise_total) zp = replica_loads<3>(a.noise_part, tbase, ntile);
+    const double ks = ks_raw, eemb = eemb_raw;
     double vi[3] = {0.0, 0.0, 0.0}, xii[3] = {0.0, 0.0, 0.0}, xr[3] = {0.0, 0.0, 0.0};
-    if (stepping) {
-        vi[0] = a.v[i];
-        vi[1] = a.v[N + i];
-        vi[2] = a.v[2 * N + i];
-    }
-    if (opening) {
-        xii[0] = a.xi[i];
-        xii[1] = a.xi[N + i];
-        xii[2] = a.xi[2 * N + i];
-        xr[0] = a.xref[i];
-        xr[1] = a.xref[N + i];
-        xr[2] = a.xref[2 * N + i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        vi[c] = stepping ? vraw[c] : 0.0;
+        xii[c] = opening ? xiraw[c] : 0.0;
+        xr[c] = opening ? xrraw[c] : 0.0;
     }
 
     // the replica's thermostat noise of this step, from the density pass's unit partials
     double zsum[3] = {0.0, 0.0, 0.0};
-    if (opening && a.fix_com) replica_total<3>(a.noise_part, R, zsum);
+    if (noise_total) replica_finish<3>(zp, a.noise_part, tbase, ntile, zsum);
 
     double e[3] = {0.0, 0.0, 0.0};   // U_EAM contribution, |x - x0|^2, row length (list work of the pass)
     if (valid && lane == 0) {
@@ -1481,30 +1586,31 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
         }
         if (a.e_atom_out) a.e_atom_out[i] = e[0];
         if (stepping) {
-            const double hdt_m = 0.5 * a.dt * R.inv_m;
+            const double hdt_m = 0.5 * a.dt * r_inv_m;
             double v[3] = {vi[0], vi[1], vi[2]};
             double F[3];
             if (it > a.it_first) {   // closing kick of step it-1 at lambda_it
-                total_force(a.mode, fe, d, R.k, R.k2, lam_it, F);
+                total_force(a.mode, fe, d, r_k, r_k2, lam_it, F);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) v[c] += hdt_m * F[c];
             }
             if (opening) {    // step it: B A O A with lambda_{it+1}
-                total_force(a.mode, fe, d, R.k, R.k2, lam_next, F);
-                const double inv_n = 1.0 / (double)R.n;
+                total_force(a.mode, fe, d, r_k, r_k2, lam_next, F);
+                const double inv_n = 1.0 / r_n;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     v[c] += hdt_m * F[c];
                     x[c] += 0.5 * a.dt * v[c];
                     const double m = a.fix_com ? zsum[c] * inv_n : 0.0;
-                    v[c] = a.c1 * v[c] + R.c2 * (xii[c] - m);
+                    v[c] = a.c1 * v[c] + r_c2 * (xii[c] - m);
                     x[c] += 0.5 * a.dt * v[c];
                 }
                 const double r0 = x[0] - xr[0], r1 = x[1] - xr[1], r2 = x[2] - xr[2];
                 if (r0 * r0 + r1 * r1 + r2 * r2 > a.half_skin2) a.rebuild[tl.rep] = 1;
             }
             a.Pn[i] = make_double4(x[0], x[1], x[2], 0.0);
-            a.Qn[i] = box_codes(R, x[0], x[1], x[2], 0u);   // list builder uses box coordinates in both forms
+            // list builder uses box coordinates in both forms
+            a.Qn[i] = make_uint4(box_code(x[0], r_invL[0]), box_code(x[1], r_invL[1]), box_code(x[2], r_invL[2]), 0u);
             a.v[i] = v[0];
             a.v[N + i] = v[1];
             a.v[2 * N + i] = v[2];
@@ -1512,7 +1618,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     }
 
     if constexpr (sizeof(real) == 4 && kFix) on_grid<2>(e, kGridE, kGridEInv);
-    unit_partial<3>(e, a.energy_part, R, tl.idx);   // e[2], a row length, is an integer
+    unit_partial<3>(e, a.energy_part, tbase, tl.idx);   // e[2], a row length, is an integer
     if constexpr (kVir) {   // pressure evaluation: (1/2) pair virial plus m v_a^2 of the atom, per unit
         double pv[3] = {0.0, 0.0, 0.0};
         if (valid && lane == 0) {
@@ -1520,11 +1626,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double vc = a.v ? a.v[c * N + i] : 0.0;
-                pv[c] = 0.5 * wv[c] + vc * vc / R.inv_m;
+                pv[c] = 0.5 * wv[c] + vc * vc / r_inv_m;
             }
         }
         if constexpr (sizeof(real) == 4 && kFix) on_grid<3>(pv, kGridE, kGridEInv);
-        unit_partial<3>(pv, a.vir_part, R, tl.idx);
+        unit_partial<3>(pv, a.vir_part, tbase, tl.idx);
     }
     };   // unit
     run_units<kStage>(a, st, stage_table, unit);
