@@ -664,7 +664,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
 {
     if (blockIdx.x == 0) {
         const int flagged = flag_prefix(a.reps, a.rebuild, a.n_rep, a.flag_pre);
-        if (s.step_kernel && threadIdx.x == 0) {   // rebuild history of the step passes
+        if (s.step_kernel && threadIdx.x == 0 && flagged > 0) {   // rebuild history of the step passes (no zeros)
             s.row_acc[a.n_rep + 1] += (double)flagged;
             s.row_acc[a.n_rep + 2] += (double)a.flag_pre[a.n_rep];
         }
@@ -723,6 +723,7 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
         const int il = f - pre[lo];
         const int i = roff + il;
         const uint4 qi = a.Q[i];
+        const double4 pi = a.P[i];   // the list's reference position, read with the record
         const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
                     sz = (float)(R.L[2] * 2.3283064365386963e-10);
         int cnt = 0;
@@ -897,7 +898,6 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
                 cnt = cap;
             }
             a.nnb[i] = cnt;
-            const double4 pi = a.P[i];
             a.xref[i] = pi.x;
             a.xref[N + i] = pi.y;
             a.xref[2 * N + i] = pi.z;
@@ -932,13 +932,18 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                       (size_t)w * rows_lds_wave_bytes(a.cap));
     __shared__ int sh_nf, sh_atoms, sh_rep, sh_part, sh_parts;
     __shared__ int wsum[16];
+    // the builder's k-th replica: the list holds them in replica order, so
+    // when it holds every replica it is the identity, and the flag and size
+    // reads need not wait for it
+    const bool all = a.n_lds == a.n_rep;
+    auto lds_rep = [&](int k) { return all ? k : a.lds_list[k]; };
 
     // flagged replicas of this builder: their number and atoms
     if (w == 0) {
         int nf = 0, at = 0;
         for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
             const int k = k0 + lw;
-            const int r = k < a.n_lds ? a.lds_list[k] : 0;
+            const int r = k < a.n_lds ? lds_rep(k) : 0;
             const bool f = k < a.n_lds && a.rebuild[r] != 0;
             nf += __popcll(__ballot(f));
             int n = f ? a.reps[r].n : 0;
@@ -953,11 +958,11 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
     }
     __syncthreads();
     const int nf = sh_nf, atoms_f = sh_atoms;
+    if (nf == 0) return;   // (the history below would add zeros)
     if (blockIdx.x == 0 && threadIdx.x == 0 && s.step_kernel) {   // rebuild history of the step passes
         s.row_acc[a.n_rep + 1] += (double)nf;
         s.row_acc[a.n_rep + 2] += (double)atoms_f;
     }
-    if (nf == 0) return;
     const int G = gridDim.x;
     // items: each flagged replica cut into parts in proportion to its atoms,
     // about G items in all; the items are numbered replica by replica
@@ -966,7 +971,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
     if (w == 0) {
         for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
             const int k = k0 + lw;
-            const int r = k < a.n_lds ? a.lds_list[k] : 0;
+            const int r = k < a.n_lds ? lds_rep(k) : 0;
             int pr = (k < a.n_lds && a.rebuild[r] != 0) ? parts_of(a.reps[r].n) : 0;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o, 64);
@@ -985,7 +990,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
             int seen = 0;
             for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
                 const int k = k0 + lw;
-                const int r = k < a.n_lds ? a.lds_list[k] : 0;
+                const int r = k < a.n_lds ? lds_rep(k) : 0;
                 const int pr = (k < a.n_lds && a.rebuild[r] != 0) ? parts_of(a.reps[r].n) : 0;
                 int incl = pr;
 #pragma unroll
@@ -1016,7 +1021,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
         const int roff = R.off, rn = R.n;
         const int nc0 = R.nc[0], nc1 = R.nc[1], nc2 = R.nc[2];
         const int ncell = nc0 * nc1 * nc2;
-        for (int k = threadIdx.x; k < rn; k += blockDim.x) st[k] = a.Q[roff + k];
+        copy_rounds<4, uint4>(rn, [&](int k) { return a.Q[roff + k]; }, [&](int k, const uint4& q) { st[k] = q; });
         if (nc0 > 0)
             for (int c = threadIdx.x; c <= ncell; c += blockDim.x) cst[c] = 0;
         __syncthreads();
@@ -1078,6 +1083,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
         for (int il = a0 + w; il < a1; il += nw) {
             const int i = roff + il;
             const uint4 qi = st[il];
+            const double4 pi = a.P[i];   // the list's reference position, read ahead of the row work
             auto close_to = [&](const uint4& qj) {
                 const float dx = (float)(int)(qi.x - qj.x) * sx, dy = (float)(int)(qi.y - qj.y) * sy,
                             dz = (float)(int)(qi.z - qj.z) * sz;
@@ -1171,7 +1177,6 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                     cnt = a.cap;
                 }
                 a.nnb[i] = cnt;
-                const double4 pi = a.P[i];
                 a.xref[i] = pi.x;
                 a.xref[a.N + i] = pi.y;
                 a.xref[2 * a.N + i] = pi.z;
