@@ -930,15 +930,57 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
     int* cst = (int*)((char*)ids + (((size_t)a.lds_atoms * 2 + 15) & ~(size_t)15));
     int* row = (int*)((char*)cst + (((size_t)(a.lds_cells + 1) * 4 + 15) & ~(size_t)15) +
                       (size_t)w * rows_lds_wave_bytes(a.cap));
-    __shared__ int sh_nf, sh_atoms, sh_rep, sh_part, sh_parts;
+    __shared__ int sh_nf, sh_atoms, sh_items, sh_rep, sh_part, sh_parts, sh_roff, sh_rn;
     __shared__ int wsum[16];
     // the builder's k-th replica: the list holds them in replica order, so
     // when it holds every replica it is the identity, and the flag and size
     // reads need not wait for it
     const bool all = a.n_lds == a.n_rep;
     auto lds_rep = [&](int k) { return all ? k : a.lds_list[k]; };
+    const int G = gridDim.x;
+    // items: each flagged replica cut into parts in proportion to its atoms,
+    // about G items in all, numbered replica by replica.  Wave 0 finds the
+    // replica, part, first atom and size of item `it` (sh_*); atoms_f: the
+    // flagged replicas' atoms.  Returns the number of items.
+    auto select = [&](int it, int atoms_f) {
+        int seen = 0;
+        bool found = false;
+        for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
+            const int k = k0 + lw;
+            const int r = k < a.n_lds ? lds_rep(k) : 0;
+            const bool f = k < a.n_lds && a.rebuild[r] != 0;
+            const int2 on = f ? *(const int2*)&a.reps[r].off : make_int2(0, 0);   // first atom, atoms
+            const int pr = f ? max(1, (int)(((long long)on.y * G) / atoms_f)) : 0;
+            int incl = pr;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lw >= o) incl += y;
+            }
+            const int chunk_total = __builtin_amdgcn_readlane(incl, 63);
+            if (!found && it < seen + chunk_total) {   // uniform: the lane whose parts hold it
+                const bool mine = pr > 0 && it >= seen + incl - pr && it < seen + incl;
+                const int src = (int)__ffsll((long long)__ballot(mine)) - 1;
+                const int rsel = __shfl(r, src, 64);
+                const int first = __shfl(seen + incl - pr, src, 64);
+                const int psel = __shfl(pr, src, 64);
+                const int osel = __shfl(on.x, src, 64), nsel = __shfl(on.y, src, 64);
+                if (lw == 0) {
+                    sh_rep = rsel;
+                    sh_part = it - first;
+                    sh_parts = psel;
+                    sh_roff = osel;
+                    sh_rn = nsel;
+                }
+                found = true;
+            }
+            seen += chunk_total;
+        }
+        return seen;
+    };
 
-    // flagged replicas of this builder: their number and atoms
+    // flagged replicas of this builder (their number and atoms) and this
+    // block's first item, behind one barrier
     if (w == 0) {
         int nf = 0, at = 0;
         for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
@@ -951,77 +993,35 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
             for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
             at += n;
         }
+        const int items = nf > 0 ? select(blockIdx.x, at) : 0;
         if (lw == 0) {
             sh_nf = nf;
             sh_atoms = at;
+            sh_items = items;
         }
     }
     __syncthreads();
-    const int nf = sh_nf, atoms_f = sh_atoms;
+    const int nf = sh_nf, atoms_f = sh_atoms, items = sh_items;
     if (nf == 0) return;   // (the history below would add zeros)
     if (blockIdx.x == 0 && threadIdx.x == 0 && s.step_kernel) {   // rebuild history of the step passes
         s.row_acc[a.n_rep + 1] += (double)nf;
         s.row_acc[a.n_rep + 2] += (double)atoms_f;
     }
-    const int G = gridDim.x;
-    // items: each flagged replica cut into parts in proportion to its atoms,
-    // about G items in all; the items are numbered replica by replica
-    auto parts_of = [&](int n) { return max(1, (int)(((long long)n * G) / atoms_f)); };
-    int items = 0;
-    if (w == 0) {
-        for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
-            const int k = k0 + lw;
-            const int r = k < a.n_lds ? lds_rep(k) : 0;
-            int pr = (k < a.n_lds && a.rebuild[r] != 0) ? parts_of(a.reps[r].n) : 0;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o, 64);
-            items += pr;
-        }
-        if (lw == 0) wsum[0] = items;
-    }
-    __syncthreads();
-    items = wsum[0];
-    __syncthreads();
     const uint64_t below = (1ull << lw) - 1ull;
     const float rl2 = a.rl2_f;
     for (int it = blockIdx.x; it < items; it += G) {
-        // the replica and part of item it
-        if (w == 0) {
-            int seen = 0;
-            for (int k0 = 0; k0 < a.n_lds; k0 += 64) {
-                const int k = k0 + lw;
-                const int r = k < a.n_lds ? lds_rep(k) : 0;
-                const int pr = (k < a.n_lds && a.rebuild[r] != 0) ? parts_of(a.reps[r].n) : 0;
-                int incl = pr;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(incl, o, 64);
-                    if (lw >= o) incl += y;
-                }
-                const int chunk_total = __builtin_amdgcn_readlane(incl, 63);
-                if (it < seen + chunk_total) {   // uniform: the lane whose parts hold it
-                    const bool mine = pr > 0 && it >= seen + incl - pr && it < seen + incl;
-                    const int src = (int)__ffsll((long long)__ballot(mine)) - 1;
-                    const int rsel = __shfl(r, src, 64);
-                    const int first = __shfl(seen + incl - pr, src, 64);
-                    const int psel = __shfl(pr, src, 64);
-                    if (lw == 0) {
-                        sh_rep = rsel;
-                        sh_part = it - first;
-                        sh_parts = psel;
-                    }
-                    break;
-                }
-                seen += chunk_total;
-            }
+        if (it != (int)blockIdx.x) {   // a later item of this block (the first one is selected above)
+            if (w == 0) select(it, atoms_f);
+            __syncthreads();
         }
-        __syncthreads();
-        const int rr = sh_rep, part = sh_part, parts = sh_parts;
+        const int rr = sh_rep, part = sh_part, parts = sh_parts, roff = sh_roff, rn = sh_rn;
         const RepDesc& R = a.reps[rr];
-        const int roff = R.off, rn = R.n;
+        // the cell counts and box go out with the record copy's loads
         const int nc0 = R.nc[0], nc1 = R.nc[1], nc2 = R.nc[2];
-        const int ncell = nc0 * nc1 * nc2;
+        const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
+                    sz = (float)(R.L[2] * 2.3283064365386963e-10);
         copy_rounds<4, uint4>(rn, [&](int k) { return a.Q[roff + k]; }, [&](int k, const uint4& q) { st[k] = q; });
+        const int ncell = nc0 * nc1 * nc2;
         if (nc0 > 0)
             for (int c = threadIdx.x; c <= ncell; c += blockDim.x) cst[c] = 0;
         __syncthreads();
@@ -1061,25 +1061,46 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                 ids[pos] = (uint16_t)k;
             }
             __syncthreads();
-            // each cell's members in id order
+            // each cell's members in id order: up to eight in registers through
+            // a sorting network (Batcher's odd-even merge; their reads in flight
+            // together), an insertion sort in LDS beyond
             for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-                const int b = cst[c], e = cst[c + 1];
-                for (int t = b + 1; t < e; ++t) {
-                    const uint16_t x = ids[t];
-                    int u = t;
-                    while (u > b && ids[u - 1] > x) {
-                        ids[u] = ids[u - 1];
-                        --u;
+                const int b = cst[c], e = cst[c + 1], m = e - b;
+                if (m <= 1) continue;
+                if (m <= 8) {
+                    int v[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) v[t] = t < m ? (int)ids[b + t] : 0xffff;
+                    auto cmpx = [&](int p, int q) {
+                        const int lo = min(v[p], v[q]), hi = max(v[p], v[q]);
+                        v[p] = lo;
+                        v[q] = hi;
+                    };
+                    cmpx(0, 1); cmpx(2, 3); cmpx(4, 5); cmpx(6, 7);
+                    cmpx(0, 2); cmpx(1, 3); cmpx(4, 6); cmpx(5, 7);
+                    cmpx(1, 2); cmpx(5, 6);
+                    cmpx(0, 4); cmpx(1, 5); cmpx(2, 6); cmpx(3, 7);
+                    cmpx(2, 4); cmpx(3, 5);
+                    cmpx(1, 2); cmpx(3, 4); cmpx(5, 6);
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (t < m) ids[b + t] = (uint16_t)v[t];
+                } else {
+                    for (int t = b + 1; t < e; ++t) {
+                        const uint16_t x = ids[t];
+                        int u = t;
+                        while (u > b && ids[u - 1] > x) {
+                            ids[u] = ids[u - 1];
+                            --u;
+                        }
+                        ids[u] = x;
                     }
-                    ids[u] = x;
                 }
             }
         }
         __syncthreads();
         // rows of this item's atoms, one wavefront per atom
         const int a0 = (int)((long long)rn * part / parts), a1 = (int)((long long)rn * (part + 1) / parts);
-        const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
-                    sz = (float)(R.L[2] * 2.3283064365386963e-10);
         for (int il = a0 + w; il < a1; il += nw) {
             const int i = roff + il;
             const uint4 qi = st[il];
@@ -1104,8 +1125,13 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                 // 125 of a 5 x 5 x 5 block), keeping a mask of its members in
                 // range; a prefix sum of the accepted counts over the cells then
                 // gives every accepted member its slot, so the row is the stream
-                // of cells in offset order, members in id order
+                // of cells in offset order, members in id order.  Five or more
+                // cells per edge: an offset of -2..2 wraps at most once.
                 const int cx = box_cell(qi.x, nc0), cy = box_cell(qi.y, nc1), cz = box_cell(qi.z, nc2);
+                auto wrap = [](int u, int n) {
+                    u = u < 0 ? u + n : u;
+                    return u >= n ? u - n : u;
+                };
                 int cb[2], cn[2];
                 uint64_t mask[2];
 #pragma unroll
@@ -1115,9 +1141,9 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                     cn[h] = 0;
                     mask[h] = 0ull;
                     if (q < kStencil) {
-                        const int ux = (cx + q / 25 - 2 + nc0) % nc0;
-                        const int uy = (cy + (q / 5) % 5 - 2 + nc1) % nc1;
-                        const int uz = (cz + q % 5 - 2 + nc2) % nc2;
+                        const int ux = wrap(cx + q / 25 - 2, nc0);
+                        const int uy = wrap(cy + (q / 5) % 5 - 2, nc1);
+                        const int uz = wrap(cz + q % 5 - 2, nc2);
                         const int c = (ux * nc1 + uy) * nc2 + uz;
                         cb[h] = cst[c];
                         cn[h] = cst[c + 1] - cb[h];
@@ -1127,19 +1153,24 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                         }
                     }
                 }
+                // both cells' members four at a time: their id and record reads
+                // in flight together
+                for (int t0 = 0; t0 < max(cn[0], cn[1]); t0 += 4) {
+                    int jl[2][4];
+                    uint4 qj[2][4];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    for (int t0 = 0; t0 < cn[h]; t0 += 4) {   // four members' loads in flight together
-                        int jl[4];
-                        uint4 qj[4];
+                    for (int h = 0; h < 2; ++h)
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) jl[u] = t0 + u < cn[h] ? (int)ids[cb[h] + t0 + u] : il;
+                        for (int u = 0; u < 4; ++u) jl[h][u] = t0 + u < cn[h] ? (int)ids[cb[h] + t0 + u] : il;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) qj[u] = st[jl[u]];
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) qj[h][u] = st[jl[h][u]];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            if (jl[u] != il && close_to(qj[u])) mask[h] |= 1ull << (t0 + u);
-                    }
+                            if (jl[h][u] != il && close_to(qj[h][u])) mask[h] |= 1ull << (t0 + u);
                 }
                 int base = 0;
 #pragma unroll
@@ -1152,10 +1183,22 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                         if (lw >= o) incl += y;
                     }
                     int slot = base + incl - n_acc;
-                    for (uint64_t m = mask[h]; m; m &= m - 1ull) {
-                        const int t = (int)__ffsll((long long)m) - 1;
-                        if (slot < a.cap) row[slot] = roff + (int)ids[cb[h] + t];
-                        ++slot;
+                    if (cn[h] <= 8) {   // the first eight members: reads in flight together
+                        int id8[8];
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) id8[t] = (int)ids[cb[h] + min(t, max(cn[h] - 1, 0))];
+#pragma unroll
+                        for (int t = 0; t < 8; ++t)
+                            if ((mask[h] >> t) & 1ull) {
+                                if (slot < a.cap) row[slot] = roff + id8[t];
+                                ++slot;
+                            }
+                    } else {
+                        for (uint64_t m = mask[h]; m; m &= m - 1ull) {
+                            const int t = (int)__ffsll((long long)m) - 1;
+                            if (slot < a.cap) row[slot] = roff + (int)ids[cb[h] + t];
+                            ++slot;
+                        }
                     }
                     base += __builtin_amdgcn_readlane(incl, 63);
                 }
@@ -1183,7 +1226,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
             }
             __builtin_amdgcn_wave_barrier();   // the row buffer is reused by the next atom
         }
-        __syncthreads();   // the staged replica is replaced by the next item's
+        if (it + G < items) __syncthreads();   // the staged replica is replaced by the next item's
     }
 }
 
