@@ -329,6 +329,35 @@ __device__ __forceinline__ void walk_row(const int32_t* nbr, const double4* P, c
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int wave_lane() { return (int)(threadIdx.x & 63u); }
 
+// The value of lane (l xor o) of a wavefront.  For o = 1, 2, 4, 8 the lanes
+// move through DPP within each 16-lane row, which costs no LDS traffic and
+// little latency: quad permutations for 1 and 2, a half-row mirror (l xor 7)
+// followed by a quad reversal (l xor 3) for 4, a row rotation by 8 for 8;
+// wider partners go through the LDS permute.  o is a compile-time constant
+// at every call (unrolled loops), and every lane of the wavefront is active
+// there (wave-uniform control flow), so each lane reads a live value.
+__device__ __forceinline__ int xor_lanes(int v, int o)
+{
+    switch (o) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+    case 4: {
+        const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror: l xor 7
+        return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);          // quad_perm [3, 2, 1, 0]
+    }
+    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    default: return __shfl_xor(v, o, 64);
+    }
+}
+
+__device__ __forceinline__ double xor_lanes(double v, int o)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned int lo = (unsigned int)xor_lanes((int)(unsigned int)b, o);
+    const unsigned int hi = (unsigned int)xor_lanes((int)(unsigned int)(b >> 32), o);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // sum over the 64 lanes of a wavefront in a fixed butterfly order
 template <int K>
 __device__ __forceinline__ void wave_sum(double (&v)[K])
@@ -336,7 +365,7 @@ __device__ __forceinline__ void wave_sum(double (&v)[K])
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], o, 64);
+        for (int k = 0; k < K; ++k) v[k] += xor_lanes(v[k], o);
 }
 
 // Store the wavefront's sum of K per-lane values as unit `idx`'s partial
@@ -1323,7 +1352,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         });
     }
 #pragma unroll
-    for (int o = T / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, T);
+    for (int o = T / 2; o > 0; o >>= 1) acc += xor_lanes(acc, o);   // (o < T: the partner is in the atom's lanes)
     // one memory round trip for the epilogue: the embedding table's interval
     // and what the epilogue needs of the replica go out together, ahead of
     // the unit's stores (after a store every descriptor read would be a round
@@ -1571,14 +1600,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
     }
 #pragma unroll
     for (int o = T / 2; o > 0; o >>= 1) {
-        f0 += __shfl_xor(f0, o, T);
-        f1 += __shfl_xor(f1, o, T);
-        f2 += __shfl_xor(f2, o, T);
-        ep += __shfl_xor(ep, o, T);
+        f0 += xor_lanes(f0, o);   // (o < T: the partner is in the atom's lanes)
+        f1 += xor_lanes(f1, o);
+        f2 += xor_lanes(f2, o);
+        ep += xor_lanes(ep, o);
         if constexpr (kVir) {
-            w0 += __shfl_xor(w0, o, T);
-            w1 += __shfl_xor(w1, o, T);
-            w2 += __shfl_xor(w2, o, T);
+            w0 += xor_lanes(w0, o);
+            w1 += xor_lanes(w1, o);
+            w2 += xor_lanes(w2, o);
         }
     }
 
