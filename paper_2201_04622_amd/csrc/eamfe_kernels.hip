@@ -358,6 +358,22 @@ __device__ __forceinline__ double xor_lanes(double v, int o)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront (every lane active):
+// within each 16-lane row by DPP row shifts of 1, 2, 4 and 8 (a lane shifted
+// in from outside the row adds the zero of the update's old value), then
+// across rows by broadcasting lane 15 into row 1 and lane 47 into row 3, and
+// lane 31 into rows 2 and 3.  Integer adds: the same result as any order.
+__device__ __forceinline__ int wave_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15, rows 1 and 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31, rows 2 and 3
+    return x;
+}
+
 // sum over the 64 lanes of a wavefront in a fixed butterfly order
 template <int K>
 __device__ __forceinline__ void wave_sum(double (&v)[K])
@@ -547,6 +563,15 @@ __device__ __forceinline__ uint4 box_codes(const RepDesc& R, double x, double y,
     return make_uint4(box_code(x, R.invL[0]), box_code(y, R.invL[1]), box_code(z, R.invL[2]), w);
 }
 
+// A stencil cell index cell + d, d in -2..2, folded into 0..n-1: with five
+// or more cells per edge (the list planner's condition for cells) it wraps
+// at most once, so no integer division is needed.
+__device__ __forceinline__ int wrap_cell(int u, int n)
+{
+    u = u < 0 ? u + n : u;
+    return u >= n ? u - n : u;
+}
+
 // Cell of a box coordinate on an nc-cell axis (exact integer arithmetic).
 __device__ __forceinline__ int box_cell(uint32_t q, int nc) { return (int)(((uint64_t)q * (uint64_t)nc) >> 32); }
 
@@ -603,15 +628,7 @@ __device__ int flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_re
             va = reps[r].n;
             vc = reps[r].nc[0] * reps[r].nc[1] * reps[r].nc[2];
         }
-        int xa = va, xc = vc;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int ya = __shfl_up(xa, o, 64), yc = __shfl_up(xc, o, 64);
-            if (lw >= o) {
-                xa += ya;
-                xc += yc;
-            }
-        }
+        const int xa = wave_scan(va), xc = wave_scan(vc);
         const int nf = __popcll(__ballot(va > 0));   // flagged replicas of this wavefront
         if (lw == 63) {
             wa[w] = xa;
@@ -780,18 +797,13 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
                 const int q = q0 + lw;
                 int n_c = 0, c = 0;
                 if (q < kStencil) {
-                    const int ux = (cx + q / 25 - 2 + R.nc[0]) % R.nc[0];
-                    const int uy = (cy + (q / 5) % 5 - 2 + R.nc[1]) % R.nc[1];
-                    const int uz = (cz + q % 5 - 2 + R.nc[2]) % R.nc[2];
+                    const int ux = wrap_cell(cx + q / 25 - 2, R.nc[0]);
+                    const int uy = wrap_cell(cy + (q / 5) % 5 - 2, R.nc[1]);
+                    const int uz = wrap_cell(cz + q % 5 - 2, R.nc[2]);
                     c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
                     n_c = min(a.cell_cnt[c], a.ccap);
                 }
-                int incl = n_c;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(incl, o, 64);
-                    if (lw >= o) incl += y;
-                }
+                int incl = wave_scan(n_c);
                 incl += tot_c;
                 if (q < kStencil) {
                     cend[w][q] = incl;
@@ -980,12 +992,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
             const bool f = k < a.n_lds && a.rebuild[r] != 0;
             const int2 on = f ? *(const int2*)&a.reps[r].off : make_int2(0, 0);   // first atom, atoms
             const int pr = f ? max(1, (int)(((long long)on.y * G) / atoms_f)) : 0;
-            int incl = pr;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o, 64);
-                if (lw >= o) incl += y;
-            }
+            int incl = wave_scan(pr);
             const int chunk_total = __builtin_amdgcn_readlane(incl, 63);
             if (!found && it < seen + chunk_total) {   // uniform: the lane whose parts hold it
                 const bool mine = pr > 0 && it >= seen + incl - pr && it < seen + incl;
@@ -1067,12 +1074,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                 const int c0 = threadIdx.x * per, c1 = min(ncell, c0 + per);
                 int tot = 0;
                 for (int c = c0; c < c1; ++c) tot += cst[c];
-                int incl = tot;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(incl, o, 64);
-                    if (lw >= o) incl += y;
-                }
+                int incl = wave_scan(tot);
                 if (lw == 63) wsum[w] = incl;
                 __syncthreads();
                 int before = incl - tot;
@@ -1157,10 +1159,6 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                 // of cells in offset order, members in id order.  Five or more
                 // cells per edge: an offset of -2..2 wraps at most once.
                 const int cx = box_cell(qi.x, nc0), cy = box_cell(qi.y, nc1), cz = box_cell(qi.z, nc2);
-                auto wrap = [](int u, int n) {
-                    u = u < 0 ? u + n : u;
-                    return u >= n ? u - n : u;
-                };
                 int cb[2], cn[2];
                 uint64_t mask[2];
 #pragma unroll
@@ -1170,9 +1168,9 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
                     cn[h] = 0;
                     mask[h] = 0ull;
                     if (q < kStencil) {
-                        const int ux = wrap(cx + q / 25 - 2, nc0);
-                        const int uy = wrap(cy + (q / 5) % 5 - 2, nc1);
-                        const int uz = wrap(cz + q % 5 - 2, nc2);
+                        const int ux = wrap_cell(cx + q / 25 - 2, nc0);
+                        const int uy = wrap_cell(cy + (q / 5) % 5 - 2, nc1);
+                        const int uz = wrap_cell(cz + q % 5 - 2, nc2);
                         const int c = (ux * nc1 + uy) * nc2 + uz;
                         cb[h] = cst[c];
                         cn[h] = cst[c + 1] - cb[h];
@@ -1205,12 +1203,7 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int n_acc = __popcll(mask[h]);
-                    int incl = n_acc;
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const int y = __shfl_up(incl, o, 64);
-                        if (lw >= o) incl += y;
-                    }
+                    int incl = wave_scan(n_acc);
                     int slot = base + incl - n_acc;
                     if (cn[h] <= 8) {   // the first eight members: reads in flight together
                         int id8[8];
