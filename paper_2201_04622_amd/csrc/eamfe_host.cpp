@@ -1843,6 +1843,11 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
     const int lanes_c[] = {1, 2, 4, 8, 16};
     const int block_c[] = {64, 128, 256, 512, 640, 768, 1024};
     const int grid_c[] = {0, c->n_cu, 2 * c->n_cu, 4 * c->n_cu};
+    struct Cand {
+        double per;
+        int L, B, G;
+    };
+    std::vector<Cand> cands;   // every timed shape
     for (int L : lanes_c) {
         for (int B : block_c) {
           for (int G : grid_c) {
@@ -1869,6 +1874,7 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
                 float ms = 0.0f;
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 const double per = ms / (double)(s1 - step - 2);
+                cands.push_back({per, L, B, c->grid});
                 if (per < best) {
                     best = per;
                     best_l = L;
@@ -1877,6 +1883,46 @@ int eamfe_autotune(eamfe_ctx* c, const eamfe_protocol* p, int64_t step, const do
                 }
             }
           }
+        }
+    }
+    // second round: shapes within 4 % of the fastest trade places from run to
+    // run on timing noise, so the (at most four) fastest within that margin are
+    // timed again over three times the steps, and the fastest of that round wins
+    if (!rc && cands.size() > 1) {
+        std::sort(cands.begin(), cands.end(), [](const Cand& u, const Cand& w) { return u.per < w.per; });
+        const int64_t s3 = std::min<int64_t>(S, step + 2 + 3 * (int64_t)trial_steps);
+        if (step + 2 < s3) {
+            double best2 = 1e300;
+            for (size_t q = 0; q < cands.size() && q < 4 && cands[q].per <= cands[0].per * 1.04; ++q) {
+                c->lanes = cands[q].L;
+                c->block = cands[q].B;
+                c->grid = cands[q].G;
+                if ((rc = build_tiles(c))) goto done;
+                if (hipMemcpyAsync(c->tune_x.p, x, v3, hipMemcpyDeviceToDevice, c->stream) ||
+                    hipMemcpyAsync(c->tune_v.p, v, v3, hipMemcpyDeviceToDevice, c->stream)) {
+                    rc = fail(c, EAMFE_EDEVICE, "autotune: copy failed");
+                    goto done;
+                }
+                if ((rc = run_switching(c, p, step, step + 2, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr,
+                                        nullptr, nullptr, 0)))
+                    goto done;
+                (void)hipEventRecord(e0, c->stream);
+                if ((rc = run_switching(c, p, step + 2, s3, (double*)c->tune_x.p, (double*)c->tune_v.p, nullptr,
+                                        nullptr, nullptr, 0)))
+                    goto done;
+                (void)hipEventRecord(e1, c->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                const double per = ms / (double)(s3 - step - 2);
+                if (per < best2) {
+                    best2 = per;
+                    best = per;
+                    best_l = cands[q].L;
+                    best_b = cands[q].B;
+                    best_g = cands[q].G;
+                }
+            }
         }
     }
     // at the chosen shape, the list builder: rows from LDS or from global memory
