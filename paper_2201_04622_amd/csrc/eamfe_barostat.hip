@@ -1,14 +1,47 @@
-// Pieces of the isotropic stochastic cell-rescaling barostat (Bernetti and
-// Bussi, J. Chem. Phys. 153, 114107, 2020) that the coupling move of
-// eamfe_barostat_step needs besides the pressure evaluation: the scaling of
-// positions and velocities by each replica's factor, and the normal deviate
-// that drives the volume.
+// Pieces of the stochastic cell-rescaling barostat (Bernetti and Bussi, J.
+// Chem. Phys. 153, 114107, 2020), isotropic or per axis, that the coupling
+// move of eamfe_barostat_step needs besides the virial: each replica's
+// kinetic sums, the scaling of positions and velocities by each replica's
+// factors, and the normal deviates that drive the box.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 
+#include "eamfe_internal.h"
+
 namespace eamfe {
+
+// sum_i v_i,a^2 over each replica's atoms, per axis a (the kinetic part of the
+// diagonal pressure, before the mass): one block per replica, a strided sum
+// per thread, then a fixed tree; out[n_rep][3].
+constexpr int kKinBlock = 256;
+
+__global__ __launch_bounds__(kKinBlock) void k_kinetic(const double* v, const RepDesc* reps, int N, double* out)
+{
+    __shared__ double sh[3][kKinBlock];
+    const RepDesc& R = reps[blockIdx.x];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < R.n; k += blockDim.x) {
+        const int i = R.off + k;
+        for (int c = 0; c < 3; ++c) s[c] += v[(size_t)c * N + i] * v[(size_t)c * N + i];
+    }
+    for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int h = kKinBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_kinetic(const double* v, const RepDesc* reps, int n_rep, int N, double* out, hipStream_t s)
+{
+    if (n_rep <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kinetic, dim3(n_rep), dim3(kKinBlock), 0, s, v, reps, N, out);
+    return hipGetLastError();
+}
 
 // x_a <- mu_a x_a, v_a <- v_a / mu_a for the atoms of each replica (SoA
 // [3][N] FP64; one thread per atom; mu[n_rep][3] on the device, one factor
@@ -52,9 +85,6 @@ static void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1)
     }
 }
 
-// The first Box--Muller deviate of the Philox block at counter (atom, step
-// low word, stream, step high word) under key (seed low word, seed high
-// word), from the uniforms (w + 1) 2^-32 of its first two words.
 // The three Box--Muller deviates of the Philox block at counter (atom, step
 // low word, stream, step high word) under key (seed low word, seed high
 // word): z0, z1 from the uniforms (w + 1) 2^-32 of its first two words, z2

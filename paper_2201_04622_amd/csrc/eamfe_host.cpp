@@ -45,6 +45,7 @@ static int scratch_setup(int device)
 namespace eamfe {
 // eamfe_barostat.hip
 hipError_t launch_rescale(double* x, double* v, const int32_t* rep_of, const double* mu, int N, hipStream_t s);
+hipError_t launch_kinetic(const double* v, const RepDesc* reps, int n_rep, int N, double* out, hipStream_t s);
 void barostat_gauss3(uint64_t seed, uint32_t atom, int64_t step, uint32_t stream, double z[3]);
 }  // namespace eamfe
 
@@ -2100,8 +2101,12 @@ int eamfe_barostat_step(eamfe_ctx* c, const eamfe_barostat* b, int64_t step, dou
     // is the internal pressure of H = w_eam U_EAM along axis a
     std::vector<double> Pc((size_t)c->n_rep * 3);
     OK(eamfe_pressure(c, x, nullptr, Pc.data()));
-    std::vector<double> vh((size_t)3 * c->N);
-    HIPCHK(c, hipMemcpy(vh.data(), v, vh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // each replica's sum of v_a^2 per axis on the device (three numbers per
+    // replica cross to the host, not the velocities)
+    std::vector<double> kin((size_t)c->n_rep * 3);
+    LCHK(c, launch_kinetic(v, (const RepDesc*)c->reps_d.p, c->n_rep, c->N, (double*)c->mu_d.p, c->stream));
+    HIPCHK(c, hipMemcpyAsync(kin.data(), c->mu_d.p, kin.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     const double rl = c->r_cut + c->skin;
     std::vector<double> mu((size_t)c->n_rep * 3), Pint((size_t)c->n_rep * 3);
     for (int r = 0; r < c->n_rep; ++r) {
@@ -2110,8 +2115,7 @@ int eamfe_barostat_step(eamfe_ctx* c, const eamfe_barostat* b, int64_t step, dou
         const double kT = kB * R.T;
         double Paa[3];
         for (int d = 0; d < 3; ++d) {
-            double mv2 = 0.0;
-            for (int i = R.off; i < R.off + R.n; ++i) mv2 += vh[(size_t)d * c->N + i] * vh[(size_t)d * c->N + i];
+            const double mv2 = kin[3 * (size_t)r + d];
             Paa[d] = (mv2 * R.mass * mvv2e + w_eam * Pc[3 * r + d] * V) / V;
             Pint[3 * r + d] = Paa[d];
         }
