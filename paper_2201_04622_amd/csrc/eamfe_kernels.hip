@@ -661,22 +661,35 @@ __device__ int flag_prefix(const RepDesc* reps, const int32_t* rebuild, int n_re
 }
 
 // Replica holding work item f of a prefix p[0..n_rep] (non-decreasing,
-// p[n_rep] > f): the last r with p[r] <= f, which skips replicas with no
-// items.  Called by a whole wavefront with a uniform f: each round its 64
-// lanes probe 64 evenly spaced entries and a ballot counts those <= f, so
-// up to 64 replicas take one round of loads (a binary search, one load per
-// level, would chain six).
-__device__ __forceinline__ int item_replica(const int32_t* p, int n_rep, int f)
+// p[0] = 0, p[n_rep] > f): the last r with p[r] <= f, which skips replicas
+// with no items; p_lo returns p[r] and r_off the replica's first atom, both
+// from the probes (each probe also reads its replica's first atom, in the same
+// round).  Called by a whole wavefront with a uniform f: each round its 64
+// lanes probe 64 evenly spaced entries and a ballot counts those <= f, so up
+// to 64 replicas take one round of loads (a binary search, one load per
+// level, would chain six).  Every probe is in bounds whatever f is.
+__device__ __forceinline__ int item_replica(const int32_t* p, const RepDesc* reps, int n_rep, int f, int& p_lo,
+                                            int& r_off)
 {
     const int lw = threadIdx.x & 63;
     int lo = 0, hi = n_rep;   // p[lo] <= f < p[hi]
+    int plo = 0, olo = 0;     // p[0] and the first atom of replica 0
     while (hi - lo > 1) {
         const int stride = (hi - lo + 63) >> 6;
         const int idx = lo + stride * (lw + 1);
-        const uint64_t le = __ballot(idx < hi && p[idx] <= f);
-        lo += stride * __popcll(le);   // the probes <= f are a prefix of the lanes
+        const bool in = idx < hi;
+        const int v = in ? p[idx] : 0x7fffffff;
+        const int o = in ? reps[idx].off : 0;
+        const int k = __popcll(__ballot(v <= f));   // the probes <= f are a prefix of the lanes
+        if (k > 0) {
+            plo = __builtin_amdgcn_readlane(v, k - 1);
+            olo = __builtin_amdgcn_readlane(o, k - 1);
+        }
+        lo += stride * k;
         hi = min(hi, lo + stride);
     }
+    p_lo = plo;
+    r_off = olo;
     return lo;
 }
 
@@ -759,19 +772,32 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
     int* row = rowbuf + (size_t)w * cap;
     int* cb = rowbuf + (size_t)(kListBlock / 64) * cap + (size_t)w * a.chunk;   // this wave's candidate chunk
     const int32_t* pre = a.flag_pre;
-    const int total = pre[n_rep];
     const uint64_t below = (1ull << lw) - 1ull;
     const int waves = gridDim.x * (kListBlock / 64);
-    for (int f = blockIdx.x * (kListBlock / 64) + w; f < total; f += waves) {
-        const int lo = item_replica(pre, n_rep, f);
+    // the wave's first item: its replica's probes go out with the total's
+    // read (the empty asm takes their results before the loop's test, so the
+    // compiler cannot sink them behind it)
+    const int f0 = blockIdx.x * (kListBlock / 64) + w;
+    const int total = pre[n_rep];
+    int plo0, off0;
+    const int lo0 = item_replica(pre, a.reps, n_rep, f0, plo0, off0);
+    __asm__ volatile("" : : "v"(lo0), "v"(plo0), "v"(off0));
+    for (int f = f0; f < total; f += waves) {
+        int plo = plo0, roff = off0;
+        const int lo = f == f0 ? lo0 : item_replica(pre, a.reps, n_rep, f, plo, roff);
         const RepDesc& R = a.reps[lo];
-        const int roff = R.off, rn = R.n;
-        const int il = f - pre[lo];
+        const int il = f - plo;
         const int i = roff + il;
+        // the atom's record and reference position go out with the
+        // replica's fields (the empty asm again keeps the field reads from
+        // sinking into the branches that use them)
         const uint4 qi = a.Q[i];
         const double4 pi = a.P[i];   // the list's reference position, read with the record
-        const float sx = (float)(R.L[0] * 2.3283064365386963e-10), sy = (float)(R.L[1] * 2.3283064365386963e-10),
-                    sz = (float)(R.L[2] * 2.3283064365386963e-10);
+        const int rn = R.n, nc0 = R.nc[0], nc1 = R.nc[1], nc2 = R.nc[2], cbase = R.cell_base;
+        const double L0 = R.L[0], L1 = R.L[1], L2 = R.L[2];
+        __asm__ volatile("" : : "v"(rn), "v"(nc0), "v"(nc1), "v"(nc2), "v"(cbase));
+        const float sx = (float)(L0 * 2.3283064365386963e-10), sy = (float)(L1 * 2.3283064365386963e-10),
+                    sz = (float)(L2 * 2.3283064365386963e-10);
         int cnt = 0;
         auto test = [&](int jl) {
             const uint4 qj = a.Q[roff + jl];
@@ -785,29 +811,35 @@ __global__ __launch_bounds__(kListBlock) void k_list(NeighArgs a, int n_rep)
             if (acc && cnt + rank < cap) row[cnt + rank] = j;
             cnt += __popcll(m);
         };
-        if (R.nc[0] == 0) {
+        if (nc0 == 0) {
             for (int s0 = 0; s0 < rn; s0 += 64) {
                 const int jl = s0 + lw;
                 append(jl < rn && test(jl), roff + jl);
             }
         } else {   // cells
-            const int cx = box_cell(qi.x, R.nc[0]), cy = box_cell(qi.y, R.nc[1]), cz = box_cell(qi.z, R.nc[2]);
-            int tot_c = 0;   // running total of the stencil cells' sizes
-            for (int q0 = 0; q0 < kStencil; q0 += 64) {
-                const int q = q0 + lw;
-                int n_c = 0, c = 0;
+            const int cx = box_cell(qi.x, nc0), cy = box_cell(qi.y, nc1), cz = box_cell(qi.z, nc2);
+            // lane l holds stencil cells l and 64 + l: both cells' counts are
+            // read together, then prefix-summed in stencil order
+            int n_c[2] = {0, 0}, cc[2] = {0, 0};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 64 * h + lw;
                 if (q < kStencil) {
-                    const int ux = wrap_cell(cx + q / 25 - 2, R.nc[0]);
-                    const int uy = wrap_cell(cy + (q / 5) % 5 - 2, R.nc[1]);
-                    const int uz = wrap_cell(cz + q % 5 - 2, R.nc[2]);
-                    c = R.cell_base + (ux * R.nc[1] + uy) * R.nc[2] + uz;
-                    n_c = min(a.cell_cnt[c], a.ccap);
+                    const int ux = wrap_cell(cx + q / 25 - 2, nc0);
+                    const int uy = wrap_cell(cy + (q / 5) % 5 - 2, nc1);
+                    const int uz = wrap_cell(cz + q % 5 - 2, nc2);
+                    cc[h] = cbase + (ux * nc1 + uy) * nc2 + uz;
+                    n_c[h] = min(a.cell_cnt[cc[h]], a.ccap);
                 }
-                int incl = wave_scan(n_c);
-                incl += tot_c;
+            }
+            int tot_c = 0;   // running total of the stencil cells' sizes
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 64 * h + lw;
+                const int incl = wave_scan(n_c[h]) + tot_c;
                 if (q < kStencil) {
                     cend[w][q] = incl;
-                    cid[w][q] = c;
+                    cid[w][q] = cc[h];
                 }
                 tot_c = __builtin_amdgcn_readlane(incl, 63);
             }
