@@ -731,16 +731,23 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(NeighArgs a, StepArgs s)
     }
     const int stride = (gridDim.x - 1) * blockDim.x;
     for (int i = (blockIdx.x - 1) * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+        // the atom's record goes out with its replica id, and the flag with the
+        // replica's fields: two rounds of loads ahead of the count, not four
+        // (the empty asm takes every value before the tests, so the compiler
+        // cannot sink the reads behind them; the record is used only for an
+        // atom of a flagged replica)
         const int r = a.rep_of[i];
-        if (!a.rebuild[r]) continue;
-        const RepDesc& R = a.reps[r];
-        if (R.nc[0] == 0 || R.lds) continue;   // all-pairs rows, or rows built from LDS: no global cells
         const uint4 q = a.Q[i];
-        const int c = R.cell_base + (box_cell(q.x, R.nc[0]) * R.nc[1] + box_cell(q.y, R.nc[1])) * R.nc[2] +
-                      box_cell(q.z, R.nc[2]);
+        const int fl = a.rebuild[r];
+        const RepDesc& R = a.reps[r];
+        const int nc0 = R.nc[0], nc1 = R.nc[1], nc2 = R.nc[2], lds = R.lds, cbase = R.cell_base, roff = R.off;
+        __asm__ volatile("" : : "v"(q.x), "v"(q.y), "v"(q.z), "v"(fl), "v"(nc0), "v"(nc1), "v"(nc2), "v"(lds),
+                         "v"(cbase), "v"(roff));
+        if (!fl || nc0 == 0 || lds) continue;   // all-pairs rows, or rows built from LDS: no global cells
+        const int c = cbase + (box_cell(q.x, nc0) * nc1 + box_cell(q.y, nc1)) * nc2 + box_cell(q.z, nc2);
         const int slot = atomicAdd(&a.cell_cnt[c], 1);
         if (slot < a.ccap)
-            a.cell_atoms[(size_t)c * a.ccap + slot] = i - R.off;
+            a.cell_atoms[(size_t)c * a.ccap + slot] = i - roff;
         else
             atomicOr(a.status, ST_CELL_OVERFLOW);
     }
