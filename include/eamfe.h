@@ -355,7 +355,11 @@ int eamfe_copy_lists(eamfe_ctx* ctx, int32_t* nnb_dev, int32_t* nbr_dev, int cap
  * at r_k = k r_cut/(n_r-1), k = 0..n_r-1; F_knots at rho_k = k rho_max/(n_rho-1).
  * Each function is the natural cubic spline through its knots; outside the
  * table the last cubic piece is continued and EAMFE_ETABLE_RANGE is latched
- * when a density exceeds rho_max.  May be called again to replace the tables. */
+ * when a density exceeds rho_max.  May be called again to replace the tables.
+ * EAMFE_FP32 holds the pair and density-derivative tables in one block's LDS
+ * (32 bytes per knot): n_r above the device's LDS per block / 32 (5120 on
+ * gfx950) returns EAMFE_EINVAL and keeps the tables the context had.
+ * EAMFE_FP64 reads its tables from global memory and has no such limit. */
 int eam_setup(eamfe_ctx* ctx, int n_r, double r_cut, const double* phi_knots,
               const double* rho_knots, int n_rho, double rho_max, const double* F_knots);
 
@@ -450,7 +454,9 @@ int eamfe_set_state(eamfe_ctx* ctx, const double* W_host, const double* xref_dev
 /* ---- differentiation --------------------------------------------------- */
 
 /* dU_EAM/dtheta at x, theta = the knot values (phi_k, rho_k, F_k) given to
- * eam_setup (n_r == n_rho required).  U is linear in the phi and F knots and,
+ * eam_setup (n_r == n_rho required, and 32 (n_r - 1) bytes of histogram must
+ * fit one block's LDS: at most 5121 knots on gfx950, else EAMFE_EINVAL
+ * before any kernel runs).  U is linear in the phi and F knots and,
  * through rho_i, depends on the rho knots; the kernels bin (1, t, t^2, t^3)
  * of every spline evaluation per interval in 2^-32 fixed point
  * (deterministic), then apply the transpose of the natural-spline map.
@@ -487,7 +493,9 @@ int eamfe_adjoint_theta_noalloc(eamfe_ctx* ctx, const double* x_dev, const doubl
  * lambda equals the protocol's start value (the H0 ensemble: lambda = 0 for
  * FL/HH, 1 for RS), accumulating as eamfe_adjoint_theta would into
  * dtheta_dev (device, kept by the caller until sampling is switched off with
- * every = 0).  Resets the sample count. */
+ * every = 0).  Resets the sample count.  A run that samples with tables the
+ * adjoint cannot take (see eamfe_adjoint_theta) returns EAMFE_EINVAL before
+ * any step runs. */
 int eamfe_set_adjoint_sampling(eamfe_ctx* ctx, int every, const double* w_host, int reduce, double* dtheta_dev);
 
 /* Samples accumulated since the last eamfe_set_adjoint_sampling. */

@@ -893,6 +893,21 @@ int pack(eamfe_ctx* c, const double* x)
     return EAMFE_OK;
 }
 
+// The adjoint's tables: equal knot counts, and each block's histogram of
+// four fixed-point words per interval (32 bytes) within one block's LDS.
+int check_adjoint_tables(eamfe_ctx* c, const char* who)
+{
+    if (c->n_r != c->n_rho)
+        return fail(c, EAMFE_EINVAL, std::string(who) + ": phi/rho and F tables must have equal knot counts");
+    const long need = 32L * (std::max(c->n_r, c->n_rho) - 1);
+    if (need > c->max_lds)
+        return fail(c, EAMFE_EINVAL, std::string(who) + ": tables of " + std::to_string(c->n_r) +
+                                         " knots need " + std::to_string(need) + " bytes of LDS per block, more than " +
+                                         std::to_string(c->max_lds) + " (at most " +
+                                         std::to_string(c->max_lds / 32 + 1) + " knots)");
+    return EAMFE_OK;
+}
+
 // dU/dtheta at the packed positions P (density pass already run with
 // rho_out, so F' and rho are current): bins -> knot gradients into out.
 // bins: n_rep * 3 * nb * 4 fixed-point words; fin: the knot transform's
@@ -900,7 +915,7 @@ int pack(eamfe_ctx* c, const double* x)
 int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce, double* out,
                unsigned long long* bins_p, double* fin_p)
 {
-    if (c->n_r != c->n_rho) return fail(c, EAMFE_EINVAL, "adjoint: phi/rho and F tables must have equal knot counts");
+    OK(check_adjoint_tables(c, "adjoint"));
     const int nb = std::max(c->n_r, c->n_rho) - 1;
     const size_t bins = (size_t)c->n_rep * 3 * nb * 4;
     LCHK(c, launch_fill_u64(bins_p, bins, 0ull, c->stream));   // a fill kernel: capturable, unlike a memset
@@ -1116,6 +1131,7 @@ bool ready(eamfe_ctx* c, bool need_pot);
 int adjoint_theta_with(eamfe_ctx* c, const double* x, const double* w_host, int reduce, double* dtheta,
                        char* static_base, size_t fin_off)
 {
+    OK(check_adjoint_tables(c, "adjoint_theta"));   // before any kernel runs
     OK(pack(c, x));
     OK(ensure_lists(c, c->have_list ? c->skin : 0.3, PA(c)));
     NeighArgs na = neigh_args(c, PA(c));
@@ -1354,6 +1370,14 @@ int eam_setup(eamfe_ctx* c, int n_r, double r_cut, const double* phi, const doub
     if (!c) return EAMFE_EINVAL;
     if (n_r < 3 || n_rho < 3 || !(r_cut > 0.0) || !(rho_max > 0.0) || !phi || !rho || !F)
         return fail(c, EAMFE_EINVAL, "eam_setup: bad table description");
+    // the FP32 pair kernels hold the pair table and the density-derivative
+    // table in one block's LDS: 16 bytes per interval each, plus a padding
+    // interval per table
+    if (c->precision == EAMFE_FP32 && 32L * n_r > c->max_lds)
+        return fail(c, EAMFE_EINVAL, "eam_setup: FP32 tables of " + std::to_string(n_r) + " knots need " +
+                                         std::to_string(32L * n_r) + " bytes of LDS per block, more than " +
+                                         std::to_string(c->max_lds) + " (at most " + std::to_string(c->max_lds / 32) +
+                                         " knots in EAMFE_FP32; EAMFE_FP64 reads its tables from global memory)");
     (void)hipSetDevice(c->device);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Shape s2 = c->shape;
@@ -1567,6 +1591,7 @@ namespace {
 int run_range(eamfe_ctx* c, const eamfe_protocol* p, int64_t S, int64_t s0, int64_t s1, double* x, double* v,
               double* dHdl_out, double* W_out, int64_t stride, int64_t trace_off, double c1, bool has_eam)
 {
+    if (has_eam && c->adj_every > 0) OK(check_adjoint_tables(c, "adjoint sampling"));   // before any step runs
     drop_graphs(c);   // captured kernel arguments belong to one call (pointers, protocol, shapes)
     OK(pack(c, x));
     double4* cur = PA(c);
