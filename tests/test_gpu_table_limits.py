@@ -9,7 +9,8 @@ adjoint at most 5121.
 * At those sizes, FP32 forces and energies follow the oracle's tables of
   the same knots. The FP64 adjoint keeps the exact identities of the EAM
   energy.
-* One knot more is refused with EAMFE_EINVAL before any kernel runs, and the
+* One knot more is refused with EAMFE_EINVAL before any kernel runs (an
+  adjoint call, or a switching run that samples the adjoint), and the
   context keeps the tables it had.
 * FP64 stepping reads its tables from global memory and takes the larger
   table."""
@@ -91,6 +92,18 @@ def test_fp64_takes_larger_tables_and_the_adjoint_stops_at_its_limit(oracle_lib)
         ctx.adjoint_theta(xd, g)
     assert err.value.code == 1 and "LDS" in str(err.value), err.value
     assert not g.any().item()   # nothing ran
+    # a switching run that samples the adjoint is refused before its first step
+    p = E.protocol("fl", n_eq=2, n_sw=2, n_hold=1, n_hold2=1)
+    v = torch.zeros_like(xd)
+    ctx.init_velocities(v, True)
+    xs, vs = xd.clone(), v.clone()
+    ctx.set_adjoint_sampling(1, g)
+    with pytest.raises(E.EamfeError) as err:
+        ctx.run_switching(p, xs, vs, 0, 2 + 4 + 1 + 1)
+    assert err.value.code == 1 and "LDS" in str(err.value), err.value
+    assert torch.equal(xs, xd) and torch.equal(vs, v) and not g.any().item()
+    assert ctx.adjoint_samples() == 0
+    ctx.set_adjoint_sampling(0)
     # at the limit the adjoint runs and keeps the energy's exact identities
     n = ADJOINT_KNOTS
     say(f"FP64 adjoint with tables of {n} knots")
