@@ -359,7 +359,8 @@ int eamfe_copy_lists(eamfe_ctx* ctx, int32_t* nnb_dev, int32_t* nbr_dev, int cap
  * EAMFE_FP32 holds the pair and density-derivative tables in one block's LDS
  * (32 bytes per knot): n_r above the device's LDS per block / 32 (5120 on
  * gfx950) returns EAMFE_EINVAL and keeps the tables the context had.
- * EAMFE_FP64 reads its tables from global memory and has no such limit. */
+ * EAMFE_FP64 has no such limit (its kernels copy the tables into LDS only
+ * when they fit, else read them from global memory). */
 int eam_setup(eamfe_ctx* ctx, int n_r, double r_cut, const double* phi_knots,
               const double* rho_knots, int n_rho, double rho_max, const double* F_knots);
 

@@ -1294,11 +1294,10 @@ __global__ __launch_bounds__(1024) void k_rows_lds(NeighArgs a, StepArgs s)
 // --------------------------------------------------------------------------
 // Density pass.  FP32 tables are staged in LDS (32 KB for rho).
 // --------------------------------------------------------------------------
-template <typename real, int T, bool kStage = false, bool kFix = true>
+template <typename real, int T, bool kStage = false, bool kFix = true, bool kLds = (sizeof(real) == 4)>
 __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
-    constexpr bool kLds = sizeof(real) == 4;
     constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter + a.it_k : 0;
@@ -1307,14 +1306,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
         return;
     }
     const int nr = a.tab.n_r;
-    auto stage_table = [&]() {   // FP32: the table in LDS once per block; its wavefronts then take units
-        if constexpr (kLds) {
+    // kLds: the table in LDS once per block; its wavefronts then take units
+    // (FP32 always; FP64 when its 32-byte intervals fit, copied as they are)
+    auto stage_table = [&]() {
+        if constexpr (kLds && kQ) {
             const float4* g = (const float4*)a.tab.rho;
             copy_rounds<2, float4>(nr - 1, [&](int k) { return g[k]; }, [&](int k, const float4& c) { lds_tab[k] = c; });
             if (threadIdx.x == 0) {   // padding interval: the value at r_cut
                 const float4 c = g[nr - 2];
                 lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
             }
+        } else if constexpr (kLds) {
+            const uint4* g = (const uint4*)a.tab.rho;
+            uint4* l = (uint4*)lds_tab;
+            copy_rounds<4, uint4>(2 * (nr - 1), [&](int k) { return g[k]; }, [&](int k, const uint4& c) { l[k] = c; });
         }
     };
     uint4* const st = (uint4*)(lds_tab + nr);   // staged form: the block's replica records, after the table
@@ -1370,11 +1375,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(StepArgs a)
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
                 real v;
-                if constexpr (kLds) {
+                if constexpr (kLds && kQ) {
                     const float4 c = lds_tab[m[s]];
                     v = c.x + t[s] * (c.y + t[s] * (c.z + t[s] * c.w));
                 } else {
-                    const auto c = Tab<real>::ld4(a.tab.rho, m[s]);
+                    const auto c = Tab<real>::ld4(kLds ? (const void*)lds_tab : a.tab.rho, m[s]);
                     v = c.x + t[s] * (c.y + t[s] * (c.z + t[s] * c.w));
                 }
                 if constexpr (kQ) part += v * (in[s] ? 1.f : 0.f);   // a product: the table read stays unconditional
@@ -1483,22 +1488,23 @@ __device__ __forceinline__ void total_force(int mode, const double (&fe)[3], con
     }
 }
 
-template <typename real, int T, bool kStage = false, bool kVir = false, bool kFix = true>
+template <typename real, int T, bool kStage = false, bool kVir = false, bool kFix = true,
+          bool kLds = (sizeof(real) == 4)>
 __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 {
     extern __shared__ float4 lds_tab[];
-    constexpr bool kLds = sizeof(real) == 4;
     constexpr bool kQ = sizeof(real) == 4;   // FP32 form gathers 16-byte box-coordinate records
     const int N = a.N;
     const int64_t it = a.step_kernel ? *a.iter + a.it_k : 0;
     const int nr = a.tab.n_r;
-    // FP32: the table in LDS once per block; its wavefronts then take units.
-    // In LDS the two 16-byte halves of an interval's record (phi's
+    // kLds: the table in LDS once per block; its wavefronts then take units.
+    // FP32: the two 16-byte halves of an interval's record (phi's
     // coefficients, rho's slope coefficients) sit in two arrays of nr entries,
     // so the random reads of each half spread over every bank, not over the
-    // even or the odd 16-byte bank groups only.
+    // even or the odd 16-byte bank groups only.  FP64 (when its 64-byte
+    // intervals fit): the table as it is in global memory.
     auto stage_table = [&]() {
-        if constexpr (kLds) {
+        if constexpr (kLds && kQ) {
             const float4* g = (const float4*)a.tab.pair;
             // the two halves as 2 (nr - 1) items: item k is half k % 2 of interval k / 2
             copy_rounds<4, float4>(2 * (nr - 1), [&](int k) { return g[k]; },
@@ -1508,6 +1514,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
                 lds_tab[nr - 1] = make_float4(c.x + c.y + c.z + c.w, 0.f, 0.f, 0.f);
                 lds_tab[2 * nr - 1] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
+        } else if constexpr (kLds) {
+            const uint4* g = (const uint4*)a.tab.pair;
+            uint4* l = (uint4*)lds_tab;
+            copy_rounds<4, uint4>(4 * (nr - 1), [&](int k) { return g[k]; }, [&](int k, const uint4& c) { l[k] = c; });
         }
     };
     // this step's lambda values, read once per block
@@ -1573,12 +1583,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(StepArgs a)
 #pragma unroll
             for (int s = 0; s < SB; ++s) {
                 real ua, ub, uc, ud, wb, wc, wd;
-                if constexpr (kLds) {
+                if constexpr (kLds && kQ) {
                     const float4 u = lds_tab[m[s]], w = lds_tab[nr + m[s]];
                     ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
                 } else {
                     decltype(Tab<real>::ld4(a.tab.rho, 0)) u, w;
-                    Tab<real>::ld8(a.tab.pair, m[s], u, w);
+                    Tab<real>::ld8(kLds ? (const void*)lds_tab : a.tab.pair, m[s], u, w);
                     ua = u.x; ub = u.y; uc = u.z; ud = u.w; wb = w.x; wc = w.y; wd = w.z;
                 }
                 const real ts = t[s];
@@ -1952,8 +1962,39 @@ int launch_rows_rowmajor(const int32_t* nbr, const int32_t* nnb, int N, int cap,
 template <typename real>
 static size_t lds_bytes(const StepArgs& a, int tables)
 {
-    // n_r - 1 intervals and one padding interval per table
-    return (sizeof(real) == 4 && a.has_eam) ? (size_t)tables * a.tab.n_r * sizeof(float4) : 0;
+    if (!a.has_eam) return 0;
+    // FP32: n_r - 1 intervals and one padding interval per table, 16 bytes
+    // each; FP64 (the density table, or the pair table as two): n_r - 1
+    // intervals of 32 bytes
+    return sizeof(real) == 4 ? (size_t)tables * a.tab.n_r * sizeof(float4) : (size_t)tables * (a.tab.n_r - 1) * 32;
+}
+
+// LDS one block may take on the current device (cached per device).
+static size_t device_lds()
+{
+    static thread_local int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    if (!cached[dev]) {
+        int v = 0;
+        cached[dev] = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0
+                          ? v
+                          : 65536;
+    }
+    return (size_t)cached[dev];
+}
+
+// FP64 pair kernels read their tables from LDS when the force pass's pair
+// table (64 bytes per interval) fits one block's and the launch holds at
+// least two units per compute unit; otherwise from global memory.  Staging
+// the table costs each block a fixed latency (128 KB at 2000 knots), which
+// a launch of few units, such as one replica of a few thousand atoms, does
+// not earn back: there the pass is latency bound and the table's reads
+// come from L2 at little cost.
+template <typename real>
+static bool fp64_lds(const StepArgs& a)
+{
+    return sizeof(real) == 8 && a.has_eam && lds_bytes<real>(a, 2) <= device_lds() && a.n_tiles >= 2 * a.n_cu;
 }
 
 // Resident blocks per CU of a pair kernel at this block size and LDS use
@@ -2039,7 +2080,17 @@ static void density_one(const StepArgs& a, int block, hipStream_t s, const Stamp
             return;
         }
     }
-    const size_t sh = lds_bytes<real>(a, 1);
+    if constexpr (sizeof(real) == 8) {
+        if (fp64_lds<real>(a)) {
+            const size_t sh = lds_bytes<real>(a, 1);
+            const void* f = reinterpret_cast<const void*>(&k_density<real, T, false, kFix, true>);
+            allow_lds(f, sh);
+            launch_pair(k_density<real, T, false, kFix, true>, dim3(pair_grid(a, f, block, sh) + a.finish_prev),
+                        dim3(block), sh, s, ts, a);
+            return;
+        }
+    }
+    const size_t sh = sizeof(real) == 4 ? lds_bytes<real>(a, 1) : 0;
     const void* f = reinterpret_cast<const void*>(&k_density<real, T, false, kFix>);
     launch_pair(k_density<real, T, false, kFix>, dim3(pair_grid(a, f, block, sh) + a.finish_prev), dim3(block), sh,
                 s, ts, a);
@@ -2049,7 +2100,17 @@ template <typename real, int T, bool kFix>
 static void force_one(const StepArgs& a, int block, hipStream_t s, const Stamp& ts)
 {
     if (a.vir_part) {   // pressure evaluation (not a step): the persistent form with the virial
-        const size_t sh = lds_bytes<real>(a, 2);
+        if constexpr (sizeof(real) == 8) {
+            if (fp64_lds<real>(a)) {
+                const size_t sh = lds_bytes<real>(a, 2);
+                const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, true, kFix, true>);
+                allow_lds(f, sh);
+                launch_pair(k_force<real, T, false, true, kFix, true>, dim3(pair_grid(a, f, block, sh)), dim3(block),
+                            sh, s, ts, a);
+                return;
+            }
+        }
+        const size_t sh = sizeof(real) == 4 ? lds_bytes<real>(a, 2) : 0;
         const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, true, kFix>);
         launch_pair(k_force<real, T, false, true, kFix>, dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, ts,
                     a);
@@ -2064,7 +2125,17 @@ static void force_one(const StepArgs& a, int block, hipStream_t s, const Stamp& 
             return;
         }
     }
-    const size_t sh = lds_bytes<real>(a, 2);
+    if constexpr (sizeof(real) == 8) {
+        if (fp64_lds<real>(a)) {
+            const size_t sh = lds_bytes<real>(a, 2);
+            const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, false, kFix, true>);
+            allow_lds(f, sh);
+            launch_pair(k_force<real, T, false, false, kFix, true>, dim3(pair_grid(a, f, block, sh)), dim3(block), sh,
+                        s, ts, a);
+            return;
+        }
+    }
+    const size_t sh = sizeof(real) == 4 ? lds_bytes<real>(a, 2) : 0;
     const void* f = reinterpret_cast<const void*>(&k_force<real, T, false, false, kFix>);
     launch_pair(k_force<real, T, false, false, kFix>, dim3(pair_grid(a, f, block, sh)), dim3(block), sh, s, ts, a);
 }
