@@ -119,3 +119,37 @@ def test_fp64_takes_larger_tables_and_the_adjoint_stops_at_its_limit(oracle_lib)
         # U is homogeneous of degree one in the (phi, F) knots together
         assert knots.phi @ gg[r, 0] + knots.embed @ gg[r, 2] == pytest.approx(U[r], rel=1e-11)
     ctx.close()
+
+
+def test_fp64_tables_from_lds_or_global_memory_give_the_same_bits():
+    """The FP64 pair kernels read their tables from LDS in a launch of at
+    least two units per compute unit and from global memory otherwise.  The
+    same replicas at the same lanes, alone (a small launch) and beside filler
+    replicas (a large one), give the same forces and energies bit for bit:
+    a replica's arithmetic and its order do not depend on where the table
+    sits or on the other replicas."""
+    import torch
+
+    import paper_2201_04622_amd.eamfe as E
+    lanes, per_unit = 8, 64 // 8
+    reps = _reps() + [I.Replica("bcc", 7, I.A_BCC_VERBATIM, 900.0, 5.0, 9)]   # 128 + 500 + 686 atoms
+    units = sum(-(-r.natoms // per_unit) for r in reps)
+    limit = 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    assert units < limit   # alone: global tables
+    filler = []
+    while units + sum(-(-r.natoms // per_unit) for r in filler) < limit:
+        filler.append(I.Replica("fcc", 6, I.A_FCC_VERBATIM, 600.0, 5.0, 20 + len(filler)))
+    say(f"FP64 tables: {units} units alone, {units + sum(-(-r.natoms // per_unit) for r in filler)} with "
+        f"{len(filler)} filler replicas (LDS from {limit})")
+    x_reps = I.displaced(I.batch_arrays(reps)["x0"], 0.05, seed=23)
+    x_fill = I.displaced(I.batch_arrays(filler)["x0"], 0.05, seed=24)
+    out = []
+    for batch, x in ((reps, x_reps), (reps + filler, np.concatenate([x_reps, x_fill]))):
+        ctx, x0, arrs = make_ctx(batch, FP64, lanes, 256)
+        xd = E.to_soa(x)
+        ctx.neigh_build(xd, 0.3, 0)
+        f, U = _forces(ctx, xd, len(batch))
+        out.append((f[: len(x_reps)], U[: len(reps)]))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
