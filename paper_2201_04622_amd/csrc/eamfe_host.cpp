@@ -950,12 +950,15 @@ int adjoint_at(eamfe_ctx* c, const double4* P, const double* w_host, int reduce,
 // Timing events of a sampled launch (kind: 0 density, 1 force, 2 lists).
 // mark records one on the stream (end = 0 start, 1 stop), around the list
 // pass's kernels; stamps hands out a pair for a pair kernel to stamp with
-// its own start and end (null pair: this launch is not sampled).
+// its own start and end (null pair: this launch is not sampled).  They are
+// read only after the stream has been synchronised, so they are recorded
+// without the system-scope fence (no cache writeback and invalidation
+// between the sampled kernel and the next).
 int next_event(eamfe_ctx* c, hipEvent_t* e)
 {
     if (c->ev_used == c->ev_pool.size()) {
         hipEvent_t n;
-        HIPCHK(c, hipEventCreate(&n));
+        HIPCHK(c, hipEventCreateWithFlags(&n, hipEventDisableSystemFence));
         c->ev_pool.push_back(n);
     }
     *e = c->ev_pool[c->ev_used++];
